@@ -1,0 +1,625 @@
+/*
+ * pic_oracle.c -- plain, slow FP64 CPU oracle of the electrostatic PIC hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg load it.  It shares no code, header, table or constant with
+ * the HIP path.
+ *
+ * What it follows (the paper is "A Comparison of Massively Parallel Performance
+ * Portable Particle-in-Cell schemes for electrostatic kinetic plasma
+ * simulations", PASC'26):
+ *   - the PIC loop scatter -> solve -> gather -> push        (Sec. 2, Fig. pic-loop)
+ *   - Poisson  Lap(phi) = -rho/eps0,  E = -grad(phi)          (Sec. 2, Eq. poisson)
+ *   - neutralising background rho_i = -Q_e / |box|            (Sec. 2, text after Eq. poisson)
+ *   - same shape function for scatter and gather (CIC)        (Sec. 2; Sec. 4.2 "Weak scaling")
+ *   - equations of motion dx/dt = v, dv/dt = (q/m) E          (Sec. 2, Eq. eom; B_ext = E_ext = 0)
+ *   - second-order central FD Laplacian, matrix-free CG       (Sec. 3.2 "PCG solver")
+ *   - previous step's solution as the CG starting guess       (Sec. 4.1 "Setup")
+ * Readings where the paper is silent (grid centring, gauge, residual norm,
+ * integrator, tie-breaking) are stated at each function.  Mixed-precision
+ * refinement and the flexible CG used by the learned preconditioner are not in
+ * the paper; they follow the textbook definitions cited at each function.
+ *
+ * Conventions shared with the product (restated, not shared code):
+ *   grid: vertex-centred, value i sits at x = i*h, h = L/N, periodic, layout
+ *         [iz][iy][ix] with ix fastest;   inv_h = (double)N / L.
+ *   Floating point: IEEE binary64, round to nearest; this file must be compiled
+ *   with -ffp-contract=off and without -ffast-math.
+ *
+ * Every sum in this file is a plain sequential sum in index order.  Loops whose
+ * iterations are independent (one output element each) may run under OpenMP;
+ * that changes no rounding.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_IDX(N, ix, iy, iz) ((((int64_t)(iz)) * (N) + (iy)) * (int64_t)(N) + (ix))
+
+int or_abi_version(void) { return 3; }
+
+/* ------------------------------------------------------------------------ */
+/* Cell index and CIC fraction of one coordinate.
+ * s = x * (N/L); i = floor(s) clamped to [0, N-1]; w = s - i.
+ * When x rounds to s == N the clamp gives i = N-1, w = 1: all weight on the
+ * periodic image of vertex 0, which is the correct CIC limit.              */
+static void or_locate(double xd, int N, double inv_h, int *i, double *w)
+{
+    double s = xd * inv_h;
+    double f = floor(s);
+    int ii = (int)f;
+    if (ii > N - 1) ii = N - 1;
+    if (ii < 0) ii = 0;
+    *i = ii;
+    *w = s - (double)ii;
+}
+
+/* Cell key of each particle: (iz*N + iy)*N + ix.  */
+void or_cell_keys(int64_t np, int N, double L, const double *x, const double *y,
+                  const double *z, uint32_t *key)
+{
+    double inv_h = (double)N / L;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < np; ++p) {
+        int ix, iy, iz;
+        double wx, wy, wz;
+        or_locate(x[p], N, inv_h, &ix, &wx);
+        or_locate(y[p], N, inv_h, &iy, &wy);
+        or_locate(z[p], N, inv_h, &iz, &wz);
+        key[p] = (uint32_t)OR_IDX(N, ix, iy, iz);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stable sort by cell key, as a counting sort (the textbook stable sort for
+ * small integer keys): perm[j] is the input index of the j-th sorted
+ * particle; equal keys keep their input order.  cell_start has ncell+1
+ * entries: cell_start[c] is the first sorted slot of cell c.              */
+int or_sort_by_key(int64_t np, int64_t ncell, const uint32_t *key, int64_t *perm,
+                   int64_t *cell_start)
+{
+    int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell > 0 ? ncell : 1));
+    if (!fill) return -1;
+    for (int64_t c = 0; c <= ncell; ++c) cell_start[c] = 0;
+    for (int64_t p = 0; p < np; ++p) {
+        if ((int64_t)key[p] >= ncell) { free(fill); return -2; }
+        cell_start[key[p] + 1] += 1;
+    }
+    for (int64_t c = 0; c < ncell; ++c) cell_start[c + 1] += cell_start[c];
+    for (int64_t c = 0; c < ncell; ++c) fill[c] = cell_start[c];
+    for (int64_t p = 0; p < np; ++p) perm[fill[key[p]]++] = p;
+    free(fill);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cloud-in-cell charge deposit (scatter, Fig. pic-loop) plus the uniform
+ * neutralising background (Sec. 2) and the zero-mean projection the periodic
+ * problem needs.
+ *   rho_e[v] = (q / h^3) * sum_p W_p(v),   W_p(v) = prod_d W_d,
+ *   W_d = 1 - w_d for the lower vertex, w_d for the upper (periodic) one.
+ *   rho = rho_e + rho_bg;  b = rho - mean(rho).
+ * Writes rho_e (may be NULL) and b; returns ||b||_2.                         */
+double or_deposit(int64_t np, int N, double L, double q, double rho_bg,
+                  const double *x, const double *y, const double *z,
+                  double *rho_e_out, double *b)
+{
+    int64_t n3 = (int64_t)N * N * N;
+    double inv_h = (double)N / L;
+    double qh3 = q * (inv_h * inv_h * inv_h);
+    double *acc = (double *)calloc((size_t)n3, sizeof(double));
+    if (!acc) return -1.0;
+    for (int64_t p = 0; p < np; ++p) {
+        int i[3];
+        double w[3];
+        or_locate(x[p], N, inv_h, &i[0], &w[0]);
+        or_locate(y[p], N, inv_h, &i[1], &w[1]);
+        or_locate(z[p], N, inv_h, &i[2], &w[2]);
+        for (int c = 0; c < 2; ++c) {
+            double wz = c ? w[2] : 1.0 - w[2];
+            int vz = (i[2] + c) % N;
+            for (int bb = 0; bb < 2; ++bb) {
+                double wy = bb ? w[1] : 1.0 - w[1];
+                int vy = (i[1] + bb) % N;
+                for (int a = 0; a < 2; ++a) {
+                    double wx = a ? w[0] : 1.0 - w[0];
+                    int vx = (i[0] + a) % N;
+                    acc[OR_IDX(N, vx, vy, vz)] += (wz * wy) * wx;
+                }
+            }
+        }
+    }
+    double sum = 0.0;
+    for (int64_t v = 0; v < n3; ++v) {
+        double re = acc[v] * qh3;
+        if (rho_e_out) rho_e_out[v] = re;
+        b[v] = re + rho_bg;
+        sum += b[v];
+    }
+    double mean = sum / (double)n3;
+    double nb = 0.0;
+    for (int64_t v = 0; v < n3; ++v) {
+        b[v] = b[v] - mean;
+        nb += b[v] * b[v];
+    }
+    free(acc);
+    return sqrt(nb);
+}
+
+/* ------------------------------------------------------------------------ */
+/* A = -Lap_h, the 7-point second-order central-difference operator on the
+ * periodic grid (Sec. 3.2):  (A u)_i = (6 u_i - sum of 6 neighbours) / h^2.
+ * Neighbour sum taken as ((xm + xp) + (ym + yp)) + (zm + zp).               */
+void or_apply_A(int N, double L, const double *u, double *Au)
+{
+    double inv_h = (double)N / L;
+    double inv_h2 = inv_h * inv_h;
+#pragma omp parallel for schedule(static)
+    for (int iz = 0; iz < N; ++iz) {
+        int zm = (iz + N - 1) % N, zp = (iz + 1) % N;
+        for (int iy = 0; iy < N; ++iy) {
+            int ym = (iy + N - 1) % N, yp = (iy + 1) % N;
+            for (int ix = 0; ix < N; ++ix) {
+                int xm = (ix + N - 1) % N, xp = (ix + 1) % N;
+                double t = ((u[OR_IDX(N, xm, iy, iz)] + u[OR_IDX(N, xp, iy, iz)]) +
+                            (u[OR_IDX(N, ix, ym, iz)] + u[OR_IDX(N, ix, yp, iz)])) +
+                           (u[OR_IDX(N, ix, iy, zm)] + u[OR_IDX(N, ix, iy, zp)]);
+                Au[OR_IDX(N, ix, iy, iz)] = (6.0 * u[OR_IDX(N, ix, iy, iz)] - t) * inv_h2;
+            }
+        }
+    }
+}
+
+static double or_dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* r = b - A x;  returns ||r||_2.  */
+static double or_true_residual(int N, double L, const double *b, const double *x,
+                               double *r)
+{
+    int64_t n3 = (int64_t)N * N * N;
+    or_apply_A(N, L, x, r);
+    for (int64_t i = 0; i < n3; ++i) r[i] = b[i] - r[i];
+    return sqrt(or_dot(n3, r, r));
+}
+
+double or_residual_norm(int N, double L, const double *b, const double *x)
+{
+    int64_t n3 = (int64_t)N * N * N;
+    double *r = (double *)malloc(sizeof(double) * (size_t)n3);
+    if (!r) return -1.0;
+    double nr = or_true_residual(N, L, b, x, r);
+    free(r);
+    return nr;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Preconditioned CG (the PCG solver of Sec. 3.2 with the Jacobi
+ * preconditioner of the same section, M^{-1} = diag(A)^{-1} = (h^2/6) I),
+ * in the textbook form (Saad, Iterative Methods for Sparse Linear Systems,
+ * 2nd ed., Alg. 9.1), starting from the caller's x (the previous step's
+ * solution, Sec. 4.1).
+ * Stop rule (the paper gives only a tolerance, Sec. 4): the recursively
+ * updated residual must satisfy ||r|| <= rtol * ||b||; the true residual
+ * b - A x is then computed, and if it fails the same test it replaces r,
+ * p restarts from M^{-1} r, and iteration continues (residual replacement).
+ * ||b|| = 0 gives x = 0.
+ * info[0]=iterations, [1]=last recursive ||r||/||b||, [2]=true ||b-Ax||/||b||,
+ * [3]=converged (1/0), [4]=residual replacements.                         */
+void or_pcg(int N, double L, const double *b, double *x, double rtol, int64_t max_iter,
+            double *info)
+{
+    int64_t n3 = (int64_t)N * N * N;
+    double inv_h = (double)N / L;
+    double minv = 1.0 / (6.0 * (inv_h * inv_h));
+    double *r = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n3);
+    int64_t it = 0, repl = 0;
+    int converged = 0;
+    double rel = 0.0, trel = 0.0;
+    double nb = sqrt(or_dot(n3, b, b));
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < n3; ++i) x[i] = 0.0;
+        info[0] = 0; info[1] = 0.0; info[2] = 0.0; info[3] = 1; info[4] = 0;
+        free(r); free(z); free(p); free(q);
+        return;
+    }
+    double tol = rtol * nb;
+    double nr = or_true_residual(N, L, b, x, r);
+    rel = trel = nr / nb;
+    if (nr <= tol) converged = 1;
+    for (int64_t i = 0; i < n3; ++i) { z[i] = minv * r[i]; p[i] = z[i]; }
+    double rz = or_dot(n3, r, z);
+    while (!converged && it < max_iter) {
+        or_apply_A(N, L, p, q);
+        double alpha = rz / or_dot(n3, p, q);
+        for (int64_t i = 0; i < n3; ++i) {
+            x[i] = x[i] + alpha * p[i];
+            r[i] = r[i] - alpha * q[i];
+        }
+        ++it;
+        double rn = sqrt(or_dot(n3, r, r));
+        rel = rn / nb;
+        if (rn <= tol) {
+            double tn = or_true_residual(N, L, b, x, q);
+            trel = tn / nb;
+            if (tn <= tol) { converged = 1; break; }
+            /* residual replacement: r <- b - A x, restart the direction */
+            for (int64_t i = 0; i < n3; ++i) { r[i] = q[i]; z[i] = minv * r[i]; p[i] = z[i]; }
+            rz = or_dot(n3, r, z);
+            rel = tn / nb;
+            ++repl;
+            continue;
+        }
+        for (int64_t i = 0; i < n3; ++i) z[i] = minv * r[i];
+        double rz_new = or_dot(n3, r, z);
+        double beta = rz_new / rz;
+        rz = rz_new;
+        for (int64_t i = 0; i < n3; ++i) p[i] = z[i] + beta * p[i];
+    }
+    if (!converged) trel = or_residual_norm(N, L, b, x) / nb;
+    info[0] = (double)it; info[1] = rel; info[2] = trel; info[3] = converged; info[4] = (double)repl;
+    free(r); free(z); free(p); free(q);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Field from potential (Sec. 2, Eq. poisson: E = -grad phi) with the
+ * second-order central difference that matches the Laplacian:
+ *   E_d[i] = -(phi[i+e_d] - phi[i-e_d]) / (2h).
+ * The gauge is fixed first: phi <- phi - mean(phi) (written back).
+ * Returns W_x = (1/2) h^3 sum E_x^2, the energy of the x component
+ * (the quantity of Fig. correctness_landau, with eps0 = 1).               */
+double or_efield(int N, double L, double *phi, double *ex, double *ey, double *ez)
+{
+    int64_t n3 = (int64_t)N * N * N;
+    double inv_h = (double)N / L;
+    double ehalf = 0.5 * inv_h;
+    double h = L / (double)N;
+    double s = 0.0;
+    for (int64_t i = 0; i < n3; ++i) s += phi[i];
+    double mean = s / (double)n3;
+    for (int64_t i = 0; i < n3; ++i) phi[i] = phi[i] - mean;
+#pragma omp parallel for schedule(static)
+    for (int iz = 0; iz < N; ++iz) {
+        int zm = (iz + N - 1) % N, zp = (iz + 1) % N;
+        for (int iy = 0; iy < N; ++iy) {
+            int ym = (iy + N - 1) % N, yp = (iy + 1) % N;
+            for (int ix = 0; ix < N; ++ix) {
+                int xm = (ix + N - 1) % N, xp = (ix + 1) % N;
+                int64_t c = OR_IDX(N, ix, iy, iz);
+                ex[c] = -(phi[OR_IDX(N, xp, iy, iz)] - phi[OR_IDX(N, xm, iy, iz)]) * ehalf;
+                ey[c] = -(phi[OR_IDX(N, ix, yp, iz)] - phi[OR_IDX(N, ix, ym, iz)]) * ehalf;
+                ez[c] = -(phi[OR_IDX(N, ix, iy, zp)] - phi[OR_IDX(N, ix, iy, zm)]) * ehalf;
+            }
+        }
+    }
+    double w = 0.0;
+    for (int64_t i = 0; i < n3; ++i) w += ex[i] * ex[i];
+    return 0.5 * w * (h * h * h);
+}
+
+/* ------------------------------------------------------------------------ */
+/* CIC gather of the three field components at one particle (Sec. 2: the same
+ * shape as the scatter).  Sum order: z offset outer, then y, then x; each
+ * term ((Wz*Wy)*Wx) * E[v].                                                */
+static void or_gather_one(int N, double inv_h, double px, double py, double pz,
+                          const double *ex, const double *ey, const double *ez,
+                          double *Ep)
+{
+    int i[3];
+    double w[3];
+    or_locate(px, N, inv_h, &i[0], &w[0]);
+    or_locate(py, N, inv_h, &i[1], &w[1]);
+    or_locate(pz, N, inv_h, &i[2], &w[2]);
+    double sx = 0.0, sy = 0.0, sz = 0.0;
+    for (int c = 0; c < 2; ++c) {
+        double wz = c ? w[2] : 1.0 - w[2];
+        int vz = (i[2] + c) % N;
+        for (int bb = 0; bb < 2; ++bb) {
+            double wy = bb ? w[1] : 1.0 - w[1];
+            int vy = (i[1] + bb) % N;
+            for (int a = 0; a < 2; ++a) {
+                double wx = a ? w[0] : 1.0 - w[0];
+                int vx = (i[0] + a) % N;
+                int64_t v = OR_IDX(N, vx, vy, vz);
+                double W = (wz * wy) * wx;
+                sx = sx + W * ex[v];
+                sy = sy + W * ey[v];
+                sz = sz + W * ez[v];
+            }
+        }
+    }
+    Ep[0] = sx; Ep[1] = sy; Ep[2] = sz;
+}
+
+/* Periodic wrap of one coordinate into [0, L); assumes |step| < L.  The last
+ * test catches a tiny negative value whose x + L rounds up to L.          */
+static double or_wrap(double xn, double L)
+{
+    if (xn >= L) xn = xn - L;
+    if (xn < 0.0) xn = xn + L;
+    if (xn >= L) xn = 0.0;
+    return xn;
+}
+
+/* Gather + leapfrog push (Eq. eom, electrostatic, no external field):
+ *   v <- v + (dt*qm) * E(x);   x <- wrap(x + dt * v);   key <- cell key of x.
+ * dt*qm is formed once.  key may be NULL.                                  */
+void or_gather_push(int64_t np, int N, double L, double dt, double qm,
+                    double *x, double *y, double *z, double *vx, double *vy, double *vz,
+                    const double *ex, const double *ey, const double *ez, uint32_t *key)
+{
+    double inv_h = (double)N / L;
+    double coef = dt * qm;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < np; ++p) {
+        double Ep[3];
+        or_gather_one(N, inv_h, x[p], y[p], z[p], ex, ey, ez, Ep);
+        vx[p] = vx[p] + coef * Ep[0];
+        vy[p] = vy[p] + coef * Ep[1];
+        vz[p] = vz[p] + coef * Ep[2];
+        x[p] = or_wrap(x[p] + dt * vx[p], L);
+        y[p] = or_wrap(y[p] + dt * vy[p], L);
+        z[p] = or_wrap(z[p] + dt * vz[p], L);
+        if (key) {
+            int ix, iy, iz;
+            double w;
+            or_locate(x[p], N, inv_h, &ix, &w);
+            or_locate(y[p], N, inv_h, &iy, &w);
+            or_locate(z[p], N, inv_h, &iz, &w);
+            key[p] = (uint32_t)OR_IDX(N, ix, iy, iz);
+        }
+    }
+}
+
+/* Leapfrog start: v^{-1/2} = v^0 - (dt/2) qm E(x^0); positions unchanged.
+ * The factor is formed once as (-0.5 * dt) * qm.                          */
+void or_half_kick(int64_t np, int N, double L, double dt, double qm,
+                  const double *x, const double *y, const double *z,
+                  double *vx, double *vy, double *vz,
+                  const double *ex, const double *ey, const double *ez)
+{
+    double inv_h = (double)N / L;
+    double coef = (-0.5 * dt) * qm;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < np; ++p) {
+        double Ep[3];
+        or_gather_one(N, inv_h, x[p], y[p], z[p], ex, ey, ez, Ep);
+        vx[p] = vx[p] + coef * Ep[0];
+        vy[p] = vy[p] + coef * Ep[1];
+        vz[p] = vz[p] + coef * Ep[2];
+    }
+}
+
+/* CIC gather of a scalar grid field at each particle (same weights and order
+ * as or_gather_one); used by the deposit/gather adjoint pin.               */
+void or_gather_scalar(int64_t np, int N, double L, const double *x, const double *y,
+                      const double *z, const double *F, double *out)
+{
+    double inv_h = (double)N / L;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < np; ++p) {
+        double Ep[3];
+        or_gather_one(N, inv_h, x[p], y[p], z[p], F, F, F, Ep);
+        out[p] = Ep[0];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-precision operator for the mixed-precision solver: the same
+ * neighbour-sum order as or_apply_A, every operation in binary32.          */
+static void or_apply_A32(int N, float inv_h2f, const float *u, float *Au)
+{
+#pragma omp parallel for schedule(static)
+    for (int iz = 0; iz < N; ++iz) {
+        int zm = (iz + N - 1) % N, zp = (iz + 1) % N;
+        for (int iy = 0; iy < N; ++iy) {
+            int ym = (iy + N - 1) % N, yp = (iy + 1) % N;
+            for (int ix = 0; ix < N; ++ix) {
+                int xm = (ix + N - 1) % N, xp = (ix + 1) % N;
+                float t = ((u[OR_IDX(N, xm, iy, iz)] + u[OR_IDX(N, xp, iy, iz)]) +
+                           (u[OR_IDX(N, ix, ym, iz)] + u[OR_IDX(N, ix, yp, iz)])) +
+                          (u[OR_IDX(N, ix, iy, zm)] + u[OR_IDX(N, ix, iy, zp)]);
+                Au[OR_IDX(N, ix, iy, iz)] = (6.0f * u[OR_IDX(N, ix, iy, iz)] - t) * inv_h2f;
+            }
+        }
+    }
+}
+
+/* FP64 accumulation of a binary32 dot product: each product formed in FP64. */
+static double or_dot32(int64_t n, const float *a, const float *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += (double)a[i] * (double)b[i];
+    return s;
+}
+
+/* Mixed-precision solve (not in the paper; classical iterative refinement,
+ * Wilkinson / Moler, as analysed by Carson & Higham 2018):
+ *   outer, FP64:  r = b - A x;  stop when ||r|| <= rtol ||b||;
+ *   inner, FP32 vectors / FP32 operator / FP32 Jacobi, dot products
+ *   accumulated in FP64:  Jacobi-PCG on A d = r from d = 0, stopped when
+ *   ||r_in|| <= inner_rtol ||r|| or after max_inner iterations;
+ *   outer, FP64:  x <- x + d.
+ * The inner right-hand side is r scaled by 1/||r|| before rounding to FP32
+ * (and d scaled back), so FP32 range never limits the refinement.
+ * info: [0]=outer steps, [1]=total inner iterations, [2]=true rel. residual,
+ *       [3]=converged.                                                    */
+void or_mixed_pcg(int N, double L, const double *b, double *x, double rtol,
+                  int64_t max_outer, double inner_rtol, int64_t max_inner, double *info)
+{
+    int64_t n3 = (int64_t)N * N * N;
+    double inv_h = (double)N / L;
+    float inv_h2f = (float)(inv_h * inv_h);
+    float minvf = (float)(1.0 / (6.0 * (inv_h * inv_h)));
+    double *r = (double *)malloc(sizeof(double) * (size_t)n3);
+    float *ri = (float *)malloc(sizeof(float) * (size_t)n3);
+    float *d = (float *)malloc(sizeof(float) * (size_t)n3);
+    float *p = (float *)malloc(sizeof(float) * (size_t)n3);
+    float *q = (float *)malloc(sizeof(float) * (size_t)n3);
+    float *zz = (float *)malloc(sizeof(float) * (size_t)n3);
+    int64_t outer = 0, inner_total = 0;
+    int converged = 0;
+    double nb = sqrt(or_dot(n3, b, b));
+    double trel = 0.0;
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < n3; ++i) x[i] = 0.0;
+        info[0] = 0; info[1] = 0; info[2] = 0.0; info[3] = 1;
+        free(r); free(ri); free(d); free(p); free(q); free(zz);
+        return;
+    }
+    for (;;) {
+        double nr = or_true_residual(N, L, b, x, r);
+        trel = nr / nb;
+        if (nr <= rtol * nb) { converged = 1; break; }
+        if (outer >= max_outer) break;
+        ++outer;
+        double sc = 1.0 / nr;
+        for (int64_t i = 0; i < n3; ++i) { ri[i] = (float)(r[i] * sc); d[i] = 0.0f; }
+        double n0 = sqrt(or_dot32(n3, ri, ri));
+        for (int64_t i = 0; i < n3; ++i) { zz[i] = minvf * ri[i]; p[i] = zz[i]; }
+        double rz = or_dot32(n3, ri, zz);
+        for (int64_t k = 0; k < max_inner; ++k) {
+            or_apply_A32(N, inv_h2f, p, q);
+            double alpha = rz / or_dot32(n3, p, q);
+            float af = (float)alpha;
+            for (int64_t i = 0; i < n3; ++i) {
+                d[i] = d[i] + af * p[i];
+                ri[i] = ri[i] - af * q[i];
+            }
+            ++inner_total;
+            double rn = sqrt(or_dot32(n3, ri, ri));
+            if (rn <= inner_rtol * n0) break;
+            for (int64_t i = 0; i < n3; ++i) zz[i] = minvf * ri[i];
+            double rz_new = or_dot32(n3, ri, zz);
+            float bf = (float)(rz_new / rz);
+            rz = rz_new;
+            for (int64_t i = 0; i < n3; ++i) p[i] = zz[i] + bf * p[i];
+        }
+        for (int64_t i = 0; i < n3; ++i) x[i] = x[i] + nr * (double)d[i];
+    }
+    info[0] = (double)outer; info[1] = (double)inner_total; info[2] = trel; info[3] = converged;
+    free(r); free(ri); free(d); free(p); free(q); free(zz);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Flexible preconditioned CG (not in the paper; Notay, SIAM J. Sci. Comput.
+ * 22 (2000); Golub & Ye, SIAM J. Sci. Comput. 21 (1999)) with a possibly
+ * nonlinear preconditioner z = M(r) supplied as a callback:
+ *   r = b - A x;  z = M(r);  p = z
+ *   loop:  q = A p;  alpha = (z.r)/(p.q);  x += alpha p;  r -= alpha q;
+ *          stop test as in or_pcg;  z' = M(r);
+ *          beta = -(z'.q)/(p.q);  p = z' + beta p.
+ * Fallback to Jacobi-PCG from the current x (r = b - A x, p = M_J^{-1} r),
+ * permanently for the solve, when (z.r) <= 0, anything is non-finite, or the
+ * best ||r|| has not improved by at least 1% over `window` consecutive
+ * iterations.  After the switch the iteration is exactly or_pcg's loop.
+ * info: [0]=total iterations, [1]=flexible iterations, [2]=true rel.
+ * residual, [3]=converged, [4]=fell back (1/0).                           */
+typedef void (*or_precond_fn)(const double *r, double *z, void *user);
+
+void or_fcg(int N, double L, const double *b, double *x, double rtol, int64_t max_iter,
+            int window, or_precond_fn M, void *user, double *info)
+{
+    int64_t n3 = (int64_t)N * N * N;
+    double inv_h = (double)N / L;
+    double minv = 1.0 / (6.0 * (inv_h * inv_h));
+    double *r = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n3);
+    int64_t it = 0, flex_it = 0;
+    int converged = 0, fell_back = 0;
+    double nb = sqrt(or_dot(n3, b, b));
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < n3; ++i) x[i] = 0.0;
+        info[0] = 0; info[1] = 0; info[2] = 0.0; info[3] = 1; info[4] = 0;
+        free(r); free(z); free(p); free(q);
+        return;
+    }
+    double tol = rtol * nb;
+    double nr = or_true_residual(N, L, b, x, r);
+    double best = nr;
+    int since_best = 0;
+    if (nr <= tol) converged = 1;
+    int flexible = 1;
+    double rz = 0.0;
+    if (!converged) {
+        M(r, z, user);
+        rz = or_dot(n3, z, r);
+        if (!(rz > 0.0) || !isfinite(rz)) flexible = 0;
+        if (flexible) for (int64_t i = 0; i < n3; ++i) p[i] = z[i];
+    }
+    while (!converged && it < max_iter) {
+        if (!flexible) {
+            if (!fell_back) {
+                fell_back = 1;
+                nr = or_true_residual(N, L, b, x, r);
+                if (nr <= tol) { converged = 1; break; }
+                for (int64_t i = 0; i < n3; ++i) { z[i] = minv * r[i]; p[i] = z[i]; }
+                rz = or_dot(n3, r, z);
+            }
+            or_apply_A(N, L, p, q);
+            double alpha = rz / or_dot(n3, p, q);
+            for (int64_t i = 0; i < n3; ++i) { x[i] = x[i] + alpha * p[i]; r[i] = r[i] - alpha * q[i]; }
+            ++it;
+            double rn = sqrt(or_dot(n3, r, r));
+            if (rn <= tol) {
+                double tn = or_true_residual(N, L, b, x, q);
+                if (tn <= tol) { converged = 1; break; }
+                for (int64_t i = 0; i < n3; ++i) { r[i] = q[i]; z[i] = minv * r[i]; p[i] = z[i]; }
+                rz = or_dot(n3, r, z);
+                continue;
+            }
+            for (int64_t i = 0; i < n3; ++i) z[i] = minv * r[i];
+            double rz_new = or_dot(n3, r, z);
+            double beta = rz_new / rz;
+            rz = rz_new;
+            for (int64_t i = 0; i < n3; ++i) p[i] = z[i] + beta * p[i];
+            continue;
+        }
+        or_apply_A(N, L, p, q);
+        double pq = or_dot(n3, p, q);
+        double alpha = rz / pq;
+        if (!isfinite(alpha) || !(pq > 0.0)) { flexible = 0; continue; }
+        for (int64_t i = 0; i < n3; ++i) { x[i] = x[i] + alpha * p[i]; r[i] = r[i] - alpha * q[i]; }
+        ++it; ++flex_it;
+        double rn = sqrt(or_dot(n3, r, r));
+        if (!isfinite(rn)) { flexible = 0; continue; }
+        if (rn <= tol) {
+            double tn = or_true_residual(N, L, b, x, z);
+            if (tn <= tol) { converged = 1; break; }
+            for (int64_t i = 0; i < n3; ++i) r[i] = z[i];
+            rn = tn;
+        }
+        if (rn < 0.99 * best) { best = rn; since_best = 0; }
+        else if (++since_best >= window) { flexible = 0; continue; }
+        M(r, z, user);
+        double zr = or_dot(n3, z, r);
+        if (!(zr > 0.0) || !isfinite(zr)) { flexible = 0; continue; }
+        double beta = -or_dot(n3, z, q) / pq;
+        if (!isfinite(beta)) { flexible = 0; continue; }
+        rz = zr;
+        for (int64_t i = 0; i < n3; ++i) p[i] = z[i] + beta * p[i];
+    }
+    double trel = or_residual_norm(N, L, b, x) / nb;
+    info[0] = (double)it; info[1] = (double)flex_it; info[2] = trel; info[3] = converged;
+    info[4] = fell_back;
+    free(r); free(z); free(p); free(q);
+}
+
+/* The Jacobi preconditioner as an or_precond_fn (user points at h^2/6). */
+void or_precond_jacobi(const double *r, double *z, void *user)
+{
+    const double *par = (const double *)user; /* par[0] = h^2/6, par[1] = n3 */
+    int64_t n3 = (int64_t)par[1];
+    for (int64_t i = 0; i < n3; ++i) z[i] = par[0] * r[i];
+}

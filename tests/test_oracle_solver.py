@@ -1,0 +1,251 @@
+"""Pins of the oracle's field pieces (operator, PCG, field, mixed precision,
+flexible CG) against closed forms, dense and FFT solves.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2605_05469_amd import synth
+
+
+def _grid(N, L):
+    c = np.arange(N) * (L / N)
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    return X, Y, Z
+
+
+def _lam(N, L, m):
+    h = L / N
+    return sum(2.0 - 2.0 * math.cos(2 * math.pi * md / N) for md in m) / h ** 2
+
+
+def _dense_A(N, L):
+    """A = (T(x)I(x)I + I(x)T(x)I + I(x)I(x)T)/h^2 with T = circ(-1, 2, -1):
+    an assembly independent of the stencil code."""
+    T = 2 * np.eye(N) - np.roll(np.eye(N), 1, axis=1) - np.roll(np.eye(N), -1, axis=1)
+    I = np.eye(N)
+    h = L / N
+    return (np.kron(np.kron(T, I), I) + np.kron(np.kron(I, T), I) + np.kron(np.kron(I, I), T)) / h ** 2
+
+
+def _fft_solve(N, L, b):
+    """Exact discrete zero-mean solution: phi_hat(m) = b_hat(m)/lambda(m)."""
+    h = L / N
+    m = np.arange(N)
+    s = (2 - 2 * np.cos(2 * np.pi * m / N)) / h ** 2
+    lam = s[:, None, None] + s[None, :, None] + s[None, None, :]
+    bh = np.fft.fftn(b.reshape(N, N, N))
+    lam[0, 0, 0] = 1.0
+    ph = bh / lam
+    ph[0, 0, 0] = 0.0
+    return np.real(np.fft.ifftn(ph)).ravel()
+
+
+# ------------------------------------------------------------- operator ---
+
+@pytest.mark.parametrize("m", [(1, 0, 0), (0, 2, 0), (1, 1, 3), (4, 4, 4)])
+def test_laplacian_single_mode_eigenvalue(orc, m):
+    N, L = 8, 4 * math.pi
+    X, Y, Z = _grid(N, L)
+    k = 2 * np.pi / L
+    u = np.cos(k * (m[0] * X + m[1] * Y + m[2] * Z)).ravel()
+    Au = orc.apply_A(N, L, u)
+    lam = _lam(N, L, m)
+    assert np.allclose(Au, lam * u, rtol=0, atol=1e-12 * lam)
+
+
+def test_laplacian_matches_kron_assembly_symmetric_and_kills_constants(orc):
+    N, L = 6, 2.5
+    A = _dense_A(N, L)
+    rng = np.random.default_rng(11)
+    u, v = rng.standard_normal((2, N ** 3))
+    assert np.allclose(orc.apply_A(N, L, u), A @ u, rtol=1e-13, atol=1e-11)
+    assert abs(orc.apply_A(N, L, u) @ v - u @ orc.apply_A(N, L, v)) < 1e-11 * np.abs(A).sum()
+    assert np.all(orc.apply_A(N, L, np.full(N ** 3, 3.7)) == 0.0)
+
+
+# ------------------------------------------------------------------ PCG ---
+
+@pytest.mark.parametrize("N", [4, 6, 8])
+def test_pcg_matches_dense_direct_solve(orc, N):
+    L = 4 * math.pi
+    rng = np.random.default_rng(N)
+    b = rng.standard_normal(N ** 3)
+    b -= b.mean()
+    A1 = _dense_A(N, L) + np.ones((N ** 3, N ** 3)) / N ** 3
+    ref = np.linalg.solve(A1, b)
+    x, info = orc.pcg(N, L, b, np.zeros(N ** 3), 1e-14, 10000)
+    assert info["converged"] and info["true_rel_res"] <= 1e-14
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_pcg_matches_fft_exact_solution(orc, N):
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=100 + N)
+    b, nb = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    ref = _fft_solve(N, P.L, b)
+    x, info = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-12, 20000)
+    assert info["converged"] and info["true_rel_res"] <= 1e-12
+    kappa = 3.0 / math.sin(math.pi / N) ** 2
+    assert np.linalg.norm(x - ref) <= kappa * 1e-12 * np.linalg.norm(ref)
+
+
+def test_pcg_single_mode_converges_in_one_iteration(orc):
+    N, L = 16, 4 * math.pi
+    X, Y, Z = _grid(N, L)
+    k = 2 * np.pi / L
+    b = np.cos(k * (X + 2 * Y)).ravel()
+    x, info = orc.pcg(N, L, b, np.zeros(N ** 3), 1e-10, 100)
+    assert info["iters"] == 1 and info["converged"]
+    assert np.allclose(x, b / _lam(N, L, (1, 2, 0)), rtol=0, atol=1e-13)
+
+
+def test_pcg_terminates_within_number_of_distinct_eigenvalues(orc):
+    N, L = 16, 4 * math.pi
+    X, Y, Z = _grid(N, L)
+    k = 2 * np.pi / L
+    b = (np.cos(k * X) + 0.5 * np.sin(k * 3 * Y) - 2.0 * np.cos(k * (2 * Z + X))).ravel()
+    x, info = orc.pcg(N, L, b, np.zeros(N ** 3), 1e-10, 100)
+    assert info["converged"] and info["iters"] <= 3
+
+
+def test_pcg_zero_rhs_and_exact_warm_start(orc):
+    N, L = 8, 1.0
+    x, info = orc.pcg(N, L, np.zeros(N ** 3), np.ones(N ** 3), 1e-10, 100)
+    assert info["iters"] == 0 and info["converged"] and np.all(x == 0)
+    rng = np.random.default_rng(12)
+    b = rng.standard_normal(N ** 3)
+    b -= b.mean()
+    sol = _fft_solve(N, L, b)
+    x, info = orc.pcg(N, L, b, sol, 1e-10, 100)
+    assert info["iters"] == 0 and info["converged"]
+
+
+def test_pcg_warm_start_is_used(orc):
+    """Sec. 4.1: the previous solution is the starting guess; a nearby guess
+    needs fewer iterations than zero."""
+    N = 16
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=13)
+    b, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    sol = _fft_solve(N, P.L, b)
+    _, cold = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 1000)
+    _, warm = orc.pcg(N, P.L, b, sol * (1 + 1e-4), 1e-10, 1000)
+    assert warm["iters"] < cold["iters"]
+
+
+def test_pcg_not_converged_reports(orc):
+    N = 16
+    rng = np.random.default_rng(14)
+    b = rng.standard_normal(N ** 3)
+    b -= b.mean()
+    _, info = orc.pcg(N, 1.0, b, np.zeros(N ** 3), 1e-10, 3)
+    assert not info["converged"] and info["iters"] == 3 and info["true_rel_res"] > 1e-10
+
+
+# ---------------------------------------------------------------- field ---
+
+def test_efield_single_mode_closed_form(orc):
+    N, L = 16, 4 * math.pi
+    h = L / N
+    X, Y, Z = _grid(N, L)
+    k = 2 * np.pi / L * 2
+    phi = np.cos(k * Y).ravel() + 3.0  # a constant offset is removed by the gauge
+    p2, ex, ey, ez, wx = orc.efield(N, L, phi)
+    assert abs(p2.mean()) < 1e-15
+    assert np.allclose(ey, (math.sin(k * h) / h) * np.sin(k * Y).ravel(), rtol=0, atol=1e-14)
+    assert np.all(np.abs(ex) < 1e-15) and np.all(np.abs(ez) < 1e-15)
+    assert wx < 1e-28
+    for e in (ex, ey, ez):
+        assert abs(e.sum()) < 1e-12
+
+
+def test_field_energy_closed_form(orc):
+    """phi = cos(kx): W_x = (1/2) h^3 sum E_x^2 = (1/4) L^3 (sin(kh)/h)^2."""
+    N, L = 16, 4 * math.pi
+    h = L / N
+    X, Y, Z = _grid(N, L)
+    k = 2 * np.pi / L
+    _, ex, _, _, wx = orc.efield(N, L, np.cos(k * X).ravel())
+    assert math.isclose(wx, 0.25 * L ** 3 * (math.sin(k * h) / h) ** 2, rel_tol=1e-12)
+
+
+def test_momentum_invariant(orc):
+    """Symmetric A and the antisymmetric central gradient commute, so
+    sum_i b_i E_i = sum_i r_i E_i ~ 0 for the solved phi."""
+    N = 16
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=15)
+    b, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    phi, _ = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-12, 5000)
+    _, ex, ey, ez, _ = orc.efield(N, P.L, phi)
+    for e in (ex, ey, ez):
+        assert abs(b @ e) <= 1e-10 * np.linalg.norm(b) * np.linalg.norm(e)
+
+
+# -------------------------------------------------------- mixed precision --
+
+def test_mixed_precision_reaches_fp64_tolerance(orc):
+    N = 32
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=16)
+    b, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    ref = _fft_solve(N, P.L, b)
+    x, info = orc.mixed_pcg(N, P.L, b, np.zeros(N ** 3), 1e-10)
+    assert info["converged"] and info["true_rel_res"] <= 1e-10
+    # true residual measured independently of the oracle's operator
+    r = b - _fft_apply(N, P.L, x)
+    assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(b)
+    kappa = 3.0 / math.sin(math.pi / N) ** 2
+    assert np.linalg.norm(x - ref) <= kappa * 1e-10 * np.linalg.norm(ref)
+    # each refinement step contracts by about the inner tolerance (1e-3)
+    assert info["outer"] <= 5
+
+
+def _fft_apply(N, L, u):
+    h = L / N
+    m = np.arange(N)
+    s = (2 - 2 * np.cos(2 * np.pi * m / N)) / h ** 2
+    lam = s[:, None, None] + s[None, :, None] + s[None, None, :]
+    return np.real(np.fft.ifftn(np.fft.fftn(u.reshape(N, N, N)) * lam)).ravel()
+
+
+# ---------------------------------------------------------- flexible CG ---
+
+def _landau_rhs(orc, N, seed):
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=seed)
+    b, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    return P, b
+
+
+def test_fcg_with_jacobi_matches_pcg_iterations(orc):
+    N = 16
+    P, b = _landau_rhs(orc, N, 17)
+    c = (P.L / N) ** 2 / 6
+    _, pinfo = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 5000)
+    x, finfo = orc.fcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 5000, lambda r: c * r)
+    assert finfo["converged"] and not finfo["fell_back"]
+    assert abs(finfo["iters"] - pinfo["iters"]) <= 1
+
+
+def test_fcg_exact_preconditioner_one_iteration(orc):
+    N = 16
+    P, b = _landau_rhs(orc, N, 18)
+    x, info = orc.fcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 100, lambda r: _fft_solve(N, P.L, r))
+    assert info["converged"] and info["iters"] == 1
+
+
+@pytest.mark.parametrize("bad", ["neg", "nan", "zero", "noise"])
+def test_fcg_fallback_on_bad_preconditioner(orc, bad):
+    N = 16
+    P, b = _landau_rhs(orc, N, 19)
+    rng = np.random.default_rng(0)
+    nets = {"neg": lambda r: -r, "nan": lambda r: np.full_like(r, np.nan),
+            "zero": lambda r: np.zeros_like(r),
+            "noise": lambda r: np.abs(rng.standard_normal(r.size)) * np.abs(r).max()}
+    x, info = orc.fcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 5000, nets[bad])
+    assert info["converged"] and info["true_rel_res"] <= 1e-10
+    if bad != "noise":
+        assert info["fell_back"]

@@ -1,0 +1,144 @@
+"""Pins of the network oracle (oracle.unet) against library convolutions,
+adjoint identities, finite differences and torch's Adam.  CPU only."""
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+from oracle import unet
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a))
+
+
+def test_bf16_rounding_matches_library():
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, -2.5e-3, 3.0e5, 1e-30, 65504.0, 0.0])
+    exp = torch.tensor(vals, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(unet.bf16(vals), exp)
+    assert unet.bf16(1 + 2 ** -8) == 1.0 and unet.bf16(1 + 3 * 2 ** -8) == 1 + 2 ** -6
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(10000) * 10.0 ** rng.integers(-5, 5, 10000)
+    exp = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(unet.bf16(x), exp)
+
+
+def test_conv3_matches_torch_circular():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((3, 6, 6, 6))
+    W = rng.standard_normal((4, 3, 3, 3, 3))
+    b = rng.standard_normal(4)
+    ref = F.conv3d(F.pad(_t(x)[None], (1, 1, 1, 1, 1, 1), mode="circular"), _t(W), _t(b))[0].numpy()
+    assert np.allclose(unet.conv3_fwd(x, W, b), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_down_up_match_torch():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((3, 8, 8, 8))
+    Wd = rng.standard_normal((5, 3, 2, 2, 2))
+    b = rng.standard_normal(5)
+    ref = F.conv3d(_t(x)[None], _t(Wd), _t(b), stride=2)[0].numpy()
+    assert np.allclose(unet.down_fwd(x, Wd, b), ref, rtol=1e-12, atol=1e-12)
+    xc = rng.standard_normal((5, 4, 4, 4))
+    Wu = rng.standard_normal((5, 3, 2, 2, 2))
+    bu = rng.standard_normal(3)
+    ref = F.conv_transpose3d(_t(xc)[None], _t(Wu), _t(bu), stride=2)[0].numpy()
+    assert np.allclose(unet.up_fwd(xc, Wu, bu), ref, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["conv3", "down", "up"])
+def test_adjoint_identities(kind):
+    rng = np.random.default_rng(3)
+    ci, co = 3, 4
+    n_in = 8
+    W = rng.standard_normal(unet.weight_shape(kind, ci, co))
+    x = rng.standard_normal((ci, n_in, n_in, n_in))
+    zero = np.zeros(co)
+    fwd = {"conv3": unet.conv3_fwd, "down": unet.down_fwd, "up": unet.up_fwd}[kind]
+    if kind == "up":
+        x = rng.standard_normal((ci, 4, 4, 4))
+    y = fwd(x, W, zero)
+    dy = rng.standard_normal(y.shape)
+    bd = {"conv3": unet.conv3_bwd_data, "down": unet.down_bwd_data, "up": unet.up_bwd_data}[kind]
+    bw = {"conv3": unet.conv3_bwd_weight, "down": unet.down_bwd_weight,
+          "up": unet.up_bwd_weight}[kind]
+    lhs = np.sum(y * dy)
+    assert np.isclose(lhs, np.sum(x * bd(dy, W)), rtol=1e-12)
+    dW, db = bw(x, dy)
+    assert np.isclose(lhs, np.sum(W * dW), rtol=1e-12)
+    assert np.allclose(db, dy.sum(axis=(1, 2, 3)))
+
+
+def test_network_gradient_finite_differences():
+    specs = unet.layer_specs(2, 3, 4)
+    p = unet.init_params(seed=4, c1=2, c2=3, c3=4)
+    rng = np.random.default_rng(5)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = 0.1 * rng.standard_normal(p[k].shape)
+    x = rng.standard_normal((8, 8, 8))
+    dout = rng.standard_normal((8, 8, 8))
+    out, acts = unet.forward(p, x, specs, round_bf16=False)
+    grads, _ = unet.backward(p, acts, dout, specs, round_bf16=False)
+
+    def f(pp):
+        return np.sum(unet.forward(pp, x, specs, round_bf16=False)[0] * dout)
+
+    eps = 1e-6
+    for name in ("e1a.W", "d1.W", "b3a.W", "u2.W", "u1.b", "out.W", "e2c.b", "d2.W"):
+        flat = p[name].ravel()
+        for j in rng.choice(flat.size, size=min(3, flat.size), replace=False):
+            pp = {k: v.copy() for k, v in p.items()}
+            pp[name].ravel()[j] += eps
+            fp = f(pp)
+            pp[name].ravel()[j] -= 2 * eps
+            fm = f(pp)
+            fd = (fp - fm) / (2 * eps)
+            an = grads[name].ravel()[j]
+            assert abs(fd - an) <= 1e-7 * max(1.0, abs(an)), (name, j, fd, an)
+
+
+def test_loss_gradient_finite_differences():
+    rng = np.random.default_rng(6)
+    o, t, r = rng.standard_normal((3, 6, 6, 6))
+    L, g = unet.loss(o, t, r, lam=0.7)
+    eps = 1e-6
+    for j in rng.choice(o.size, 5, replace=False):
+        op = o.copy(); op.ravel()[j] += eps
+        om = o.copy(); om.ravel()[j] -= eps
+        fd = (unet.loss(op, t, r, 0.7)[0] - unet.loss(om, t, r, 0.7)[0]) / (2 * eps)
+        assert abs(fd - g.ravel()[j]) <= 1e-7 * max(1.0, abs(fd))
+
+
+def test_adam_matches_torch():
+    rng = np.random.default_rng(7)
+    th = rng.standard_normal(50)
+    tt = torch.tensor(th.copy(), requires_grad=True)
+    opt = torch.optim.Adam([tt], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    m = np.zeros(50); v = np.zeros(50)
+    for step in range(1, 6):
+        g = rng.standard_normal(50)
+        th, m, v = unet.adam(th, g, m, v, step)
+        tt.grad = torch.tensor(g)
+        opt.step()
+    assert np.allclose(th, tt.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+def test_preconditioner_scale_equivariance_and_zero_mean():
+    specs = unet.layer_specs(2, 3, 4)
+    p = unet.init_params(seed=8, c1=2, c2=3, c3=4)
+    r = np.random.default_rng(9).standard_normal(8 ** 3)
+    z = unet.precondition(p, r, 0.3, specs)
+    assert abs(z.mean()) < 1e-14 * np.abs(z).max()
+    assert np.array_equal(unet.precondition(p, 4.0 * r, 0.3, specs), 4.0 * z)
+    assert np.all(unet.precondition(p, 0 * r, 0.3, specs) == 0)
+
+
+def test_flatten_roundtrip_and_sizes():
+    specs = unet.layer_specs()
+    p = unet.init_params(seed=1)
+    flat = unet.flatten(p, specs)
+    q = unet.unflatten(flat, specs)
+    assert all(np.array_equal(p[k], q[k]) for k in p)
+    n = sum(int(np.prod(unet.weight_shape(k, a, b))) + b for (_, k, a, b) in specs)
+    assert flat.size == n
