@@ -70,6 +70,7 @@ def lib():
                                    _dp, _dp, _dp, _dp, _dp, _dp]
         L.or_gather_scalar.argtypes = [c_i64, c_int, c_dbl, _dp, _dp, _dp, _dp, _dp]
         L.or_mixed_pcg.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_dbl, c_i64, _dp]
+        L.or_deposit_vertices.argtypes = [c_i64, c_int, c_dbl, c_dbl, _dp, _dp, _dp, c_i64, _i64p, _dp]
         L.or_fcg.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_int, PRECOND_FN,
                              ctypes.c_void_p, _dp]
         _lib = L
@@ -113,6 +114,15 @@ def deposit(N: int, L: float, q: float, rho_bg: float, x, y, z, want_rho_e=False
     if want_rho_e:
         return b, nb, rho_e
     return b, nb
+
+
+def deposit_vertices(N: int, L: float, q: float, x, y, z, vid) -> np.ndarray:
+    """rho_e at the listed vertices from the listed particles (no background)."""
+    x, y, z = _f64(x), _f64(y), _f64(z)
+    vid = np.ascontiguousarray(vid, dtype=np.int64)
+    out = np.empty(vid.size)
+    lib().or_deposit_vertices(x.shape[0], N, L, q, x, y, z, vid.size, vid, out)
+    return out
 
 
 def apply_A(N: int, L: float, u) -> np.ndarray:

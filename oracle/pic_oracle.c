@@ -623,3 +623,34 @@ void or_precond_jacobi(const double *r, double *z, void *user)
     int64_t n3 = (int64_t)par[1];
     for (int64_t i = 0; i < n3; ++i) z[i] = par[0] * r[i];
 }
+
+/* ------------------------------------------------------------------------ */
+/* The deposit definition evaluated at single vertices (for sampled checks at
+ * sizes where the whole grid is out of reach): out[k] = sum over the given
+ * particles, in order, of the CIC weight of particle p at vertex vid[k],
+ * times q/h^3.  Particles whose cell is not adjacent contribute nothing.   */
+void or_deposit_vertices(int64_t np, int N, double L, double q, const double *x,
+                         const double *y, const double *z, int64_t nv, const int64_t *vid,
+                         double *out)
+{
+    double inv_h = (double)N / L;
+    double qh3 = q * (inv_h * inv_h * inv_h);
+    for (int64_t k = 0; k < nv; ++k) {
+        int vx = (int)(vid[k] % N), vy = (int)((vid[k] / N) % N), vz = (int)(vid[k] / ((int64_t)N * N));
+        double acc = 0.0;
+        for (int64_t p = 0; p < np; ++p) {
+            int i[3];
+            double w[3];
+            or_locate(x[p], N, inv_h, &i[0], &w[0]);
+            or_locate(y[p], N, inv_h, &i[1], &w[1]);
+            or_locate(z[p], N, inv_h, &i[2], &w[2]);
+            int c = (vz - i[2] + N) % N, bb = (vy - i[1] + N) % N, a = (vx - i[0] + N) % N;
+            if (c > 1 || bb > 1 || a > 1) continue;
+            double wz = c ? w[2] : 1.0 - w[2];
+            double wy = bb ? w[1] : 1.0 - w[1];
+            double wx = a ? w[0] : 1.0 - w[0];
+            acc += (wz * wy) * wx;
+        }
+        out[k] = acc * qh3;
+    }
+}

@@ -251,3 +251,13 @@ def test_cold_plasma_oscillation_frequency(orc):
     w_theory = 2.0 / dt * math.asin(dt / 2 * 1.0)
     assert len(zc) >= 4
     assert abs(w - w_theory) / w_theory < 0.01
+
+
+def test_deposit_vertices_matches_full_deposit(orc):
+    N = 8
+    P = synth.LandauParams(N=N, ppc=4)
+    parts = synth.landau_particles_np(N, 4, seed=21)
+    _, _, re = orc.deposit(N, P.L, P.q, 0.0, *parts[:3], want_rho_e=True)
+    vid = np.array([0, 7, 63, 64, 200, N ** 3 - 1])
+    got = orc.deposit_vertices(N, P.L, P.q, *parts[:3], vid)
+    assert np.allclose(got, re[vid], rtol=1e-13, atol=1e-13 * np.abs(re).max())
