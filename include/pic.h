@@ -1,0 +1,211 @@
+/*
+ * pic.h -- C ABI of the MI355X (gfx950) electrostatic PIC hot path.
+ *
+ * The operations are those of the PIC loop of "A Comparison of Massively
+ * Parallel Performance Portable Particle-in-Cell schemes for electrostatic
+ * kinetic plasma simulations" (PASC'26), Sec. 2, Fig. pic-loop:
+ *   scatter (CIC deposit) -> solve (matrix-free FD PCG, Sec. 3.2)
+ *   -> gather (CIC) -> push (Eq. eom),
+ * on the periodic Landau-damping box of Sec. 2.1.
+ *
+ * Conventions (every entry point):
+ *   - Grid: N points per axis, vertex-centred (value i at x = i*h, h = L/N),
+ *     periodic, FP64 arrays of N^3 values laid out [iz][iy][ix], ix fastest.
+ *   - Particles: structure of arrays, FP64 x, y, z, vx, vy, vz, positions in
+ *     [0, L).  All macro-particles carry the same charge q.
+ *   - Every array argument is a DEVICE pointer owned by the caller; the library
+ *     never frees it and keeps no reference after the call returns.  Host
+ *     pointers are marked "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on that stream unless an argument marked "host
+ *     out" is non-NULL, in which case the call synchronises `stream` once
+ *     before returning.
+ *   - Return value: PIC_OK (0); PIC_NOT_CONVERGED (+1, not fatal: outputs hold
+ *     the last iterate); or a negative error code with a message available
+ *     from pic_last_error().  No exception or abort crosses the ABI.
+ *   - One context per stream; a context is not safe for concurrent use.
+ *   - Requirements checked on entry: N a multiple of 32, 32 <= N <= 2048,
+ *     N^3 < 2^32, 0 <= np <= np_max, non-NULL required pointers, 8-byte
+ *     aligned arrays.  Violations return PIC_ERR_INVALID and launch nothing.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PIC_OK = 0,
+    PIC_NOT_CONVERGED = 1,
+    PIC_ERR_INVALID = -1,
+    PIC_ERR_HIP = -2,
+    PIC_ERR_NOMEM = -3,
+    PIC_ERR_STATE = -4
+};
+
+/* Poisson solver forms selectable in pic_params.solver. */
+enum {
+    PIC_SOLVER_PCG_FP64 = 0,   /* Jacobi-PCG in FP64 (Sec. 3.2)                */
+    PIC_SOLVER_PCG_MIXED = 1,  /* FP32 inner PCG inside FP64 refinement        */
+    PIC_SOLVER_FCG_LEARNED = 2 /* flexible PCG, U-Net warm start/precond.      */
+};
+
+/* Problem statement (Sec. 2 and 2.1; tolerance as in Sec. 4). */
+typedef struct pic_params {
+    int32_t n;            /* grid points per axis N                         */
+    int32_t ppc;          /* particles per cell (informational)             */
+    int64_t np_max;       /* largest particle count any call will pass      */
+    double length;        /* box side L of the periodic cube [0, L)^3       */
+    double charge;        /* charge q of one macro-particle                 */
+    double qm;            /* charge / mass                                  */
+    double rho_bg;        /* uniform neutralising background density        */
+    double dt;            /* time step                                      */
+    double rtol;          /* stop when ||b - A phi||_2 <= rtol * ||b||_2    */
+    int64_t max_iter;     /* iteration cap (all CG iterations of a solve)   */
+    int32_t solver;       /* PIC_SOLVER_*                                   */
+    int32_t check_every;  /* iterations launched between host checks (>=1) */
+    double inner_rtol;    /* mixed: inner relative tolerance                */
+    int64_t max_inner;    /* mixed: inner iteration cap per refinement step */
+    int64_t max_outer;    /* mixed: refinement step cap                     */
+    int32_t fcg_window;   /* learned: stall window (iterations)             */
+    int32_t reserved;
+} pic_params;
+
+/* Host-side result of one Poisson solve. */
+typedef struct pic_solve_info {
+    int64_t iterations;        /* CG iterations (inner ones for mixed)           */
+    int64_t outer_iterations;  /* mixed: refinement steps; others: 0            */
+    int64_t flex_iterations;   /* learned: iterations with the net, else 0      */
+    double rel_res;            /* true ||b - A phi|| / ||b|| at exit            */
+    double norm_b;             /* ||b||_2                                       */
+    double wx;                 /* (1/2) h^3 sum Ex^2 if the field was computed  */
+    int32_t converged;         /* 1 if rel_res <= rtol                          */
+    int32_t replacements;      /* residual replacements performed               */
+    int32_t fell_back;         /* learned: switched to Jacobi-PCG               */
+    int32_t warm_start_used;   /* learned: network warm start accepted          */
+} pic_solve_info;
+
+typedef struct pic_particle_arrays {
+    double *x, *y, *z, *vx, *vy, *vz;
+} pic_particle_arrays;
+
+/* Particles for pic_step / pic_init: `cur` holds the state; `alt` is a
+ * second set of the same size that the cell sort writes into, after which
+ * the two sets are swapped in this struct (host memory).                    */
+typedef struct pic_particles {
+    pic_particle_arrays cur;
+    pic_particle_arrays alt;
+    int64_t np;
+    uint32_t *key;        /* np cell keys                                    */
+    uint32_t *cell_start; /* N^3 + 1 entries                                 */
+} pic_particles;
+
+typedef struct pic_fields {
+    double *rho; /* zero-mean right-hand side b (N^3)                          */
+    double *phi; /* potential: in = previous step's solution, out = new one    */
+    double *ex, *ey, *ez;
+} pic_fields;
+
+typedef struct pic_step_info {
+    pic_solve_info solve;
+    double ms_push, ms_sort, ms_deposit, ms_solve, ms_field; /* event times */
+} pic_step_info;
+
+typedef struct pic_ctx pic_ctx;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Validate `params` and allocate all scratch (solver vectors, sort buffers,
+ * reduction partials) on the current HIP device.  No later call allocates. */
+int pic_create(const pic_params *params, pic_ctx **out);
+int pic_destroy(pic_ctx *ctx);
+/* Device bytes pic_create would allocate for `params`. */
+size_t pic_workspace_bytes(const pic_params *params);
+/* Message of the last error on this thread ("" if none). */
+const char *pic_last_error(void);
+/* Change the solver form (allocates the extra scratch it needs, once). */
+int pic_set_solver(pic_ctx *ctx, int32_t solver);
+/* Library ABI version. */
+int pic_abi_version(void);
+
+/* ---- the hot path ------------------------------------------------------ */
+
+/* Cell key of each particle: (iz*N + iy)*N + ix with i_d = floor(x_d*N/L)
+ * clamped to [0, N-1] (Sec. 2, CIC shape; cells are the grid's cells). */
+int pic_cell_keys(pic_ctx *ctx, int64_t np, const double *x, const double *y,
+                  const double *z, uint32_t *key, void *stream);
+
+/* Stable sort of particles by cell key (equal keys keep input order).
+ * src[0..5] = x, y, z, vx, vy, vz (read), dst[0..5] (written; must not alias
+ * src).  cell_start (N^3 + 1 entries) receives the first sorted index of each
+ * cell; perm (nullable) receives the source index of each sorted slot.     */
+int pic_sort_cells(pic_ctx *ctx, int64_t np, const uint32_t *key,
+                   const double *const src[6], double *const dst[6],
+                   uint32_t *cell_start, uint32_t *perm, void *stream);
+
+/* Scatter (Sec. 2, Fig. pic-loop): CIC charge deposit of np particles of
+ * charge q, plus the neutralising background rho_bg (Sec. 2), projected to
+ * zero mean (the periodic problem's solvability condition):
+ *   rho[v] = (q/h^3) sum_p W_p(v) + rho_bg - mean(...).
+ * With cell_start (particles sorted by pic_sort_cells) the sum is formed per
+ * vertex in a fixed order (deterministic); with cell_start == NULL particles
+ * may be in any order and FP64 atomics are used (order not deterministic).
+ * norm_b (host out, nullable) receives ||rho||_2.                          */
+int pic_deposit_cic(pic_ctx *ctx, int64_t np, const double *x, const double *y,
+                    const double *z, const uint32_t *cell_start, double *rho,
+                    double *norm_b, void *stream);
+
+/* Solve (Sec. 3.2): A phi = rho with A = -Lap_h, the periodic 7-point
+ * second-order operator, by the solver form selected in the context, starting
+ * from the phi passed in (the previous step's solution, Sec. 4.1), to
+ * ||rho - A phi|| <= rtol ||rho||.  rho must have zero mean.  If ex, ey, ez are
+ * all non-NULL, phi is gauge-fixed to zero mean and E = -grad_h phi is
+ * computed by central differences (Sec. 2, Eq. poisson).  info: host out. */
+int pic_poisson_pcg(pic_ctx *ctx, const double *rho, double *phi, double *ex,
+                    double *ey, double *ez, pic_solve_info *info, void *stream);
+
+/* Gather + push (Sec. 2, Eq. eom without external fields), leapfrog:
+ *   v <- v + (dt*qm) * E_cic(x);  x <- periodic wrap of x + dt*v;
+ * key_out (nullable) receives the new cell keys.  Arithmetic is bit-identical
+ * to the CPU oracle (no contraction; fixed summation order).                */
+int pic_gather_push(pic_ctx *ctx, int64_t np, double *x, double *y, double *z,
+                    double *vx, double *vy, double *vz, const double *ex,
+                    const double *ey, const double *ez, uint32_t *key_out,
+                    void *stream);
+
+/* Leapfrog start: v <- v - (dt/2)*qm * E_cic(x); positions unchanged. */
+int pic_half_kick(pic_ctx *ctx, int64_t np, const double *x, const double *y,
+                  const double *z, double *vx, double *vy, double *vz,
+                  const double *ex, const double *ey, const double *ez, void *stream);
+
+/* E = -grad_h phi after gauge-fixing phi to zero mean; wx (host out,
+ * nullable) = (1/2) h^3 sum Ex^2, the x-field energy of Fig. correctness_landau. */
+int pic_efield(pic_ctx *ctx, double *phi, double *ex, double *ey, double *ez,
+               double *wx, void *stream);
+
+/* Initial state: keys + sort (cur -> alt, swapped), deposit, t = 0 solve,
+ * field, half kick.  info: host out (nullable).                            */
+int pic_init(pic_ctx *ctx, pic_particles *parts, pic_fields *fields,
+             pic_step_info *info, void *stream);
+
+/* One PIC step (Fig. pic-loop): gather+push -> stable cell sort (cur -> alt,
+ * swapped) -> deposit -> solve (warm start from fields->phi) -> field.
+ * info: host out (nullable; when set, per-phase event times are recorded). */
+int pic_step(pic_ctx *ctx, pic_particles *parts, pic_fields *fields,
+             pic_step_info *info, void *stream);
+
+/* Average duration (ms) of the most recent solve's dominant kernel launches,
+ * measured with HIP events on the solve's stream when timing is enabled by
+ * pic_set_kernel_timing(ctx, 1); kernel_id: 0 = direction/stencil kernel,
+ * 1 = update kernel.  Host out.                                            */
+int pic_set_kernel_timing(pic_ctx *ctx, int32_t enable);
+int pic_kernel_time(pic_ctx *ctx, int32_t kernel_id, double *avg_ms, int64_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PIC_H */

@@ -1,0 +1,300 @@
+"""Python binding of libpic.so -- the MI355X electrostatic PIC hot path.
+
+Argument marshalling only: every step runs in the library's HIP kernels
+(include/pic.h documents each entry point).  PyTorch provides device memory
+(tensors are passed by ``data_ptr()``) and the stream.  If the library has not
+been built the import of the binding's functions fails loudly; there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+PIC_OK, PIC_NOT_CONVERGED = 0, 1
+PIC_ERR_INVALID, PIC_ERR_HIP, PIC_ERR_NOMEM, PIC_ERR_STATE = -1, -2, -3, -4
+SOLVERS = {"pcg_fp64": 0, "pcg_mixed": 1, "fcg_learned": 2}
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("pic error %d: %s" % (code, msg))
+        self.code = code
+
+
+class pic_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("ppc", ctypes.c_int32), ("np_max", ctypes.c_int64),
+                ("length", ctypes.c_double), ("charge", ctypes.c_double),
+                ("qm", ctypes.c_double), ("rho_bg", ctypes.c_double), ("dt", ctypes.c_double),
+                ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int64),
+                ("solver", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("inner_rtol", ctypes.c_double), ("max_inner", ctypes.c_int64),
+                ("max_outer", ctypes.c_int64), ("fcg_window", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class pic_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("outer_iterations", ctypes.c_int64),
+                ("flex_iterations", ctypes.c_int64), ("rel_res", ctypes.c_double),
+                ("norm_b", ctypes.c_double), ("wx", ctypes.c_double),
+                ("converged", ctypes.c_int32), ("replacements", ctypes.c_int32),
+                ("fell_back", ctypes.c_int32), ("warm_start_used", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class pic_particle_arrays(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("x", "y", "z", "vx", "vy", "vz")]
+
+
+class pic_particles(ctypes.Structure):
+    _fields_ = [("cur", pic_particle_arrays), ("alt", pic_particle_arrays),
+                ("np", ctypes.c_int64), ("key", ctypes.c_void_p),
+                ("cell_start", ctypes.c_void_p)]
+
+
+class pic_fields(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("rho", "phi", "ex", "ey", "ez")]
+
+
+class pic_step_info(ctypes.Structure):
+    _fields_ = [("solve", pic_solve_info), ("ms_push", ctypes.c_double),
+                ("ms_sort", ctypes.c_double), ("ms_deposit", ctypes.c_double),
+                ("ms_solve", ctypes.c_double), ("ms_field", ctypes.c_double)]
+
+    def as_dict(self):
+        d = self.solve.as_dict()
+        for f in ("ms_push", "ms_sort", "ms_deposit", "ms_solve", "ms_field"):
+            d[f] = getattr(self, f)
+        return d
+
+
+_lib = None
+
+# every entry point declared in include/pic.h
+EXPORTS = ["pic_create", "pic_destroy", "pic_workspace_bytes", "pic_last_error",
+           "pic_set_solver", "pic_abi_version", "pic_cell_keys", "pic_sort_cells",
+           "pic_deposit_cic", "pic_poisson_pcg", "pic_gather_push", "pic_half_kick",
+           "pic_efield", "pic_init", "pic_step", "pic_set_kernel_timing", "pic_kernel_time"]
+
+
+def lib():
+    """Load libpic.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime the library must share)
+
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libpic.so is not built (run paper_2605_05469_amd/build.py); "
+                          "there is no fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.pic_create.argtypes = [ctypes.POINTER(pic_params), ctypes.POINTER(vp)]
+    L.pic_destroy.argtypes = [vp]
+    L.pic_workspace_bytes.argtypes = [ctypes.POINTER(pic_params)]
+    L.pic_workspace_bytes.restype = ctypes.c_size_t
+    L.pic_last_error.restype = ctypes.c_char_p
+    L.pic_set_solver.argtypes = [vp, i32]
+    L.pic_cell_keys.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    L.pic_sort_cells.argtypes = [vp, i64, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]
+    L.pic_deposit_cic.argtypes = [vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]
+    L.pic_poisson_pcg.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(pic_solve_info), vp]
+    L.pic_gather_push.argtypes = [vp, i64] + [vp] * 10 + [vp]
+    L.pic_half_kick.argtypes = [vp, i64] + [vp] * 9 + [vp]
+    L.pic_efield.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]
+    L.pic_init.argtypes = [vp, ctypes.POINTER(pic_particles), ctypes.POINTER(pic_fields),
+                           ctypes.POINTER(pic_step_info), vp]
+    L.pic_step.argtypes = L.pic_init.argtypes
+    L.pic_set_kernel_timing.argtypes = [vp, i32]
+    L.pic_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    _lib = L
+    return L
+
+
+def _check(rc, allow_not_converged=True):
+    if rc < 0 or (rc == PIC_NOT_CONVERGED and not allow_not_converged):
+        raise PicError(rc, lib().pic_last_error().decode())
+    return rc
+
+
+def _ptr(t, dtype=None, name="array"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def landau_params(N, ppc, k=0.5, dt=0.05, qm=-1.0, rtol=1e-10, max_iter=20000,
+                  solver="pcg_fp64", np_max=None, check_every=16, inner_rtol=1e-3,
+                  max_inner=20000, max_outer=50, fcg_window=5):
+    """Parameters of the Landau-damping box (Sec. 2.1): L = 2 pi / k, unit
+    mean density, q = -L^3/Np, background +1."""
+    L = 2.0 * math.pi / k
+    npart = ppc * N ** 3
+    q = -(L ** 3) / npart
+    p = pic_params()
+    p.n, p.ppc = N, ppc
+    p.np_max = npart if np_max is None else np_max
+    p.length, p.charge, p.qm = L, q, qm
+    p.rho_bg = -(q * npart) / L ** 3
+    p.dt, p.rtol, p.max_iter = dt, rtol, max_iter
+    p.solver = SOLVERS[solver] if isinstance(solver, str) else int(solver)
+    p.check_every = check_every
+    p.inner_rtol, p.max_inner, p.max_outer = inner_rtol, max_inner, max_outer
+    p.fcg_window = fcg_window
+    return p
+
+
+class Context:
+    """Owns a pic_ctx (scratch on the current device)."""
+
+    def __init__(self, params: pic_params):
+        self.params = params
+        self._h = ctypes.c_void_p()
+        _check(lib().pic_create(ctypes.byref(params), ctypes.byref(self._h)))
+        self.N = params.n
+
+    def close(self):
+        if self._h:
+            lib().pic_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ pieces --
+    def set_solver(self, solver):
+        s = SOLVERS[solver] if isinstance(solver, str) else int(solver)
+        _check(lib().pic_set_solver(self._h, s))
+
+    def cell_keys(self, x, y, z, key, stream=None):
+        import torch
+        _check(lib().pic_cell_keys(self._h, x.numel(), _ptr(x, torch.float64), _ptr(y, torch.float64),
+                                   _ptr(z, torch.float64), _ptr(key, torch.int32 if key.dtype == torch.int32 else torch.uint32),
+                                   _stream(stream)))
+
+    def sort_cells(self, key, src, dst, cell_start, perm=None, stream=None):
+        sp = (ctypes.c_void_p * 6)(*[_ptr(a) for a in src])
+        dp = (ctypes.c_void_p * 6)(*[_ptr(a) for a in dst])
+        _check(lib().pic_sort_cells(self._h, src[0].numel(), _ptr(key), sp, dp, _ptr(cell_start),
+                                    _ptr(perm), _stream(stream)))
+
+    def deposit(self, x, y, z, cell_start, rho, stream=None, want_norm=False):
+        nb = ctypes.c_double(0.0)
+        _check(lib().pic_deposit_cic(self._h, 0 if x is None else x.numel(), _ptr(x), _ptr(y),
+                                     _ptr(z), _ptr(cell_start), _ptr(rho),
+                                     ctypes.byref(nb) if want_norm else None, _stream(stream)))
+        return nb.value if want_norm else None
+
+    def poisson(self, rho, phi, ex=None, ey=None, ez=None, stream=None):
+        info = pic_solve_info()
+        rc = _check(lib().pic_poisson_pcg(self._h, _ptr(rho), _ptr(phi), _ptr(ex), _ptr(ey),
+                                          _ptr(ez), ctypes.byref(info), _stream(stream)))
+        d = info.as_dict()
+        d["status"] = rc
+        return d
+
+    def efield(self, phi, ex, ey, ez, stream=None):
+        wx = ctypes.c_double(0.0)
+        _check(lib().pic_efield(self._h, _ptr(phi), _ptr(ex), _ptr(ey), _ptr(ez),
+                                ctypes.byref(wx), _stream(stream)))
+        return wx.value
+
+    def gather_push(self, x, y, z, vx, vy, vz, ex, ey, ez, key=None, stream=None):
+        _check(lib().pic_gather_push(self._h, x.numel(), *[_ptr(a) for a in (x, y, z, vx, vy, vz,
+                                                                              ex, ey, ez)],
+                                     _ptr(key), _stream(stream)))
+
+    def half_kick(self, x, y, z, vx, vy, vz, ex, ey, ez, stream=None):
+        _check(lib().pic_half_kick(self._h, x.numel(), *[_ptr(a) for a in (x, y, z, vx, vy, vz,
+                                                                            ex, ey, ez)],
+                                   _stream(stream)))
+
+    def set_kernel_timing(self, on=True):
+        _check(lib().pic_set_kernel_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self, kid):
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().pic_kernel_time(self._h, kid, ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
+
+
+class Simulation:
+    """Device-resident PIC state driven through pic_init / pic_step."""
+
+    def __init__(self, ctx: Context, x, y, z, vx, vy, vz):
+        import torch
+        self.ctx = ctx
+        N = ctx.N
+        dev = x.device
+        n = x.numel()
+        self._cur = [x, y, z, vx, vy, vz]
+        self._alt = [torch.empty_like(a) for a in self._cur]
+        self.key = torch.empty(n, dtype=torch.int32, device=dev)
+        self.cell_start = torch.empty(N ** 3 + 1, dtype=torch.int32, device=dev)
+        self.rho = torch.zeros(N ** 3, dtype=torch.float64, device=dev)
+        self.phi = torch.zeros(N ** 3, dtype=torch.float64, device=dev)
+        self.ex = torch.zeros(N ** 3, dtype=torch.float64, device=dev)
+        self.ey = torch.zeros_like(self.ex)
+        self.ez = torch.zeros_like(self.ex)
+        self._P = pic_particles()
+        self._P.np = n
+        self._set(self._P.cur, self._cur)
+        self._set(self._P.alt, self._alt)
+        self._P.key = self.key.data_ptr()
+        self._P.cell_start = self.cell_start.data_ptr()
+        self._F = pic_fields(self.rho.data_ptr(), self.phi.data_ptr(), self.ex.data_ptr(),
+                             self.ey.data_ptr(), self.ez.data_ptr())
+
+    @staticmethod
+    def _set(arr, ts):
+        for nm, t in zip(("x", "y", "z", "vx", "vy", "vz"), ts):
+            setattr(arr, nm, t.data_ptr())
+
+    def _sync_views(self):
+        # the library swaps cur/alt after the sort; follow it
+        if self._P.cur.x != self._cur[0].data_ptr():
+            self._cur, self._alt = self._alt, self._cur
+
+    @property
+    def particles(self):
+        return self._cur
+
+    def init(self, stream=None):
+        info = pic_step_info()
+        rc = _check(lib().pic_init(self.ctx._h, ctypes.byref(self._P), ctypes.byref(self._F),
+                                   ctypes.byref(info), _stream(stream)))
+        self._sync_views()
+        d = info.as_dict()
+        d["status"] = rc
+        return d
+
+    def step(self, stream=None, timed=True):
+        info = pic_step_info()
+        rc = _check(lib().pic_step(self.ctx._h, ctypes.byref(self._P), ctypes.byref(self._F),
+                                   ctypes.byref(info) if timed else None, _stream(stream)))
+        self._sync_views()
+        d = info.as_dict()
+        d["status"] = rc
+        return d

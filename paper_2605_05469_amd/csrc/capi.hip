@@ -1,0 +1,710 @@
+// capi.hip -- the C ABI declared in include/pic.h: context, validation, and
+// the host drivers of the solvers and of the PIC step.
+//
+// Host drivers only enqueue kernels; every arithmetic step runs on the GPU.
+// The CG scalars live in device memory (DevState); the host reads them back
+// once every `check_every` iterations to decide whether to launch more.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "learned.hpp"
+#include "particles.hpp"
+#include "solver_state.hpp"
+
+using namespace pic;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(PIC_ERR_HIP, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                           \
+    } while (0)
+
+#define RETCHK(expr)              \
+    do {                          \
+        int rc_ = (expr);         \
+        if (rc_ < 0) return rc_;  \
+    } while (0)
+
+struct pic_ctx {
+    pic_params p;
+    int device = 0;
+    SweepGeo geo;
+    int64_t n3 = 0;
+    double L = 0, inv_h = 0, inv_h2 = 0, minv = 0, h = 0, h3 = 0, ehalf = 0, qh3 = 0;
+    double coef_push = 0, coef_kick = 0;
+    float inv_h2f = 0, minvf = 0;
+    // device memory
+    DevState* st = nullptr;
+    DevState* st_host = nullptr;  // pinned mirror
+    double* partials = nullptr;
+    int npartials = 0;
+    double* r = nullptr;
+    double* p2[2] = {nullptr, nullptr};
+    float* r32 = nullptr;
+    float* d32 = nullptr;
+    float* p32[2] = {nullptr, nullptr};
+    void* sort_pool = nullptr;
+    SortScratch sort{};
+    Learned* learned = nullptr;
+    std::vector<void*> allocs;
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    double t_sum[2] = {0, 0};
+    int64_t t_cnt[2] = {0, 0};
+};
+
+// ------------------------------------------------------------------ helpers --
+
+static bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+static int validate_params(const pic_params* p) {
+    if (!p) return fail(PIC_ERR_INVALID, "params is NULL");
+    if (p->n < 32 || p->n > 1024 || (p->n % 32) != 0)
+        return fail(PIC_ERR_INVALID, "n = %d: must be a multiple of 32 in [32, 1024]", p->n);
+    if (!(p->length > 0.0) || !std::isfinite(p->length))
+        return fail(PIC_ERR_INVALID, "length must be positive and finite");
+    if (p->np_max < 0 || p->np_max >= ((int64_t)1 << 32))
+        return fail(PIC_ERR_INVALID, "np_max must be in [0, 2^32)");
+    if (!(p->rtol > 0.0) || !std::isfinite(p->rtol)) return fail(PIC_ERR_INVALID, "rtol must be > 0");
+    if (p->max_iter < 0) return fail(PIC_ERR_INVALID, "max_iter must be >= 0");
+    if (p->solver < PIC_SOLVER_PCG_FP64 || p->solver > PIC_SOLVER_FCG_LEARNED)
+        return fail(PIC_ERR_INVALID, "unknown solver %d", p->solver);
+    if (!std::isfinite(p->charge) || !std::isfinite(p->qm) || !std::isfinite(p->dt) ||
+        !std::isfinite(p->rho_bg))
+        return fail(PIC_ERR_INVALID, "charge, qm, dt and rho_bg must be finite");
+    return PIC_OK;
+}
+
+static size_t vec_bytes(int64_t n3, size_t elem) { return ((size_t)n3 * elem + 255) & ~(size_t)255; }
+
+static size_t base_bytes(const pic_params* p) {
+    const int64_t n3 = (int64_t)p->n * p->n * p->n;
+    SweepGeo g = make_geo(p->n);
+    int np = (int)g.nb;
+    if (np < 2 * deposit_partials()) np = 2 * deposit_partials();
+    size_t b = 0;
+    b += 4096;                               // DevState
+    b += (size_t)4 * np * sizeof(double);    // partials
+    b += 3 * vec_bytes(n3, 8);               // r, p[2]
+    return b;
+}
+
+static size_t mixed_bytes(const pic_params* p) {
+    const int64_t n3 = (int64_t)p->n * p->n * p->n;
+    return 4 * vec_bytes(n3, 4);
+}
+
+static int dev_alloc(pic_ctx* c, void** out, size_t bytes) {
+    void* ptr = nullptr;
+    hipError_t e = hipMalloc(&ptr, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PIC_ERR_NOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    }
+    c->allocs.push_back(ptr);
+    *out = ptr;
+    return PIC_OK;
+}
+
+static int ensure_mixed(pic_ctx* c) {
+    if (c->r32) return PIC_OK;
+    void* m = nullptr;
+    RETCHK(dev_alloc(c, &m, mixed_bytes(&c->p)));
+    char* q = (char*)m;
+    const size_t vb = vec_bytes(c->n3, 4);
+    c->r32 = (float*)q;
+    c->d32 = (float*)(q + vb);
+    c->p32[0] = (float*)(q + 2 * vb);
+    c->p32[1] = (float*)(q + 3 * vb);
+    return PIC_OK;
+}
+
+static int ensure_learned(pic_ctx* c) {
+    if (c->learned) return PIC_OK;
+    int rc = learned_create(&c->learned, c->p.n, c->n3);
+    if (rc != PIC_OK) return fail(rc, "learned solver scratch: %s", learned_last_error());
+    return PIC_OK;
+}
+
+static int read_state(pic_ctx* c, hipStream_t s) {
+    HIPCHK(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------------- kernels --
+
+__global__ void state_init_kernel(DevState* st, int32_t outer_state) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->outer_state = outer_state;
+        st->cg.state = CG_RUNNING;
+        st->cg.iter = 0;
+        st->cg.replacements = 0;
+    }
+}
+
+// --------------------------------------------------------------- timing ----
+
+static void timing_reset(pic_ctx* c) {
+    c->t_sum[0] = c->t_sum[1] = 0;
+    c->t_cnt[0] = c->t_cnt[1] = 0;
+}
+
+static int timing_events(pic_ctx* c, size_t need) {
+    while (c->ev.size() < need) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        c->ev.push_back(e);
+    }
+    return PIC_OK;
+}
+
+// Accumulate the first `valid` (iteration) pairs of a batch.
+static int timing_collect(pic_ctx* c, int launched, int64_t valid) {
+    for (int k = 0; k < launched && k < valid; ++k) {
+        for (int j = 0; j < 2; ++j) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, c->ev[4 * k + 2 * j], c->ev[4 * k + 2 * j + 1]));
+            c->t_sum[j] += ms;
+            c->t_cnt[j] += 1;
+        }
+    }
+    return PIC_OK;
+}
+
+// ------------------------------------------------------------- FP64 PCG ----
+
+// Runs batches of (direction, update) sweeps until the device state leaves
+// RUNNING; handles candidate verification (residual replacement).
+static int pcg64_iterate(pic_ctx* c, const double* b, double* x, hipStream_t s) {
+    const SweepGeo& g = c->geo;
+    const int K = c->p.check_every > 0 ? c->p.check_every : 16;
+    int cur = 0;
+    if (c->timing) RETCHK(timing_events(c, (size_t)4 * K));
+    for (;;) {
+        CgScalars& cg = c->st_host->cg;
+        if (cg.state == CG_RUNNING) {
+            const int64_t it0 = cg.iter;
+            for (int k = 0; k < K; ++k) {
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
+                HIPCHK(launch_dir64(g, c->r, c->p2[cur], c->p2[cur ^ 1], c->minv, c->inv_h2, c->st,
+                                    c->partials, s));
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 2], s));
+                HIPCHK(launch_upd64(g, c->p2[cur ^ 1], x, c->r, c->minv, c->inv_h2, c->st,
+                                    c->partials, s));
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 3], s));
+                cur ^= 1;
+            }
+            RETCHK(read_state(c, s));
+            if (c->timing) RETCHK(timing_collect(c, K, c->st_host->cg.iter - it0));
+            if (c->st_host->cg.state == CG_RUNNING && c->st_host->cg.iter == it0)
+                return fail(PIC_ERR_STATE, "solver made no progress (iteration %lld)",
+                            (long long)it0);
+            continue;
+        }
+        if (cg.state == CG_CANDIDATE) {
+            HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 0, c->p.rtol, c->p.max_iter,
+                                     c->st, c->partials, s));
+            RETCHK(read_state(c, s));
+            continue;
+        }
+        return PIC_OK;  // CONVERGED, MAXIT, BREAKDOWN, ZERO_RHS
+    }
+}
+
+static int solve_fp64(pic_ctx* c, const double* b, double* x, pic_solve_info* out, hipStream_t s) {
+    const SweepGeo& g = c->geo;
+    HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 1, c->p.rtol, c->p.max_iter, c->st,
+                             c->partials, s));
+    RETCHK(read_state(c, s));
+    if (c->st_host->cg.state == CG_ZERO_RHS) {
+        HIPCHK(launch_fill(c->n3, x, 0.0, s));
+    } else {
+        RETCHK(pcg64_iterate(c, b, x, s));
+    }
+    const CgScalars& cg = c->st_host->cg;
+    out->iterations = cg.iter;
+    out->replacements = cg.replacements;
+    out->norm_b = cg.nb;
+    if (cg.state == CG_CONVERGED || cg.state == CG_ZERO_RHS) {
+        out->converged = 1;
+        out->rel_res = cg.nb > 0 ? cg.true_rn / cg.nb : 0.0;
+    } else {
+        // report the true residual of the last iterate (2 = report only)
+        HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 2, c->p.rtol, c->p.max_iter,
+                                 c->st, c->partials, s));
+        RETCHK(read_state(c, s));
+        out->converged = 0;
+        out->rel_res = c->st_host->cg.true_rn / c->st_host->cg.nb;
+    }
+    return PIC_OK;
+}
+
+// ---------------------------------------------------------- mixed form -----
+
+static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* out, hipStream_t s) {
+    RETCHK(ensure_mixed(c));
+    const SweepGeo& g = c->geo;
+    const int K = c->p.check_every > 0 ? c->p.check_every : 16;
+    HIPCHK(launch_sum(c->n3, b, c->st, c->partials, 1, s));
+    hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, c->st, (int32_t)CG_RUNNING);
+    HIPCHK(hipGetLastError());
+    RETCHK(read_state(c, s));
+    const double nb = std::sqrt(c->st_host->bb);
+    out->norm_b = nb;
+    if (nb == 0.0) {
+        HIPCHK(launch_fill(c->n3, x, 0.0, s));
+        out->converged = 1;
+        out->rel_res = 0.0;
+        return PIC_OK;
+    }
+    const double tol = c->p.rtol * nb;
+    int64_t outer = 0, inner_total = 0;
+    int cur = 0;
+    if (c->timing) RETCHK(timing_events(c, (size_t)4 * K));
+    for (;;) {
+        HIPCHK(launch_outer_resid(g, b, x, c->d32, c->r, outer > 0 ? 1 : 0, c->inv_h2, c->st,
+                                  c->partials, tol, s));
+        RETCHK(read_state(c, s));
+        const double nr = c->st_host->out_nr;
+        if (!std::isfinite(nr)) break;
+        if (nr <= tol) {
+            out->converged = 1;
+            break;
+        }
+        if (outer >= c->p.max_outer) break;
+        ++outer;
+        HIPCHK(launch_convert32(c->n3, c->r, c->r32, c->d32, c->minvf, c->p.inner_rtol,
+                                c->p.max_inner, c->st, c->partials, s));
+        RETCHK(read_state(c, s));
+        while (c->st_host->cg.state == CG_RUNNING) {
+            const int64_t it0 = c->st_host->cg.iter;
+            for (int k = 0; k < K; ++k) {
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
+                HIPCHK(launch_dir32(g, c->r32, c->p32[cur], c->p32[cur ^ 1], c->minvf, c->inv_h2f,
+                                    c->st, c->partials, s));
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 2], s));
+                HIPCHK(launch_upd32(g, c->p32[cur ^ 1], c->d32, c->r32, c->minvf, c->inv_h2f, c->st,
+                                    c->partials, s));
+                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 3], s));
+                cur ^= 1;
+            }
+            RETCHK(read_state(c, s));
+            if (c->timing) RETCHK(timing_collect(c, K, c->st_host->cg.iter - it0));
+            if (c->st_host->cg.state == CG_RUNNING && c->st_host->cg.iter == it0)
+                return fail(PIC_ERR_STATE, "inner solver made no progress");
+        }
+        inner_total += c->st_host->cg.iter;
+        if (c->st_host->cg.state == CG_BREAKDOWN) {
+            // an FP32 breakdown still leaves a usable correction; the next outer
+            // residual decides, and the step cap bounds the loop
+        }
+    }
+    out->iterations = inner_total;
+    out->outer_iterations = outer;
+    out->rel_res = c->st_host->out_nr / nb;
+    return PIC_OK;
+}
+
+// ------------------------------------------------------------------ field --
+
+static int field(pic_ctx* c, double* phi, double* ex, double* ey, double* ez, hipStream_t s) {
+    HIPCHK(launch_sum(c->n3, phi, c->st, c->partials, 0, s));
+    HIPCHK(launch_field(c->geo, phi, ex, ey, ez, c->ehalf, c->h3, c->st, c->partials, s));
+    return PIC_OK;
+}
+
+// ====================================================================== ABI ==
+
+extern "C" {
+
+int pic_abi_version(void) { return 1; }
+
+const char* pic_last_error(void) { return g_err.c_str(); }
+
+size_t pic_workspace_bytes(const pic_params* p) {
+    if (validate_params(p) != PIC_OK) return 0;
+    size_t b = base_bytes(p);
+    if (p->np_max > 0) b += sort_scratch_bytes(p->np_max);
+    if (p->solver == PIC_SOLVER_PCG_MIXED) b += mixed_bytes(p);
+    if (p->solver == PIC_SOLVER_FCG_LEARNED) b += learned_bytes(p->n);
+    return b;
+}
+
+int pic_create(const pic_params* params, pic_ctx** out) {
+    g_err.clear();
+    if (!out) return fail(PIC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    RETCHK(validate_params(params));
+    pic_ctx* c = new (std::nothrow) pic_ctx();
+    if (!c) return fail(PIC_ERR_NOMEM, "host allocation failed");
+    c->p = *params;
+    if (c->p.check_every <= 0) c->p.check_every = 16;
+    if (c->p.max_outer <= 0) c->p.max_outer = 50;
+    if (c->p.max_inner <= 0) c->p.max_inner = 20000;
+    if (!(c->p.inner_rtol > 0.0)) c->p.inner_rtol = 1e-3;
+    if (c->p.fcg_window <= 0) c->p.fcg_window = 5;
+    const int n = c->p.n;
+    c->n3 = (int64_t)n * n * n;
+    c->geo = make_geo(n);
+    c->L = c->p.length;
+    // the same formulas, in the same order, as the CPU definition
+    c->inv_h = (double)n / c->L;
+    c->inv_h2 = c->inv_h * c->inv_h;
+    c->minv = 1.0 / (6.0 * (c->inv_h * c->inv_h));
+    c->h = c->L / (double)n;
+    c->h3 = c->h * c->h * c->h;
+    c->ehalf = 0.5 * c->inv_h;
+    c->qh3 = c->p.charge * (c->inv_h * c->inv_h * c->inv_h);
+    c->coef_push = c->p.dt * c->p.qm;
+    c->coef_kick = (-0.5 * c->p.dt) * c->p.qm;
+    c->inv_h2f = (float)(c->inv_h * c->inv_h);
+    c->minvf = (float)(1.0 / (6.0 * (c->inv_h * c->inv_h)));
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(PIC_ERR_HIP, "no HIP device");
+    }
+    int rc = PIC_OK;
+    do {
+        void* m = nullptr;
+        if ((rc = dev_alloc(c, &m, base_bytes(&c->p))) != PIC_OK) break;
+        char* q = (char*)m;
+        c->st = (DevState*)q;
+        q += 4096;
+        c->npartials = (int)c->geo.nb < 2 * deposit_partials() ? 2 * deposit_partials() : (int)c->geo.nb;
+        c->partials = (double*)q;
+        q += (size_t)4 * c->npartials * sizeof(double);
+        q = (char*)(((uintptr_t)q + 255) & ~(uintptr_t)255);
+        const size_t vb = vec_bytes(c->n3, 8);
+        c->r = (double*)q;
+        c->p2[0] = (double*)(q + vb);
+        c->p2[1] = (double*)(q + 2 * vb);
+        if (hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
+            rc = fail(PIC_ERR_NOMEM, "pinned host allocation failed");
+            break;
+        }
+        std::memset(c->st_host, 0, sizeof(DevState));
+        if (hipMemcpy(c->st, c->st_host, sizeof(DevState), hipMemcpyHostToDevice) != hipSuccess) {
+            rc = fail(PIC_ERR_HIP, "state upload failed");
+            break;
+        }
+        if (c->p.np_max > 0) {
+            if ((rc = dev_alloc(c, &c->sort_pool, sort_scratch_bytes(c->p.np_max))) != PIC_OK) break;
+            sort_scratch_carve(c->sort_pool, c->p.np_max, &c->sort);
+        }
+        if (c->p.solver == PIC_SOLVER_PCG_MIXED && (rc = ensure_mixed(c)) != PIC_OK) break;
+        if (c->p.solver == PIC_SOLVER_FCG_LEARNED && (rc = ensure_learned(c)) != PIC_OK) break;
+    } while (0);
+    if (rc != PIC_OK) {
+        std::string keep = g_err;
+        pic_destroy(c);
+        g_err = keep;
+        return rc;
+    }
+    *out = c;
+    return PIC_OK;
+}
+
+int pic_destroy(pic_ctx* c) {
+    if (!c) return PIC_OK;
+    (void)hipDeviceSynchronize();
+    for (void* a : c->allocs) (void)hipFree(a);
+    if (c->st_host) (void)hipHostFree(c->st_host);
+    for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->learned) learned_destroy(c->learned);
+    delete c;
+    return PIC_OK;
+}
+
+int pic_set_solver(pic_ctx* c, int32_t solver) {
+    if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
+    if (solver < PIC_SOLVER_PCG_FP64 || solver > PIC_SOLVER_FCG_LEARNED)
+        return fail(PIC_ERR_INVALID, "unknown solver %d", solver);
+    if (solver == PIC_SOLVER_PCG_MIXED) RETCHK(ensure_mixed(c));
+    if (solver == PIC_SOLVER_FCG_LEARNED) RETCHK(ensure_learned(c));
+    c->p.solver = solver;
+    return PIC_OK;
+}
+
+int pic_set_kernel_timing(pic_ctx* c, int32_t enable) {
+    if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
+    c->timing = enable != 0;
+    timing_reset(c);
+    return PIC_OK;
+}
+
+int pic_kernel_time(pic_ctx* c, int32_t id, double* avg_ms, int64_t* count) {
+    if (!c || !avg_ms || !count || id < 0 || id > 1)
+        return fail(PIC_ERR_INVALID, "bad arguments to pic_kernel_time");
+    *count = c->t_cnt[id];
+    *avg_ms = c->t_cnt[id] ? c->t_sum[id] / (double)c->t_cnt[id] : 0.0;
+    return PIC_OK;
+}
+
+#define NEED(ptr, what)                                                   \
+    do {                                                                  \
+        if (!(ptr)) return fail(PIC_ERR_INVALID, "%s is NULL", what);     \
+        if (!aligned8(ptr)) return fail(PIC_ERR_INVALID, "%s is not 8-byte aligned", what); \
+    } while (0)
+
+static int check_np(pic_ctx* c, int64_t np) {
+    if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
+    if (np < 0 || np > c->p.np_max)
+        return fail(PIC_ERR_INVALID, "np = %lld outside [0, np_max = %lld]", (long long)np,
+                    (long long)c->p.np_max);
+    return PIC_OK;
+}
+
+int pic_cell_keys(pic_ctx* c, int64_t np, const double* x, const double* y, const double* z,
+                  uint32_t* key, void* stream) {
+    RETCHK(check_np(c, np));
+    if (np == 0) return PIC_OK;
+    NEED(x, "x"); NEED(y, "y"); NEED(z, "z");
+    if (!key) return fail(PIC_ERR_INVALID, "key is NULL");
+    HIPCHK(launch_keys(np, x, y, z, key, c->p.n, c->inv_h, (hipStream_t)stream));
+    return PIC_OK;
+}
+
+int pic_sort_cells(pic_ctx* c, int64_t np, const uint32_t* key, const double* const src[6],
+                   double* const dst[6], uint32_t* cell_start, uint32_t* perm, void* stream) {
+    RETCHK(check_np(c, np));
+    if (!src || !dst) return fail(PIC_ERR_INVALID, "src/dst is NULL");
+    if (!cell_start) return fail(PIC_ERR_INVALID, "cell_start is NULL");
+    if (np > 0) {
+        if (!key) return fail(PIC_ERR_INVALID, "key is NULL");
+        for (int i = 0; i < 6; ++i) {
+            NEED(src[i], "src[i]");
+            NEED(dst[i], "dst[i]");
+            for (int j = 0; j < 6; ++j)
+                if ((const void*)src[i] == (const void*)dst[j])
+                    return fail(PIC_ERR_INVALID, "dst must not alias src");
+        }
+    }
+    HIPCHK(launch_sort_cells(np, c->n3, key, src, dst, cell_start, perm, &c->sort,
+                             (hipStream_t)stream));
+    return PIC_OK;
+}
+
+int pic_deposit_cic(pic_ctx* c, int64_t np, const double* x, const double* y, const double* z,
+                    const uint32_t* cell_start, double* rho, double* norm_b, void* stream) {
+    RETCHK(check_np(c, np));
+    NEED(rho, "rho");
+    if (np > 0) { NEED(x, "x"); NEED(y, "y"); NEED(z, "z"); }
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(launch_deposit(np, x, y, z, np > 0 ? cell_start : nullptr, rho, c->p.n, c->inv_h,
+                          c->qh3, c->p.rho_bg, c->st, c->partials, s));
+    if (norm_b) {
+        RETCHK(read_state(c, s));
+        *norm_b = std::sqrt(c->st_host->bb);
+    }
+    return PIC_OK;
+}
+
+int pic_efield(pic_ctx* c, double* phi, double* ex, double* ey, double* ez, double* wx,
+               void* stream) {
+    if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
+    NEED(phi, "phi"); NEED(ex, "ex"); NEED(ey, "ey"); NEED(ez, "ez");
+    hipStream_t s = (hipStream_t)stream;
+    RETCHK(field(c, phi, ex, ey, ez, s));
+    if (wx) {
+        RETCHK(read_state(c, s));
+        *wx = c->st_host->wx;
+    }
+    return PIC_OK;
+}
+
+int pic_poisson_pcg(pic_ctx* c, const double* rho, double* phi, double* ex, double* ey,
+                    double* ez, pic_solve_info* info, void* stream) {
+    if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
+    NEED(rho, "rho");
+    NEED(phi, "phi");
+    const bool want_e = ex && ey && ez;
+    if (want_e) { NEED(ex, "ex"); NEED(ey, "ey"); NEED(ez, "ez"); }
+    hipStream_t s = (hipStream_t)stream;
+    pic_solve_info si;
+    std::memset(&si, 0, sizeof si);
+    if (c->timing) timing_reset(c);
+    switch (c->p.solver) {
+        case PIC_SOLVER_PCG_FP64: RETCHK(solve_fp64(c, rho, phi, &si, s)); break;
+        case PIC_SOLVER_PCG_MIXED: RETCHK(solve_mixed(c, rho, phi, &si, s)); break;
+        default: {
+            LearnedEnv env{c->geo, c->n3, c->inv_h2, c->minv, c->h, c->p.rtol, c->p.max_iter,
+                           c->p.check_every, c->p.fcg_window, c->st, c->st_host, c->partials,
+                           c->r, c->p2[0], c->p2[1]};
+            int rc = learned_solve(c->learned, &env, rho, phi, &si, s);
+            if (rc != PIC_OK) return fail(rc, "learned solve: %s", learned_last_error());
+        }
+    }
+    if (want_e) {
+        RETCHK(field(c, phi, ex, ey, ez, s));
+        RETCHK(read_state(c, s));
+        si.wx = c->st_host->wx;
+    }
+    if (info) *info = si;
+    return si.converged ? PIC_OK : PIC_NOT_CONVERGED;
+}
+
+int pic_gather_push(pic_ctx* c, int64_t np, double* x, double* y, double* z, double* vx,
+                    double* vy, double* vz, const double* ex, const double* ey, const double* ez,
+                    uint32_t* key_out, void* stream) {
+    RETCHK(check_np(c, np));
+    if (np == 0) return PIC_OK;
+    NEED(x, "x"); NEED(y, "y"); NEED(z, "z"); NEED(vx, "vx"); NEED(vy, "vy"); NEED(vz, "vz");
+    NEED(ex, "ex"); NEED(ey, "ey"); NEED(ez, "ez");
+    HIPCHK(launch_gather_push(np, x, y, z, vx, vy, vz, ex, ey, ez, key_out, c->p.n, c->inv_h, c->L,
+                              c->p.dt, c->coef_push, (hipStream_t)stream));
+    return PIC_OK;
+}
+
+int pic_half_kick(pic_ctx* c, int64_t np, const double* x, const double* y, const double* z,
+                  double* vx, double* vy, double* vz, const double* ex, const double* ey,
+                  const double* ez, void* stream) {
+    RETCHK(check_np(c, np));
+    if (np == 0) return PIC_OK;
+    NEED(x, "x"); NEED(y, "y"); NEED(z, "z"); NEED(vx, "vx"); NEED(vy, "vy"); NEED(vz, "vz");
+    NEED(ex, "ex"); NEED(ey, "ey"); NEED(ez, "ez");
+    HIPCHK(launch_half_kick(np, x, y, z, vx, vy, vz, ex, ey, ez, c->p.n, c->inv_h, c->coef_kick,
+                            (hipStream_t)stream));
+    return PIC_OK;
+}
+
+static int check_parts(pic_ctx* c, pic_particles* P, pic_fields* F) {
+    if (!P || !F) return fail(PIC_ERR_INVALID, "particles/fields is NULL");
+    RETCHK(check_np(c, P->np));
+    NEED(F->rho, "rho"); NEED(F->phi, "phi"); NEED(F->ex, "ex"); NEED(F->ey, "ey"); NEED(F->ez, "ez");
+    if (!P->cell_start) return fail(PIC_ERR_INVALID, "cell_start is NULL");
+    if (P->np > 0) {
+        if (!P->key) return fail(PIC_ERR_INVALID, "key is NULL");
+        double* a[12] = {P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy, P->cur.vz,
+                         P->alt.x, P->alt.y, P->alt.z, P->alt.vx, P->alt.vy, P->alt.vz};
+        for (int i = 0; i < 12; ++i) NEED(a[i], "particle array");
+    }
+    return PIC_OK;
+}
+
+static int sort_swap(pic_ctx* c, pic_particles* P, hipStream_t s) {
+    const double* src[6] = {P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy, P->cur.vz};
+    double* dst[6] = {P->alt.x, P->alt.y, P->alt.z, P->alt.vx, P->alt.vy, P->alt.vz};
+    HIPCHK(launch_sort_cells(P->np, c->n3, P->key, src, dst, P->cell_start, nullptr, &c->sort, s));
+    pic_particle_arrays t = P->cur;
+    P->cur = P->alt;
+    P->alt = t;
+    return PIC_OK;
+}
+
+struct PhaseTimer {
+    bool on = false;
+    hipEvent_t e[6];
+    int init(bool enable) {
+        on = enable;
+        if (!on) return PIC_OK;
+        for (auto& x : e) HIPCHK(hipEventCreate(&x));
+        return PIC_OK;
+    }
+    int mark(int i, hipStream_t s) {
+        if (on) HIPCHK(hipEventRecord(e[i], s));
+        return PIC_OK;
+    }
+    double ms(int a, int b) {
+        float t = 0.f;
+        if (on) (void)hipEventElapsedTime(&t, e[a], e[b]);
+        return t;
+    }
+    ~PhaseTimer() {
+        if (on)
+            for (auto& x : e) (void)hipEventDestroy(x);
+    }
+};
+
+int pic_init(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, void* stream) {
+    RETCHK(check_parts(c, P, F));
+    hipStream_t s = (hipStream_t)stream;
+    if (P->np > 0) HIPCHK(launch_keys(P->np, P->cur.x, P->cur.y, P->cur.z, P->key, c->p.n, c->inv_h, s));
+    RETCHK(sort_swap(c, P, s));
+    HIPCHK(launch_deposit(P->np, P->cur.x, P->cur.y, P->cur.z, P->np > 0 ? P->cell_start : nullptr,
+                          F->rho, c->p.n, c->inv_h, c->qh3, c->p.rho_bg, c->st, c->partials, s));
+    pic_solve_info si;
+    int rc = pic_poisson_pcg(c, F->rho, F->phi, F->ex, F->ey, F->ez, &si, stream);
+    if (rc < 0) return rc;
+    HIPCHK(launch_half_kick(P->np, P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy, P->cur.vz,
+                            F->ex, F->ey, F->ez, c->p.n, c->inv_h, c->coef_kick, s));
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+        info->solve = si;
+        HIPCHK(hipStreamSynchronize(s));
+    }
+    return rc;
+}
+
+int pic_step(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, void* stream) {
+    RETCHK(check_parts(c, P, F));
+    hipStream_t s = (hipStream_t)stream;
+    PhaseTimer T;
+    RETCHK(T.init(info != nullptr));
+    RETCHK(T.mark(0, s));
+    HIPCHK(launch_gather_push(P->np, P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy, P->cur.vz,
+                              F->ex, F->ey, F->ez, P->key, c->p.n, c->inv_h, c->L, c->p.dt,
+                              c->coef_push, s));
+    RETCHK(T.mark(1, s));
+    RETCHK(sort_swap(c, P, s));
+    RETCHK(T.mark(2, s));
+    HIPCHK(launch_deposit(P->np, P->cur.x, P->cur.y, P->cur.z, P->np > 0 ? P->cell_start : nullptr,
+                          F->rho, c->p.n, c->inv_h, c->qh3, c->p.rho_bg, c->st, c->partials, s));
+    RETCHK(T.mark(3, s));
+    pic_solve_info si;
+    std::memset(&si, 0, sizeof si);
+    int rc;
+    switch (c->p.solver) {
+        case PIC_SOLVER_PCG_FP64: rc = solve_fp64(c, F->rho, F->phi, &si, s); break;
+        case PIC_SOLVER_PCG_MIXED: rc = solve_mixed(c, F->rho, F->phi, &si, s); break;
+        default: {
+            LearnedEnv env{c->geo, c->n3, c->inv_h2, c->minv, c->h, c->p.rtol, c->p.max_iter,
+                           c->p.check_every, c->p.fcg_window, c->st, c->st_host, c->partials,
+                           c->r, c->p2[0], c->p2[1]};
+            rc = learned_solve(c->learned, &env, F->rho, F->phi, &si, s);
+            if (rc < 0) return fail(rc, "learned solve: %s", learned_last_error());
+        }
+    }
+    if (rc < 0) return rc;
+    RETCHK(T.mark(4, s));
+    RETCHK(field(c, F->phi, F->ex, F->ey, F->ez, s));
+    RETCHK(T.mark(5, s));
+    if (info) {
+        RETCHK(read_state(c, s));
+        si.wx = c->st_host->wx;
+        info->solve = si;
+        info->ms_push = T.ms(0, 1);
+        info->ms_sort = T.ms(1, 2);
+        info->ms_deposit = T.ms(2, 3);
+        info->ms_solve = T.ms(3, 4);
+        info->ms_field = T.ms(4, 5);
+    }
+    return si.converged ? PIC_OK : PIC_NOT_CONVERGED;
+}
+
+}  // extern "C"

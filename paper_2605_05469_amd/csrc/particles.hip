@@ -1,0 +1,328 @@
+// particles.hip -- particle side of the PIC loop (Sec. 2, Fig. pic-loop):
+// cell keys, CIC gather + leapfrog push (Eq. eom, electrostatic), the initial
+// half kick, and the CIC charge deposit (scatter) with the neutralising
+// background of Sec. 2.
+//
+// Bit-exactness: the whole library is compiled without floating-point
+// contraction, and the per-particle arithmetic below follows the CPU oracle's
+// definition operation by operation (cell index floor(x*N/L) clamped to
+// [0, N-1]; weight products ((Wz*Wy)*Wx); gather summed z-offset outer, then y,
+// then x; v += (dt*qm)*E; x = wrap(x + dt*v)), so keys, positions and
+// velocities match the oracle bit for bit given the same field.
+//
+// Deposit on cell-sorted particles is written as a gather over the eight
+// cells around each vertex: every vertex sums its contributions in one fixed
+// order (cells in increasing key order, particles in sorted order) -- no
+// atomics, deterministic, and the same accumulation order as a sequential
+// scatter over the sorted particle list.
+#include "common.hpp"
+#include "particles.hpp"
+#include "solver_state.hpp"
+
+namespace pic {
+
+constexpr int kPT = 256;
+
+__device__ __forceinline__ void locate(double xd, int n, double inv_h, int& i, double& w) {
+    const double s = xd * inv_h;
+    const double f = floor(s);
+    int ii = (int)f;
+    if (ii > n - 1) ii = n - 1;
+    if (ii < 0) ii = 0;
+    i = ii;
+    w = s - (double)ii;
+}
+
+__device__ __forceinline__ double wrap(double xn, double L) {
+    if (xn >= L) xn = xn - L;
+    if (xn < 0.0) xn = xn + L;
+    if (xn >= L) xn = 0.0;
+    return xn;
+}
+
+__device__ __forceinline__ uint32_t key_of(double x, double y, double z, int n, double inv_h) {
+    int ix, iy, iz;
+    double w;
+    locate(x, n, inv_h, ix, w);
+    locate(y, n, inv_h, iy, w);
+    locate(z, n, inv_h, iz, w);
+    return (uint32_t)(((uint64_t)iz * n + iy) * n + ix);
+}
+
+// CIC gather of (Ex, Ey, Ez) at one particle.
+__device__ __forceinline__ void gather3(double px, double py, double pz, int n, double inv_h,
+                                        const double* __restrict__ ex,
+                                        const double* __restrict__ ey,
+                                        const double* __restrict__ ez, double& sx, double& sy,
+                                        double& sz) {
+    int i0, i1, i2;
+    double w0, w1, w2;
+    locate(px, n, inv_h, i0, w0);
+    locate(py, n, inv_h, i1, w1);
+    locate(pz, n, inv_h, i2, w2);
+    sx = 0.0;
+    sy = 0.0;
+    sz = 0.0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const double wz = c ? w2 : 1.0 - w2;
+        int vz = i2 + c;
+        vz = vz == n ? 0 : vz;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const double wy = b ? w1 : 1.0 - w1;
+            int vy = i1 + b;
+            vy = vy == n ? 0 : vy;
+            const size_t row = ((size_t)vz * n + vy) * n;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const double wx = a ? w0 : 1.0 - w0;
+                int vx = i0 + a;
+                vx = vx == n ? 0 : vx;
+                const size_t v = row + vx;
+                const double W = (wz * wy) * wx;
+                sx = sx + W * ex[v];
+                sy = sy + W * ey[v];
+                sz = sz + W * ez[v];
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(kPT) void keys_kernel(int64_t np, const double* __restrict__ x,
+                                                   const double* __restrict__ y,
+                                                   const double* __restrict__ z,
+                                                   uint32_t* __restrict__ key, int n, double inv_h) {
+    for (int64_t p = (int64_t)blockIdx.x * kPT + threadIdx.x; p < np; p += (int64_t)gridDim.x * kPT)
+        key[p] = key_of(x[p], y[p], z[p], n, inv_h);
+}
+
+__global__ __launch_bounds__(kPT) void gather_push_kernel(
+    int64_t np, double* __restrict__ x, double* __restrict__ y, double* __restrict__ z,
+    double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
+    const double* __restrict__ ex, const double* __restrict__ ey, const double* __restrict__ ez,
+    uint32_t* __restrict__ key, int n, double inv_h, double L, double dt, double coef) {
+    for (int64_t p = (int64_t)blockIdx.x * kPT + threadIdx.x; p < np; p += (int64_t)gridDim.x * kPT) {
+        const double px = x[p], py = y[p], pz = z[p];
+        double sx, sy, sz;
+        gather3(px, py, pz, n, inv_h, ex, ey, ez, sx, sy, sz);
+        const double ux = vx[p] + coef * sx;
+        const double uy = vy[p] + coef * sy;
+        const double uz = vz[p] + coef * sz;
+        const double nx = wrap(px + dt * ux, L);
+        const double ny = wrap(py + dt * uy, L);
+        const double nz = wrap(pz + dt * uz, L);
+        vx[p] = ux;
+        vy[p] = uy;
+        vz[p] = uz;
+        x[p] = nx;
+        y[p] = ny;
+        z[p] = nz;
+        if (key) key[p] = key_of(nx, ny, nz, n, inv_h);
+    }
+}
+
+__global__ __launch_bounds__(kPT) void half_kick_kernel(
+    int64_t np, const double* __restrict__ x, const double* __restrict__ y,
+    const double* __restrict__ z, double* __restrict__ vx, double* __restrict__ vy,
+    double* __restrict__ vz, const double* __restrict__ ex, const double* __restrict__ ey,
+    const double* __restrict__ ez, int n, double inv_h, double coef) {
+    for (int64_t p = (int64_t)blockIdx.x * kPT + threadIdx.x; p < np; p += (int64_t)gridDim.x * kPT) {
+        double sx, sy, sz;
+        gather3(x[p], y[p], z[p], n, inv_h, ex, ey, ez, sx, sy, sz);
+        vx[p] = vx[p] + coef * sx;
+        vy[p] = vy[p] + coef * sy;
+        vz[p] = vz[p] + coef * sz;
+    }
+}
+
+// Deterministic deposit on sorted particles: one thread per vertex.
+// rho[v] = (sum of CIC weights) * (q/h^3) + rho_bg; partial sums of rho.
+__global__ __launch_bounds__(kPT) void deposit_sorted_kernel(
+    const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
+    const uint32_t* __restrict__ cs, double* __restrict__ rho, int n, double inv_h, double qh3,
+    double rho_bg, double* part, DevState* st) {
+    __shared__ double red[kPT / kWave];
+    const int64_t n3 = (int64_t)n * n * n;
+    double acc[1] = {0.0};
+    for (int64_t v = (int64_t)blockIdx.x * kPT + threadIdx.x; v < n3; v += (int64_t)gridDim.x * kPT) {
+        const int ix = (int)(v % n);
+        const int iy = (int)((v / n) % n);
+        const int iz = (int)(v / ((int64_t)n * n));
+        double s = 0.0;
+        // Cells around the vertex in increasing key order: per axis the cell
+        // below (offset 1) precedes the cell at the vertex (offset 0), except
+        // at index 0 where the periodic image n-1 sorts last.
+        for (int kc = 0; kc < 2; ++kc) {
+            const int c = (iz == 0) ? kc : 1 - kc;
+            const int cz = iz - c < 0 ? n - 1 : iz - c;
+            for (int kb = 0; kb < 2; ++kb) {
+                const int b = (iy == 0) ? kb : 1 - kb;
+                const int cy = iy - b < 0 ? n - 1 : iy - b;
+                for (int ka = 0; ka < 2; ++ka) {
+                    const int a = (ix == 0) ? ka : 1 - ka;
+                    const int cx = ix - a < 0 ? n - 1 : ix - a;
+                    const size_t cell = ((size_t)cz * n + cy) * n + cx;
+                    const uint32_t pe = cs[cell + 1];
+                    for (uint32_t p = cs[cell]; p < pe; ++p) {
+                        int i0;
+                        double w0, w1, w2;
+                        locate(x[p], n, inv_h, i0, w0);
+                        locate(y[p], n, inv_h, i0, w1);
+                        locate(z[p], n, inv_h, i0, w2);
+                        const double wz = c ? w2 : 1.0 - w2;
+                        const double wy = b ? w1 : 1.0 - w1;
+                        const double wx = a ? w0 : 1.0 - w0;
+                        s += (wz * wy) * wx;
+                    }
+                }
+            }
+        }
+        const double rv = s * qh3 + rho_bg;
+        rho[v] = rv;
+        acc[0] += rv;
+    }
+    block_sum<kPT, 1>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+    __shared__ int lflag;
+    if (last_block(&st->tickets[7], gridDim.x, &lflag)) {
+        double t[1];
+        sum_partials<kPT, 1>(part, gridDim.x, t, red);
+        if (threadIdx.x == 0) st->mean = t[0] / (double)n3;
+    }
+}
+
+// Unsorted deposit: FP64 atomics into acc (zeroed), one thread per particle.
+__global__ __launch_bounds__(kPT) void deposit_atomic_kernel(int64_t np,
+                                                             const double* __restrict__ x,
+                                                             const double* __restrict__ y,
+                                                             const double* __restrict__ z,
+                                                             double* acc, int n, double inv_h) {
+    for (int64_t p = (int64_t)blockIdx.x * kPT + threadIdx.x; p < np; p += (int64_t)gridDim.x * kPT) {
+        int i0, i1, i2;
+        double w0, w1, w2;
+        locate(x[p], n, inv_h, i0, w0);
+        locate(y[p], n, inv_h, i1, w1);
+        locate(z[p], n, inv_h, i2, w2);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const double wz = c ? w2 : 1.0 - w2;
+            const int vz = i2 + c == n ? 0 : i2 + c;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const double wy = b ? w1 : 1.0 - w1;
+                const int vy = i1 + b == n ? 0 : i1 + b;
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const double wx = a ? w0 : 1.0 - w0;
+                    const int vx = i0 + a == n ? 0 : i0 + a;
+                    unsafeAtomicAdd(acc + (((size_t)vz * n + vy) * n + vx), (wz * wy) * wx);
+                }
+            }
+        }
+    }
+}
+
+// rho = acc * (q/h^3) + rho_bg in place; partial sums of rho.
+__global__ __launch_bounds__(kPT) void deposit_scale_kernel(int64_t n3, double* __restrict__ rho,
+                                                            double qh3, double rho_bg,
+                                                            double* part, DevState* st) {
+    __shared__ double red[kPT / kWave];
+    double acc[1] = {0.0};
+    for (int64_t v = (int64_t)blockIdx.x * kPT + threadIdx.x; v < n3; v += (int64_t)gridDim.x * kPT) {
+        const double rv = rho[v] * qh3 + rho_bg;
+        rho[v] = rv;
+        acc[0] += rv;
+    }
+    block_sum<kPT, 1>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+    __shared__ int lflag;
+    if (last_block(&st->tickets[7], gridDim.x, &lflag)) {
+        double t[1];
+        sum_partials<kPT, 1>(part, gridDim.x, t, red);
+        if (threadIdx.x == 0) st->mean = t[0] / (double)n3;
+    }
+}
+
+// b = rho - mean(rho) (mean formed by the previous kernel), partial sums of
+// b^2; the last block stores ||b||^2.
+__global__ __launch_bounds__(kPT) void project_kernel(int64_t n3, double* __restrict__ rho,
+                                                      double* part, DevState* st) {
+    __shared__ double red[kPT / kWave];
+    __shared__ int lflag;
+    const double mean = st->mean;
+    double acc[1] = {0.0};
+    for (int64_t v = (int64_t)blockIdx.x * kPT + threadIdx.x; v < n3; v += (int64_t)gridDim.x * kPT) {
+        const double bv = rho[v] - mean;
+        rho[v] = bv;
+        acc[0] += bv * bv;
+    }
+    block_sum<kPT, 1>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+    if (last_block(&st->tickets[6], gridDim.x, &lflag)) {
+        double t[1];
+        sum_partials<kPT, 1>(part, gridDim.x, t, red);
+        if (threadIdx.x == 0) st->bb = t[0];
+    }
+}
+
+// --------------------------------------------------------------------------
+static int pblocks(int64_t n, int cap = 8192) {
+    int64_t b = (n + kPT - 1) / kPT;
+    if (b < 1) b = 1;
+    return (int)(b < cap ? b : cap);
+}
+
+hipError_t launch_keys(int64_t np, const double* x, const double* y, const double* z,
+                       uint32_t* key, int n, double inv_h, hipStream_t s) {
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(keys_kernel, dim3(pblocks(np)), dim3(kPT), 0, s, np, x, y, z, key, n, inv_h);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_push(int64_t np, double* x, double* y, double* z, double* vx, double* vy,
+                              double* vz, const double* ex, const double* ey, const double* ez,
+                              uint32_t* key, int n, double inv_h, double L, double dt,
+                              double coef, hipStream_t s) {
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_push_kernel, dim3(pblocks(np, 16384)), dim3(kPT), 0, s, np, x, y, z,
+                       vx, vy, vz, ex, ey, ez, key, n, inv_h, L, dt, coef);
+    return hipGetLastError();
+}
+
+hipError_t launch_half_kick(int64_t np, const double* x, const double* y, const double* z,
+                            double* vx, double* vy, double* vz, const double* ex,
+                            const double* ey, const double* ez, int n, double inv_h, double coef,
+                            hipStream_t s) {
+    if (np == 0) return hipSuccess;
+    hipLaunchKernelGGL(half_kick_kernel, dim3(pblocks(np, 16384)), dim3(kPT), 0, s, np, x, y, z,
+                       vx, vy, vz, ex, ey, ez, n, inv_h, coef);
+    return hipGetLastError();
+}
+
+int deposit_partials() { return 4096; }
+
+hipError_t launch_deposit(int64_t np, const double* x, const double* y, const double* z,
+                          const uint32_t* cs, double* rho, int n, double inv_h, double qh3,
+                          double rho_bg, DevState* st, double* part, hipStream_t s) {
+    const int64_t n3 = (int64_t)n * n * n;
+    const int nb = pblocks(n3, deposit_partials());
+    if (cs) {
+        hipLaunchKernelGGL(deposit_sorted_kernel, dim3(nb), dim3(kPT), 0, s, x, y, z, cs, rho, n,
+                           inv_h, qh3, rho_bg, part, st);
+    } else {
+        hipError_t e = launch_fill(n3, rho, 0.0, s);
+        if (e != hipSuccess) return e;
+        if (np > 0)
+            hipLaunchKernelGGL(deposit_atomic_kernel, dim3(pblocks(np, 16384)), dim3(kPT), 0, s, np,
+                               x, y, z, rho, n, inv_h);
+        hipLaunchKernelGGL(deposit_scale_kernel, dim3(nb), dim3(kPT), 0, s, n3, rho, qh3, rho_bg,
+                           part, st);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(project_kernel, dim3(nb), dim3(kPT), 0, s, n3, rho, part, st);
+    return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,91 @@
+// solver_state.hpp -- device-resident scalars of the iterative solvers and the
+// launch interface of the field kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pic {
+
+// CG progress states (device).
+enum : int32_t {
+    CG_RUNNING = 0,
+    CG_CANDIDATE = 1,   // recursive residual passed the test; verify it
+    CG_CONVERGED = 2,
+    CG_MAXIT = 3,
+    CG_BREAKDOWN = 4,   // non-finite or non-positive curvature
+    CG_ZERO_RHS = 5
+};
+
+struct CgScalars {
+    double rz;        // r . M^{-1} r of the current residual
+    double alpha;
+    double beta;
+    double rr;        // last recursive r . r
+    double nb;        // ||b||
+    double tol;       // stop threshold on ||r||
+    double true_rn;   // last true residual norm
+    double pq;        // last p . A p
+    int64_t iter;
+    int64_t max_iter;
+    int32_t state;
+    int32_t restart;  // next direction = M^{-1} r (ignore the old direction)
+    int32_t replacements;
+    int32_t pad;
+};
+
+struct DevState {
+    CgScalars cg;      // the FP64 solve, or the inner FP32 solve of the mixed form
+    double out_nr;     // mixed: ||b - A x|| of the current outer step
+    double out_sc;     // mixed: 1 / out_nr
+    double mean;       // mean(phi) for the gauge fix
+    double wx;         // (1/2) h^3 sum Ex^2
+    double bb;         // ||b||^2
+    double sum;        // generic reduction result
+    double flex_zq;    // learned: z . q
+    double flex_zr;    // learned: z . r
+    int32_t outer_state;
+    int32_t pad;
+    uint32_t tickets[8];
+};
+
+// Geometry of a z-marching stencil sweep.
+struct SweepGeo {
+    int32_t n;      // grid points per axis
+    int32_t zc;     // planes per block
+    uint32_t nbx, nby, nbz, nb;
+};
+
+SweepGeo make_geo(int n);
+
+// Host launchers (stream-ordered, asynchronous).  All return hipError_t.
+// FP64 Jacobi-PCG pieces.
+hipError_t launch_residual64(const SweepGeo& g, const double* b, const double* x, double* r,
+                             double minv, double inv_h2, int init, double rtol, int64_t max_iter,
+                             DevState* st, double* partials, hipStream_t s);
+hipError_t launch_dir64(const SweepGeo& g, const double* r, const double* p_old, double* p_new,
+                        double minv, double inv_h2, DevState* st, double* partials, hipStream_t s);
+hipError_t launch_upd64(const SweepGeo& g, const double* p_new, double* x, double* r,
+                        double minv, double inv_h2, DevState* st, double* partials, hipStream_t s);
+// Mixed-precision pieces.
+hipError_t launch_outer_resid(const SweepGeo& g, const double* b, double* x, const float* d,
+                              double* r, int fuse_update, double inv_h2, DevState* st,
+                              double* partials, double tol, hipStream_t s);
+hipError_t launch_convert32(int64_t n3, const double* r, float* r32, float* d32, float minvf,
+                            double inner_rtol, int64_t max_inner, DevState* st,
+                            double* partials, hipStream_t s);
+hipError_t launch_dir32(const SweepGeo& g, const float* r, const float* p_old, float* p_new,
+                        float minvf, float inv_h2f, DevState* st, double* partials, hipStream_t s);
+hipError_t launch_upd32(const SweepGeo& g, const float* p_new, float* d, float* r, float minvf,
+                        float inv_h2f, DevState* st, double* partials, hipStream_t s);
+hipError_t launch_update_x(int64_t n3, double* x, const float* d, DevState* st, hipStream_t s);
+// Field.
+hipError_t launch_sum(int64_t n3, const double* v, DevState* st, double* partials, int what,
+                      hipStream_t s);
+hipError_t launch_field(const SweepGeo& g, double* phi, double* ex, double* ey, double* ez,
+                        double ehalf, double h3, DevState* st, double* partials, hipStream_t s);
+hipError_t launch_fill(int64_t n, double* v, double val, hipStream_t s);
+
+int partials_per_sweep(const SweepGeo& g);
+
+}  // namespace pic

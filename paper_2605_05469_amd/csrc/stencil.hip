@@ -1,0 +1,549 @@
+// stencil.hip -- matrix-free periodic 7-point sweeps of the PCG solver
+// (Sec. 3.2: second-order central differences, action of A only) and of the
+// field E = -grad phi (Sec. 2, Eq. poisson).
+//
+// Design (MI355X / gfx950):
+//  * One 256-thread workgroup owns a TX x 16 tile of (x, y) and marches over
+//    `zc` consecutive z-planes.  A ring of three LDS planes (z-1, z, z+1),
+//    each with a one-point periodic halo in x and y, holds the operand; every
+//    grid value is read from HBM once per sweep apart from the halo.
+//  * Each sweep fuses its vector updates and dot products: the direction
+//    sweep forms p_new = M^{-1} r + beta p_old while filling the ring and
+//    reduces p.(A p); the update sweep recomputes A p from p_new in LDS (no q
+//    vector is stored), updates x and r and reduces r.r and r.M^{-1} r.
+//    Per iteration this streams 24 + 40 = 64 bytes per grid point in FP64.
+//  * Dot products are deterministic: wave tree + fixed-order block sum, one
+//    partial per block, summed in index order by the last block, which also
+//    advances the CG scalars held in device memory (alpha, beta, state).  The
+//    host polls the state only every few iterations; once the state leaves
+//    RUNNING the remaining queued sweeps return immediately.
+//  * Workgroup ids are remapped so that neighbouring tiles run on one XCD and
+//    share its L2 for their halos.
+//
+// Arithmetic order matches the CPU oracle's definition (neighbour sum
+// ((xm+xp)+(ym+yp))+(zm+zp), no contraction) so that A p is bit-identical;
+// only the summation order of the dot products differs.
+#include "common.hpp"
+#include "solver_state.hpp"
+
+namespace pic {
+
+constexpr int kNT = 256;
+constexpr int kTY = 16;
+
+// --------------------------------------------------------------------------
+// Generic sweep.  Op provides:
+//   using T;  static constexpr int NACC;
+//   bool active() const;  void prepare();   // reads device scalars
+//   T load(size_t g, bool own);                      // value placed in LDS
+//   void out(size_t g, T c, T xm, T xp, T ym, T yp, T zm, T zp, double (&acc)[NACC]);
+//   void finish(double (&tot)[NACC]);                // thread 0 of last block
+//   uint32_t* ticket();  double* partials();
+template <class Op, int TX>
+__global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
+    using T = typename Op::T;
+    constexpr int NACC = Op::NACC;
+    constexpr int PX = TX + 2;
+    constexpr int PY = kTY + 2;
+    constexpr int PLANE = PX * PY;
+    constexpr int RPT = kNT / TX;     // thread rows
+    constexpr int PPT = kTY / RPT;    // points per thread per plane
+    __shared__ T ring[3][PLANE];
+    __shared__ double red[NACC > 0 ? NACC * (kNT / kWave) : 1];
+    __shared__ int lflag;
+
+    Op op = op_in;
+    if (!op.active()) return;
+    op.prepare();
+
+    const int n = g.n;
+    const uint32_t lb = remap_xcd(blockIdx.x, g.nb);
+    const uint32_t bx = lb % g.nbx;
+    const uint32_t t1 = lb / g.nbx;
+    const uint32_t by = t1 % g.nby;
+    const uint32_t bz = t1 / g.nby;
+    const int x0 = (int)bx * TX, y0 = (int)by * kTY, z0 = (int)bz * g.zc;
+    const size_t nn = (size_t)n * n;
+    const int tid = threadIdx.x;
+    const int lx = tid % TX, ly0 = tid / TX;
+
+    double acc[NACC > 0 ? NACC : 1];
+#pragma unroll
+    for (int k = 0; k < (NACC > 0 ? NACC : 1); ++k) acc[k] = 0.0;
+
+    auto fill = [&](T* dst, int gz, bool ownz) {
+        const size_t zoff = (size_t)gz * nn;
+        for (int e = tid; e < PLANE; e += kNT) {
+            const int ly = e / PX;
+            const int lxx = e - ly * PX;
+            int gx = x0 + lxx - 1;
+            gx = gx < 0 ? gx + n : (gx >= n ? gx - n : gx);
+            int gy = y0 + ly - 1;
+            gy = gy < 0 ? gy + n : (gy >= n ? gy - n : gy);
+            const bool own = ownz && lxx >= 1 && lxx <= TX && ly >= 1 && ly <= kTY;
+            dst[e] = op.load(zoff + (size_t)gy * n + gx, own);
+        }
+    };
+
+    T* sm = ring[0];
+    T* sc = ring[1];
+    T* sp = ring[2];
+    fill(sm, z0 == 0 ? n - 1 : z0 - 1, false);
+    fill(sc, z0, true);
+    for (int i = 0; i < g.zc; ++i) {
+        const int z = z0 + i;
+        fill(sp, z + 1 == n ? 0 : z + 1, i + 1 < g.zc);
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int ly = ly0 + k * RPT;
+            const int e = (ly + 1) * PX + lx + 1;
+            const size_t gi = (size_t)z * nn + (size_t)(y0 + ly) * n + (x0 + lx);
+            op.out(gi, sc[e], sc[e - 1], sc[e + 1], sc[e - PX], sc[e + PX], sm[e], sp[e], acc);
+        }
+        __syncthreads();
+        T* tmp = sm;
+        sm = sc;
+        sc = sp;
+        sp = tmp;
+    }
+
+    if constexpr (NACC > 0) {
+        block_sum<kNT, NACC>(acc, red);
+        double* part = op.partials();
+        if (tid == 0) {
+#pragma unroll
+            for (int k = 0; k < NACC; ++k) part[(size_t)k * g.nb + lb] = acc[k];
+        }
+        if (last_block(op.ticket(), g.nb, &lflag)) {
+            double tot[NACC];
+            sum_partials<kNT, NACC>(part, (int)g.nb, tot, red);
+            if (tid == 0) op.finish(tot);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// The operator at one point, in the oracle's order.
+template <class T>
+__device__ __forceinline__ T apply_A(T c, T xm, T xp, T ym, T yp, T zm, T zp, T inv_h2) {
+    T t = ((xm + xp) + (ym + yp)) + (zm + zp);
+    return (T(6) * c - t) * inv_h2;
+}
+
+// r = b - A x with norms.  init != 0: first residual of a solve (also forms
+// ||b|| and the stop threshold); otherwise the check of a candidate.
+struct OpResidual64 {
+    using T = double;
+    static constexpr int NACC = 3;
+    const double* b;
+    const double* x;
+    double* r;
+    double minv, inv_h2, rtol;
+    int64_t max_iter;
+    int init;
+    DevState* st;
+    double* part;
+    __device__ bool active() const {
+        return init ? true : st->cg.state == CG_CANDIDATE;
+    }  // init: 1 = first residual of a solve, 0 = verify a candidate, 2 = report only
+    __device__ void prepare() {}
+    __device__ double load(size_t g, bool) const { return x[g]; }
+    __device__ void out(size_t g, double c, double xm, double xp, double ym, double yp, double zm,
+                        double zp, double (&acc)[3]) const {
+        const double bv = b[g];
+        const double rv = bv - apply_A<double>(c, xm, xp, ym, yp, zm, zp, inv_h2);
+        r[g] = rv;
+        acc[0] += bv * bv;
+        acc[1] += rv * rv;
+        acc[2] += rv * (minv * rv);
+    }
+    __device__ void finish(double (&t)[3]) const {
+        CgScalars& cg = st->cg;
+        if (init == 2) {
+            cg.true_rn = sqrt(t[1]);
+            return;
+        }
+        if (init) {
+            st->bb = t[0];
+            cg.nb = sqrt(t[0]);
+            cg.tol = rtol * cg.nb;
+            cg.iter = 0;
+            cg.max_iter = max_iter;
+            cg.replacements = 0;
+            cg.restart = 1;
+            cg.alpha = 0.0;
+            cg.beta = 0.0;
+        }
+        const double rn = sqrt(t[1]);
+        cg.true_rn = rn;
+        cg.rr = t[1];
+        cg.rz = t[2];
+        cg.restart = 1;
+        if (init && cg.nb == 0.0) {
+            cg.state = CG_ZERO_RHS;
+        } else if (!isfinite(rn)) {
+            cg.state = CG_BREAKDOWN;
+        } else if (rn <= cg.tol) {
+            cg.state = CG_CONVERGED;
+        } else {
+            if (!init) cg.replacements += 1;
+            cg.state = cg.iter >= cg.max_iter ? CG_MAXIT : CG_RUNNING;
+        }
+    }
+    __device__ uint32_t* ticket() const { return &st->tickets[0]; }
+    __device__ double* partials() const { return part; }
+};
+
+// Direction sweep: p_new = M^{-1} r + beta p_old (filled into LDS and stored
+// at own points), reduce p_new . A p_new; the last block forms alpha.
+// beta and the restart flag are read from the device state at kernel start.
+template <class V>
+struct OpDir {
+    using T = V;
+    static constexpr int NACC = 1;
+    const V* r;
+    const V* p_old;
+    V* p_new;
+    V minv, inv_h2;
+    DevState* st;
+    double* part;
+    V beta;
+    int restart;
+    __device__ bool active() const { return st->cg.state == CG_RUNNING; }
+    __device__ void prepare() {
+        restart = st->cg.restart;
+        beta = (V)st->cg.beta;
+    }
+    __device__ V load(size_t g, bool own) const {
+        V pn = minv * r[g];
+        if (!restart) pn = pn + beta * p_old[g];
+        if (own) p_new[g] = pn;
+        return pn;
+    }
+    __device__ void out(size_t, V c, V xm, V xp, V ym, V yp, V zm, V zp, double (&acc)[1]) const {
+        const V q = apply_A<V>(c, xm, xp, ym, yp, zm, zp, inv_h2);
+        acc[0] += (double)c * (double)q;
+    }
+    __device__ void finish(double (&t)[1]) const {
+        CgScalars& cg = st->cg;
+        cg.pq = t[0];
+        const double a = cg.rz / t[0];
+        cg.alpha = a;
+        cg.restart = 0;
+        if (!isfinite(a) || !(t[0] > 0.0)) cg.state = CG_BREAKDOWN;
+    }
+    __device__ uint32_t* ticket() const { return &st->tickets[1]; }
+    __device__ double* partials() const { return part; }
+};
+
+// Update sweep: x += alpha p, r -= alpha A p; reduce r.r and r.M^{-1} r; the
+// last block advances the iteration (stop test on ||r||, then beta).  For the
+// FP32 inner solve of the mixed form the same test uses the inner threshold
+// and CG_CANDIDATE just ends the inner solve.
+template <class V>
+struct OpUpd {
+    using T = V;
+    static constexpr int NACC = 2;
+    const V* p;
+    V* x;
+    V* r;
+    V minv, inv_h2;
+    DevState* st;
+    double* part;
+    V alpha;
+    __device__ bool active() const { return st->cg.state == CG_RUNNING; }
+    __device__ void prepare() { alpha = (V)st->cg.alpha; }
+    __device__ V load(size_t g, bool) const { return p[g]; }
+    __device__ void out(size_t g, V c, V xm, V xp, V ym, V yp, V zm, V zp, double (&acc)[2]) const {
+        const V q = apply_A<V>(c, xm, xp, ym, yp, zm, zp, inv_h2);
+        const V xv = x[g] + alpha * c;
+        const V rv = r[g] - alpha * q;
+        x[g] = xv;
+        r[g] = rv;
+        acc[0] += (double)rv * (double)rv;
+        acc[1] += (double)rv * (double)(minv * rv);
+    }
+    __device__ void finish(double (&t)[2]) const {
+        CgScalars& cg = st->cg;
+        cg.iter += 1;
+        cg.rr = t[0];
+        const double rn = sqrt(t[0]);
+        if (!isfinite(rn)) {
+            cg.state = CG_BREAKDOWN;
+            return;
+        }
+        if (rn <= cg.tol) {
+            cg.state = CG_CANDIDATE;
+            return;
+        }
+        cg.beta = t[1] / cg.rz;
+        cg.rz = t[1];
+        if (cg.iter >= cg.max_iter) cg.state = CG_MAXIT;
+    }
+    __device__ uint32_t* ticket() const { return &st->tickets[2]; }
+    __device__ double* partials() const { return part; }
+};
+
+// Mixed form, outer step: optionally x <- x + ||r_prev|| * d (fused into the
+// fill), then r = b - A x in FP64; reduce r.r; the last block decides.
+struct OpOuterResid {
+    using T = double;
+    static constexpr int NACC = 1;
+    const double* b;
+    double* x;
+    const float* d;
+    double* r;
+    double inv_h2;
+    double tol;    // outer stop threshold rtol * ||b||
+    double scale;  // ||r_prev||, read from the state at launch
+    int fuse_update;
+    DevState* st;
+    double* part;
+    __device__ bool active() const { return st->outer_state == CG_RUNNING; }
+    __device__ void prepare() { scale = st->out_nr; }
+    __device__ double load(size_t g, bool own) const {
+        double v = x[g];
+        if (fuse_update) {
+            v = v + scale * (double)d[g];
+            if (own) x[g] = v;
+        }
+        return v;
+    }
+    __device__ void out(size_t g, double c, double xm, double xp, double ym, double yp, double zm,
+                        double zp, double (&acc)[1]) const {
+        const double rv = b[g] - apply_A<double>(c, xm, xp, ym, yp, zm, zp, inv_h2);
+        r[g] = rv;
+        acc[0] += rv * rv;
+    }
+    __device__ void finish(double (&t)[1]) const {
+        const double nr = sqrt(t[0]);
+        st->out_nr = nr;
+        st->out_sc = 1.0 / nr;
+        st->cg.true_rn = nr;
+        if (!isfinite(nr)) st->outer_state = CG_BREAKDOWN;
+        else if (nr <= tol) st->outer_state = CG_CONVERGED;
+    }
+    __device__ uint32_t* ticket() const { return &st->tickets[3]; }
+    __device__ double* partials() const { return part; }
+};
+
+// Field: phi <- phi - mean (written at own points), E = -grad phi,
+// W_x = (1/2) h^3 sum Ex^2.
+struct OpField {
+    using T = double;
+    static constexpr int NACC = 1;
+    double* phi;
+    double* ex;
+    double* ey;
+    double* ez;
+    double ehalf, h3, mean;
+    DevState* st;
+    double* part;
+    __device__ bool active() const { return true; }
+    __device__ void prepare() { mean = st->mean; }
+    __device__ double load(size_t g, bool own) const {
+        const double v = phi[g] - mean;
+        if (own) phi[g] = v;
+        return v;
+    }
+    __device__ void out(size_t g, double, double xm, double xp, double ym, double yp, double zm,
+                        double zp, double (&acc)[1]) const {
+        const double exv = -(xp - xm) * ehalf;
+        ex[g] = exv;
+        ey[g] = -(yp - ym) * ehalf;
+        ez[g] = -(zp - zm) * ehalf;
+        acc[0] += exv * exv;
+    }
+    __device__ void finish(double (&t)[1]) const { st->wx = 0.5 * t[0] * h3; }
+    __device__ uint32_t* ticket() const { return &st->tickets[4]; }
+    __device__ double* partials() const { return part; }
+};
+
+// --------------------------------------------------------------------------
+// Streaming (non-stencil) kernels.
+constexpr int kStreamBlocks = 2048;
+
+// r32 = (float)(r * (1/||r||)), d = 0; reduce r32.r32 and r32.(minv r32); the
+// last block starts the inner solve.
+__global__ __launch_bounds__(kNT) void convert32_kernel(int64_t n3, const double* __restrict__ r,
+                                                        float* __restrict__ r32,
+                                                        float* __restrict__ d32, float minvf,
+                                                        double inner_rtol, int64_t max_inner,
+                                                        DevState* st, double* part) {
+    __shared__ double red[2 * (kNT / kWave)];
+    __shared__ int lflag;
+    if (st->outer_state != CG_RUNNING) return;
+    const double sc = st->out_sc;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT) {
+        const float v = (float)(r[i] * sc);
+        r32[i] = v;
+        d32[i] = 0.0f;
+        acc[0] += (double)v * (double)v;
+        acc[1] += (double)v * (double)(minvf * v);
+    }
+    block_sum<kNT, 2>(acc, red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc[0];
+        part[gridDim.x + blockIdx.x] = acc[1];
+    }
+    if (last_block(&st->tickets[5], gridDim.x, &lflag)) {
+        double tot[2];
+        sum_partials<kNT, 2>(part, gridDim.x, tot, red);
+        if (threadIdx.x == 0) {
+            CgScalars& cg = st->cg;
+            const double n0 = sqrt(tot[0]);
+            cg.nb = n0;
+            cg.tol = inner_rtol * n0;
+            cg.rz = tot[1];
+            cg.rr = tot[0];
+            cg.iter = 0;
+            cg.max_iter = max_inner;
+            cg.restart = 1;
+            cg.state = (n0 == 0.0 || !isfinite(n0)) ? CG_BREAKDOWN : CG_RUNNING;
+        }
+    }
+}
+
+// x += ||r|| * d (used when the update is not fused into the next residual).
+__global__ __launch_bounds__(kNT) void update_x_kernel(int64_t n3, double* __restrict__ x,
+                                                       const float* __restrict__ d,
+                                                       const DevState* st) {
+    const double s = st->out_nr;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
+        x[i] = x[i] + s * (double)d[i];
+}
+
+// sum of v (what = 0: st->mean = sum/n3; what = 1: st->bb = sum v^2).
+__global__ __launch_bounds__(kNT) void sum_kernel(int64_t n3, const double* __restrict__ v,
+                                                  DevState* st, double* part, int what) {
+    __shared__ double red[kNT / kWave];
+    __shared__ int lflag;
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT) {
+        const double a = v[i];
+        acc[0] += what ? a * a : a;
+    }
+    block_sum<kNT, 1>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+    if (last_block(&st->tickets[6], gridDim.x, &lflag)) {
+        double tot[1];
+        sum_partials<kNT, 1>(part, gridDim.x, tot, red);
+        if (threadIdx.x == 0) {
+            if (what == 0) st->mean = tot[0] / (double)n3;
+            else st->bb = tot[0];
+            st->sum = tot[0];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kNT) void fill_kernel(int64_t n, double* __restrict__ v, double val) {
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kNT)
+        v[i] = val;
+}
+
+// --------------------------------------------------------------------------
+// Host side.
+SweepGeo make_geo(int n) {
+    SweepGeo g;
+    g.n = n;
+    const int tx = (n % 64 == 0) ? 64 : 32;
+    g.nbx = (uint32_t)(n / tx);
+    g.nby = (uint32_t)(n / kTY);
+    // choose the z-chunk so that there are enough workgroups to fill 256 CUs
+    int zc = n;
+    while (zc > 4 && (uint64_t)g.nbx * g.nby * (uint64_t)(n / zc) < 2048 && (zc % 2) == 0) zc /= 2;
+    g.zc = zc;
+    g.nbz = (uint32_t)(n / zc);
+    g.nb = g.nbx * g.nby * g.nbz;
+    return g;
+}
+
+int partials_per_sweep(const SweepGeo& g) { return (int)g.nb; }
+
+template <class Op>
+static hipError_t launch_sweep(const Op& op, const SweepGeo& g, hipStream_t s) {
+    if (g.n % 64 == 0)
+        hipLaunchKernelGGL((sweep_kernel<Op, 64>), dim3(g.nb), dim3(kNT), 0, s, op, g);
+    else
+        hipLaunchKernelGGL((sweep_kernel<Op, 32>), dim3(g.nb), dim3(kNT), 0, s, op, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual64(const SweepGeo& g, const double* b, const double* x, double* r,
+                             double minv, double inv_h2, int init, double rtol, int64_t max_iter,
+                             DevState* st, double* partials, hipStream_t s) {
+    OpResidual64 op{b, x, r, minv, inv_h2, rtol, max_iter, init, st, partials};
+    return launch_sweep(op, g, s);
+}
+
+hipError_t launch_dir64(const SweepGeo& g, const double* r, const double* p_old, double* p_new,
+                        double minv, double inv_h2, DevState* st, double* partials, hipStream_t s) {
+    OpDir<double> op{r, p_old, p_new, minv, inv_h2, st, partials, 0.0, 0};
+    return launch_sweep(op, g, s);
+}
+
+hipError_t launch_upd64(const SweepGeo& g, const double* p_new, double* x, double* r, double minv,
+                        double inv_h2, DevState* st, double* partials, hipStream_t s) {
+    OpUpd<double> op{p_new, x, r, minv, inv_h2, st, partials, 0.0};
+    return launch_sweep(op, g, s);
+}
+
+hipError_t launch_dir32(const SweepGeo& g, const float* r, const float* p_old, float* p_new,
+                        float minvf, float inv_h2f, DevState* st, double* partials, hipStream_t s) {
+    OpDir<float> op{r, p_old, p_new, minvf, inv_h2f, st, partials, 0.0f, 0};
+    return launch_sweep(op, g, s);
+}
+
+hipError_t launch_upd32(const SweepGeo& g, const float* p_new, float* d, float* r, float minvf,
+                        float inv_h2f, DevState* st, double* partials, hipStream_t s) {
+    OpUpd<float> op{p_new, d, r, minvf, inv_h2f, st, partials, 0.0f};
+    return launch_sweep(op, g, s);
+}
+
+hipError_t launch_outer_resid(const SweepGeo& g, const double* b, double* x, const float* d,
+                              double* r, int fuse_update, double inv_h2, DevState* st,
+                              double* partials, double tol, hipStream_t s) {
+    OpOuterResid op{b, x, d, r, inv_h2, tol, 0.0, fuse_update, st, partials};
+    return launch_sweep(op, g, s);
+}
+
+hipError_t launch_field(const SweepGeo& g, double* phi, double* ex, double* ey, double* ez,
+                        double ehalf, double h3, DevState* st, double* partials, hipStream_t s) {
+    OpField op{phi, ex, ey, ez, ehalf, h3, 0.0, st, partials};
+    return launch_sweep(op, g, s);
+}
+
+static int stream_blocks(int64_t n) {
+    int64_t b = (n + kNT - 1) / kNT;
+    return (int)(b < kStreamBlocks ? (b < 1 ? 1 : b) : kStreamBlocks);
+}
+
+hipError_t launch_convert32(int64_t n3, const double* r, float* r32, float* d32, float minvf,
+                            double inner_rtol, int64_t max_inner, DevState* st, double* partials,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(convert32_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, r, r32, d32,
+                       minvf, inner_rtol, max_inner, st, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_update_x(int64_t n3, double* x, const float* d, DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(update_x_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, x, d,
+                       (const DevState*)st);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(int64_t n3, const double* v, DevState* st, double* partials, int what,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(sum_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, v, st, partials,
+                       what);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(int64_t n, double* v, double val, hipStream_t s) {
+    hipLaunchKernelGGL(fill_kernel, dim3(stream_blocks(n)), dim3(kNT), 0, s, n, v, val);
+    return hipGetLastError();
+}
+
+}  // namespace pic
