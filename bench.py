@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark of the electrostatic PIC step on one MI355X.
+
+Workload (default): Landau damping (k = 0.5, alpha = 0.05, L = 4 pi) on a
+512^3 grid with 8 particles per cell (2^30 particles, FP64 positions and
+velocities), Jacobi-PCG to relative residual 1e-10, dt = 0.05 -- the paper's
+case A shape (Sec. 4.1, Table setup_sizes) on one GPU.  A step is one pass of
+the whole hot path: gather + push -> stable cell sort -> CIC deposit -> PCG
+solve (warm start) -> field.  Inputs are synthetic and seeded, drawn on the
+device; initialisation and the t = 0 solve are not timed (Sec. 4.1 times the
+run minus initialisation).
+
+Prints ONE JSON line.  `roofline` is for the dominant kernel (the PCG update
+sweep), timed with HIP events on the stream it runs on during the timed
+steps; `cpu_baseline` times the CPU oracle on a bounded sample of the same
+workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "s/PIC step + PCG HBM GB/s, 512^3x8ppc; learned vs plain time at rtol 1e-10"
+PEAK_HBM_GBS = 8000.0
+# algorithmic bytes per grid point of one launch of each PCG sweep (FP64):
+# direction sweep reads r, p_old and writes p_new; update sweep reads p, x, r
+# and writes x, r.  (FP32 inner sweeps of the mixed form: half.)
+SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 40)}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(N, ppc, p, sim, iters_per_step, budget_s):
+    """Time the CPU oracle on a bounded sample of the same step and scale it
+    to seconds per step: PCG iterations at the full grid (from the GPU's
+    right-hand side) x iterations per step, plus the particle phases timed at
+    two sample sizes and extrapolated linearly to all particles, plus the
+    field at the full grid."""
+    import numpy as np
+    import torch
+
+    import oracle
+
+    oracle.build()
+    L = p.length
+    threads = oracle.num_threads()
+    b = sim.rho.cpu().numpy()
+    phi = sim.phi.cpu().numpy()
+    ex, ey, ez = (t.cpu().numpy() for t in (sim.ex, sim.ey, sim.ez))
+    # PCG: k iterations from the previous potential
+    tm = {}
+    for m in (1, 5):
+        t0 = time.perf_counter()
+        oracle.pcg(N, L, b, phi, p.rtol, m)
+        tm[m] = time.perf_counter() - t0
+    t_iter = max((tm[5] - tm[1]) / 4.0, tm[1] / 2.0)
+    # field at the full grid
+    t0 = time.perf_counter()
+    oracle.efield(N, L, phi)
+    t_field = time.perf_counter() - t0
+    # particle phases (push, keys, sort, deposit) at two sample sizes
+    cur = sim.particles
+    samples = []
+    for n in (1 << 20, 1 << 21):
+        parts = [a[:n].cpu().numpy() for a in cur]
+        t0 = time.perf_counter()
+        out = oracle.gather_push(N, L, p.dt, p.qm, *parts, ex, ey, ez)
+        perm, cs = oracle.sort_by_key(out[6], N ** 3)
+        xs = [out[k][perm] for k in range(3)]
+        oracle.deposit(N, L, p.charge, p.rho_bg, *xs)
+        samples.append((n, time.perf_counter() - t0))
+    (n1, s1), (n2, s2) = samples
+    per_particle = max((s2 - s1) / (n2 - n1), 0.0)
+    fixed = max(s1 - per_particle * n1, 0.0)
+    npart = ppc * N ** 3
+    t_particles = fixed + per_particle * npart
+    s_step = iters_per_step * t_iter + t_particles + t_field
+    sample = ("oracle PCG: 1 and 5 iterations at %d^3 (%.3f s/iteration) x %.0f iterations/step; "
+              "gather+push+sort+deposit on 2^20 and 2^21 particles extrapolated linearly to %d "
+              "(%.1f s); field at %d^3 (%.2f s)" % (N, t_iter, iters_per_step, npart, t_particles,
+                                                   N, t_field))
+    return {"value": s_step, "unit": "s/step", "cores": threads, "kind": "oracle",
+            "sample": sample}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=512)
+    ap.add_argument("--ppc", type=int, default=8)
+    ap.add_argument("--solver", default="pcg_fp64", choices=sorted(SWEEP_BYTES))
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--seed", type=int, default=20262)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2605_05469_amd as P
+    from paper_2605_05469_amd import synth
+
+    torch.cuda.set_device(0)
+    N, ppc = args.grid, args.ppc
+    p = P.landau_params(N, ppc, rtol=args.rtol, solver=args.solver, check_every=32)
+    ctx = P.Context(p)
+    t0 = time.perf_counter()
+    parts = synth.landau_particles_torch(N, ppc, seed=args.seed, device="cuda")
+    sim = P.Simulation(ctx, *parts)
+    del parts
+    info0 = sim.init()
+    torch.cuda.synchronize()
+    log("init: %.1f s, t=0 solve %d iterations" % (time.perf_counter() - t0, info0["iterations"]))
+    for k in range(args.warmup):
+        w = sim.step()
+        log("warmup %d: %d iterations, %.1f ms solve" % (k, w["iterations"], w["ms_solve"]))
+
+    ctx.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(args.steps):
+        infos.append(sim.step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s_step = elapsed / args.steps
+    iters = sum(i["iterations"] for i in infos) / len(infos)
+    n3 = N ** 3
+    npart = ppc * n3
+    bdir, bupd = SWEEP_BYTES[args.solver]
+    ms_dir, cnt_dir = P.Context.kernel_time(ctx, 0)
+    ms_upd, cnt_upd = P.Context.kernel_time(ctx, 1)
+    # (pic_step accumulates the sampled kernel times over all timed steps)
+    ctx.set_kernel_timing(False)
+    gbs_upd = bupd * n3 / (ms_upd * 1e-3) / 1e9 if ms_upd > 0 else 0.0
+    gbs_dir = bdir * n3 / (ms_dir * 1e-3) / 1e9 if ms_dir > 0 else 0.0
+    gbs_iter = (bdir + bupd) * n3 / ((ms_dir + ms_upd) * 1e-3) / 1e9 if ms_upd > 0 else 0.0
+    phases = {k: sum(i[k] for i in infos) / len(infos)
+              for k in ("ms_push", "ms_sort", "ms_deposit", "ms_solve", "ms_field")}
+    for i, inf in enumerate(infos):
+        log("step %d: %d iterations, rel_res %.2e, solve %.0f ms" % (i, inf["iterations"],
+                                                                     inf["rel_res"], inf["ms_solve"]))
+    out = {
+        "metric": METRIC,
+        "value": s_step,
+        "unit": "s/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * s_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.solver != "pcg_mixed" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "landau_damping_%d^3_%dppc_%s" % (N, ppc, args.solver),
+                   "grid": N, "ppc": ppc, "particles": npart, "solver": args.solver,
+                   "rtol": args.rtol, "dt": p.dt, "k": 0.5, "alpha": 0.05,
+                   "parallelism": "single_gpu"},
+        "particles_per_s": npart / s_step,
+        "pcg_iterations_per_step": iters,
+        "pcg_gbs_per_iteration": gbs_iter,
+        "all_converged": all(i["converged"] for i in infos),
+        "max_rel_res": max(i["rel_res"] for i in infos),
+        "phases_ms": phases,
+        "kernels": {"pcg_direction_sweep": {"avg_ms": ms_dir, "launches_timed": cnt_dir,
+                                            "bytes_per_point": bdir, "gbs": gbs_dir},
+                    "pcg_update_sweep": {"avg_ms": ms_upd, "launches_timed": cnt_upd,
+                                         "bytes_per_point": bupd, "gbs": gbs_upd}},
+        "roofline": {"bound": "hbm", "kernel": "pcg_update_sweep", "achieved": gbs_upd,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs_upd / PEAK_HBM_GBS,
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(N, ppc, p, sim, iters, args.cpu_budget)
+        except Exception as e:  # the GPU line must still be printed
+            out["cpu_baseline"] = {"error": repr(e)}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -52,6 +52,7 @@ def lib():
         L = ctypes.CDLL(_LIB)
         c_int, c_i64, c_dbl = ctypes.c_int, ctypes.c_int64, ctypes.c_double
         L.or_abi_version.restype = c_int
+        L.or_num_threads.restype = c_int
         L.or_cell_keys.argtypes = [c_i64, c_int, c_dbl, _dp, _dp, _dp, _u32p]
         L.or_sort_by_key.argtypes = [c_i64, c_i64, _u32p, _i64p, _i64p]
         L.or_sort_by_key.restype = c_int
@@ -75,6 +76,10 @@ def lib():
                              ctypes.c_void_p, _dp]
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
 
 
 def _f64(a):

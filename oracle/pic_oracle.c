@@ -654,3 +654,11 @@ void or_deposit_vertices(int64_t np, int N, double L, double q, const double *x,
         out[k] = acc * qh3;
     }
 }
+
+/* Threads the OpenMP loops above use (for reporting the CPU baseline). */
+#ifdef _OPENMP
+#include <omp.h>
+int or_num_threads(void) { return omp_get_max_threads(); }
+#else
+int or_num_threads(void) { return 1; }
+#endif

@@ -182,9 +182,14 @@ static int timing_events(pic_ctx* c, size_t need) {
     return PIC_OK;
 }
 
-// Accumulate the first `valid` (iteration) pairs of a batch.
+// Kernel timing samples every kTimeStride-th iteration of a batch (events
+// between every launch would perturb what they measure).
+constexpr int kTimeStride = 4;
+static bool timed_iter(const pic_ctx* c, int k) { return c->timing && (k % kTimeStride) == 0; }
+
+// Accumulate the sampled pairs among the first `valid` iterations of a batch.
 static int timing_collect(pic_ctx* c, int launched, int64_t valid) {
-    for (int k = 0; k < launched && k < valid; ++k) {
+    for (int k = 0; k < launched && k < valid; k += kTimeStride) {
         for (int j = 0; j < 2; ++j) {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, c->ev[4 * k + 2 * j], c->ev[4 * k + 2 * j + 1]));
@@ -209,14 +214,14 @@ static int pcg64_iterate(pic_ctx* c, const double* b, double* x, hipStream_t s) 
         if (cg.state == CG_RUNNING) {
             const int64_t it0 = cg.iter;
             for (int k = 0; k < K; ++k) {
-                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
+                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
                 HIPCHK(launch_dir64(g, c->r, c->p2[cur], c->p2[cur ^ 1], c->minv, c->inv_h2, c->st,
                                     c->partials, s));
-                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
-                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 2], s));
+                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
+                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 2], s));
                 HIPCHK(launch_upd64(g, c->p2[cur ^ 1], x, c->r, c->minv, c->inv_h2, c->st,
                                     c->partials, s));
-                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 3], s));
+                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 3], s));
                 cur ^= 1;
             }
             RETCHK(read_state(c, s));
@@ -287,8 +292,8 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
     int cur = 0;
     if (c->timing) RETCHK(timing_events(c, (size_t)4 * K));
     for (;;) {
-        HIPCHK(launch_outer_resid(g, b, x, c->d32, c->r, outer > 0 ? 1 : 0, c->inv_h2, c->st,
-                                  c->partials, tol, s));
+        if (outer > 0) HIPCHK(launch_update_x(c->n3, x, c->d32, c->st, s));
+        HIPCHK(launch_outer_resid(g, b, x, c->r, c->inv_h2, c->st, c->partials, tol, s));
         RETCHK(read_state(c, s));
         const double nr = c->st_host->out_nr;
         if (!std::isfinite(nr)) break;
@@ -304,14 +309,14 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
         while (c->st_host->cg.state == CG_RUNNING) {
             const int64_t it0 = c->st_host->cg.iter;
             for (int k = 0; k < K; ++k) {
-                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
+                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
                 HIPCHK(launch_dir32(g, c->r32, c->p32[cur], c->p32[cur ^ 1], c->minvf, c->inv_h2f,
                                     c->st, c->partials, s));
-                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
-                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 2], s));
+                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
+                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 2], s));
                 HIPCHK(launch_upd32(g, c->p32[cur ^ 1], c->d32, c->r32, c->minvf, c->inv_h2f, c->st,
                                     c->partials, s));
-                if (c->timing) HIPCHK(hipEventRecord(c->ev[4 * k + 3], s));
+                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 3], s));
                 cur ^= 1;
             }
             RETCHK(read_state(c, s));

@@ -68,9 +68,9 @@ hipError_t launch_dir64(const SweepGeo& g, const double* r, const double* p_old,
 hipError_t launch_upd64(const SweepGeo& g, const double* p_new, double* x, double* r,
                         double minv, double inv_h2, DevState* st, double* partials, hipStream_t s);
 // Mixed-precision pieces.
-hipError_t launch_outer_resid(const SweepGeo& g, const double* b, double* x, const float* d,
-                              double* r, int fuse_update, double inv_h2, DevState* st,
-                              double* partials, double tol, hipStream_t s);
+hipError_t launch_outer_resid(const SweepGeo& g, const double* b, const double* x, double* r,
+                              double inv_h2, DevState* st, double* partials, double tol,
+                              hipStream_t s);
 hipError_t launch_convert32(int64_t n3, const double* r, float* r32, float* d32, float minvf,
                             double inner_rtol, int64_t max_inner, DevState* st,
                             double* partials, hipStream_t s);

@@ -32,7 +32,9 @@ constexpr int kNT = 256;
 constexpr int kTY = 16;
 
 // --------------------------------------------------------------------------
-// Generic sweep.  Op provides:
+// Generic sweep.  A sweep never writes the array it stages into LDS:
+// neighbouring workgroups read that array as their halo at any time.
+// Op provides:
 //   using T;  static constexpr int NACC;
 //   bool active() const;  void prepare();   // reads device scalars
 //   T load(size_t g, bool own);                      // value placed in LDS
@@ -285,31 +287,23 @@ struct OpUpd {
     __device__ double* partials() const { return part; }
 };
 
-// Mixed form, outer step: optionally x <- x + ||r_prev|| * d (fused into the
-// fill), then r = b - A x in FP64; reduce r.r; the last block decides.
+// Mixed form, outer step: r = b - A x in FP64; reduce r.r; the last block
+// decides.  (The correction x += ||r_prev|| d is a separate pass before it:
+// a sweep never writes the array it stages, because neighbouring workgroups
+// read that array as their halo.)
 struct OpOuterResid {
     using T = double;
     static constexpr int NACC = 1;
     const double* b;
-    double* x;
-    const float* d;
+    const double* x;
     double* r;
     double inv_h2;
-    double tol;    // outer stop threshold rtol * ||b||
-    double scale;  // ||r_prev||, read from the state at launch
-    int fuse_update;
+    double tol;  // outer stop threshold rtol * ||b||
     DevState* st;
     double* part;
     __device__ bool active() const { return st->outer_state == CG_RUNNING; }
-    __device__ void prepare() { scale = st->out_nr; }
-    __device__ double load(size_t g, bool own) const {
-        double v = x[g];
-        if (fuse_update) {
-            v = v + scale * (double)d[g];
-            if (own) x[g] = v;
-        }
-        return v;
-    }
+    __device__ void prepare() {}
+    __device__ double load(size_t g, bool) const { return x[g]; }
     __device__ void out(size_t g, double c, double xm, double xp, double ym, double yp, double zm,
                         double zp, double (&acc)[1]) const {
         const double rv = b[g] - apply_A<double>(c, xm, xp, ym, yp, zm, zp, inv_h2);
@@ -328,12 +322,12 @@ struct OpOuterResid {
     __device__ double* partials() const { return part; }
 };
 
-// Field: phi <- phi - mean (written at own points), E = -grad phi,
-// W_x = (1/2) h^3 sum Ex^2.
+// Field: E = -grad (phi - mean) from the gauge-fixed values, W_x =
+// (1/2) h^3 sum Ex^2.  phi itself is shifted by a separate pass afterwards.
 struct OpField {
     using T = double;
     static constexpr int NACC = 1;
-    double* phi;
+    const double* phi;
     double* ex;
     double* ey;
     double* ez;
@@ -342,11 +336,7 @@ struct OpField {
     double* part;
     __device__ bool active() const { return true; }
     __device__ void prepare() { mean = st->mean; }
-    __device__ double load(size_t g, bool own) const {
-        const double v = phi[g] - mean;
-        if (own) phi[g] = v;
-        return v;
-    }
+    __device__ double load(size_t g, bool) const { return phi[g] - mean; }
     __device__ void out(size_t g, double, double xm, double xp, double ym, double yp, double zm,
                         double zp, double (&acc)[1]) const {
         const double exv = -(xp - xm) * ehalf;
@@ -406,7 +396,7 @@ __global__ __launch_bounds__(kNT) void convert32_kernel(int64_t n3, const double
     }
 }
 
-// x += ||r|| * d (used when the update is not fused into the next residual).
+// x += ||r|| * d: the refinement step's correction, before the next residual.
 __global__ __launch_bounds__(kNT) void update_x_kernel(int64_t n3, double* __restrict__ x,
                                                        const float* __restrict__ d,
                                                        const DevState* st) {
@@ -502,17 +492,32 @@ hipError_t launch_upd32(const SweepGeo& g, const float* p_new, float* d, float* 
     return launch_sweep(op, g, s);
 }
 
-hipError_t launch_outer_resid(const SweepGeo& g, const double* b, double* x, const float* d,
-                              double* r, int fuse_update, double inv_h2, DevState* st,
-                              double* partials, double tol, hipStream_t s) {
-    OpOuterResid op{b, x, d, r, inv_h2, tol, 0.0, fuse_update, st, partials};
+hipError_t launch_outer_resid(const SweepGeo& g, const double* b, const double* x, double* r,
+                              double inv_h2, DevState* st, double* partials, double tol,
+                              hipStream_t s) {
+    OpOuterResid op{b, x, r, inv_h2, tol, st, partials};
     return launch_sweep(op, g, s);
 }
+
+// phi -= st->mean (the gauge fix, after the field sweep has read phi).
+__global__ __launch_bounds__(kNT) void shift_kernel(int64_t n3, double* __restrict__ v,
+                                                    const DevState* st) {
+    const double m = st->mean;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
+        v[i] = v[i] - m;
+}
+
+static int stream_blocks(int64_t n);
 
 hipError_t launch_field(const SweepGeo& g, double* phi, double* ex, double* ey, double* ez,
                         double ehalf, double h3, DevState* st, double* partials, hipStream_t s) {
     OpField op{phi, ex, ey, ez, ehalf, h3, 0.0, st, partials};
-    return launch_sweep(op, g, s);
+    hipError_t e = launch_sweep(op, g, s);
+    if (e != hipSuccess) return e;
+    const int64_t n3 = (int64_t)g.n * g.n * g.n;
+    hipLaunchKernelGGL(shift_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, phi,
+                       (const DevState*)st);
+    return hipGetLastError();
 }
 
 static int stream_blocks(int64_t n) {

@@ -184,7 +184,7 @@ def test_deposit_charge_conservation_dyadic(pic, orc):
     are exact, so total charge is conserved bit for bit."""
     N = 32
     L = 8.0  # h = 1/4
-    p = pic.landau_params(N, 1)
+    p = pic.landau_params(N, 4)
     p.length = L
     p.charge = 1.0
     p.rho_bg = 0.0
@@ -266,7 +266,8 @@ def test_efield_parity(pic, orc):
     E = [torch.empty(N ** 3, dtype=torch.float64, device="cuda") for _ in range(3)]
     wx = ctx.efield(dphi, *E)
     rphi, rex, rey, rez, rwx = orc.efield(N, p.length, phi)
-    assert np.max(np.abs(_host(dphi) - rphi)) <= 1e-15
+    # the mean is summed in a different order: phi agrees to its rounding
+    assert np.max(np.abs(_host(dphi) - rphi)) <= 1e-13 * np.abs(rphi).max()
     for g, r in zip(E, (rex, rey, rez)):
         assert np.max(np.abs(_host(g) - r)) <= 1e-13 * np.abs(r).max()
     assert abs(wx - rwx) <= 1e-12 * rwx
@@ -278,7 +279,7 @@ def test_mixed_precision_reaches_tolerance(pic, orc):
     b = _rhs(orc, N, 8, 6300)
     dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
     info = ctx.poisson(_dev(b), dx)
-    assert info["converged"] and info["outer_iterations"] >= 2
+    assert info["converged"] and info["outer_iterations"] >= 2, info
     got = _host(dx)
     assert orc.residual_norm(N, p.length, b, got) <= p.rtol * np.linalg.norm(b)
     ref, rinfo = orc.pcg(N, p.length, b, np.zeros(N ** 3), 1e-13, 20000)
