@@ -102,8 +102,7 @@ static size_t vec_bytes(int64_t n3, size_t elem) { return ((size_t)n3 * elem + 2
 
 static size_t base_bytes(const pic_params* p) {
     const int64_t n3 = (int64_t)p->n * p->n * p->n;
-    SweepGeo g = make_geo(p->n);
-    int np = (int)g.nb;
+    int np = max_sweep_blocks();
     if (np < 2 * deposit_partials()) np = 2 * deposit_partials();
     size_t b = 0;
     b += 4096;                               // DevState
@@ -401,7 +400,8 @@ int pic_create(const pic_params* params, pic_ctx** out) {
         char* q = (char*)m;
         c->st = (DevState*)q;
         q += 4096;
-        c->npartials = (int)c->geo.nb < 2 * deposit_partials() ? 2 * deposit_partials() : (int)c->geo.nb;
+        c->npartials = max_sweep_blocks() < 2 * deposit_partials() ? 2 * deposit_partials()
+                                                                    : max_sweep_blocks();
         c->partials = (double*)q;
         q += (size_t)4 * c->npartials * sizeof(double);
         q = (char*)(((uintptr_t)q + 255) & ~(uintptr_t)255);

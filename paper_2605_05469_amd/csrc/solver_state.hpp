@@ -49,10 +49,11 @@ struct DevState {
     uint32_t tickets[8];
 };
 
-// Geometry of a z-marching stencil sweep.
+// Geometry of a z-marching stencil sweep: the caller sets n; the launcher
+// fills in the tiling (tiles in x and y, blocks per column in z).
 struct SweepGeo {
-    int32_t n;      // grid points per axis
-    int32_t zc;     // planes per block
+    int32_t n;   // grid points per axis
+    int32_t zc;  // unused (kept for layout)
     uint32_t nbx, nby, nbz, nb;
 };
 
@@ -86,6 +87,7 @@ hipError_t launch_field(const SweepGeo& g, double* phi, double* ex, double* ey, 
                         double ehalf, double h3, DevState* st, double* partials, hipStream_t s);
 hipError_t launch_fill(int64_t n, double* v, double val, hipStream_t s);
 
-int partials_per_sweep(const SweepGeo& g);
+// Upper bound on the workgroups of one sweep (size of the partials array).
+int max_sweep_blocks();
 
 }  // namespace pic

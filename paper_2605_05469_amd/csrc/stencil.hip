@@ -29,29 +29,62 @@
 namespace pic {
 
 constexpr int kNT = 256;
-constexpr int kTY = 16;
+#ifndef PIC_TY
+#define PIC_TY 32
+#endif
+#ifndef PIC_NT
+#define PIC_NT 1
+#endif
+constexpr int kTY = PIC_TY;  // tile rows in y
+
+// Own-point operands (read or written by exactly one workgroup, never staged
+// as a halo) may bypass L2 retention so the halo rows stay cached.
+template <class T>
+__device__ __forceinline__ T ld_own(const T* p) {
+    if constexpr (PIC_NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <class T>
+__device__ __forceinline__ void st_own(T v, T* p) {
+    if constexpr (PIC_NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+constexpr int kMaxSweepBlocks = 8192;
 
 // --------------------------------------------------------------------------
 // Generic sweep.  A sweep never writes the array it stages into LDS:
 // neighbouring workgroups read that array as their halo at any time.
+//
+// LDS holds two planes (z and z+1, each with its halo); the z-1 neighbour of
+// each thread's own points is kept in registers from the previous plane.  The
+// loads for plane z+2 (halo plane) and for the own-point operands of plane z+1
+// are issued one plane ahead, so their latency overlaps the arithmetic and the
+// barriers of the current plane.
+//
 // Op provides:
-//   using T;  static constexpr int NACC;
-//   bool active() const;  void prepare();   // reads device scalars
-//   T load(size_t g, bool own);                      // value placed in LDS
-//   void out(size_t g, T c, T xm, T xp, T ym, T yp, T zm, T zp, double (&acc)[NACC]);
-//   void finish(double (&tot)[NACC]);                // thread 0 of last block
-//   uint32_t* ticket();  double* partials();
+//   using T, In, Own;  static constexpr int NACC;
+//   bool active() const;  void prepare();            // reads device scalars
+//   In  fetch(size_t g) const;                        // loads for a staged value
+//   T   make(const In&, size_t g, bool own) const;    // staged value (may store)
+//   Own pre(size_t g) const;                          // loads at an own point
+//   void out(const Own&, size_t g, T c, T xm, T xp, T ym, T yp, T zm, T zp,
+//            double (&acc)[NACC]) const;
+//   void finish(double (&tot)[NACC]) const;           // thread 0 of last block
+//   uint32_t* ticket() const;  double* partials() const;
 template <class Op, int TX>
 __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
     using T = typename Op::T;
+    using In = typename Op::In;
+    using Own = typename Op::Own;
     constexpr int NACC = Op::NACC;
     constexpr int PX = TX + 2;
     constexpr int PY = kTY + 2;
     constexpr int PLANE = PX * PY;
-    constexpr int RPT = kNT / TX;     // thread rows
-    constexpr int PPT = kTY / RPT;    // points per thread per plane
-    __shared__ T ring[3][PLANE];
-    __shared__ double red[NACC > 0 ? NACC * (kNT / kWave) : 1];
+    constexpr int NE = (PLANE + kNT - 1) / kNT;  // staged entries per thread
+    constexpr int RPT = kNT / TX;                // thread rows
+    constexpr int PPT = kTY / RPT;               // own points per thread per plane
+    __shared__ T buf[2][PLANE];
+    __shared__ double red[NACC * (kNT / kWave)];
     __shared__ int lflag;
 
     Op op = op_in;
@@ -64,66 +97,112 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
     const uint32_t t1 = lb / g.nbx;
     const uint32_t by = t1 % g.nby;
     const uint32_t bz = t1 / g.nby;
-    const int x0 = (int)bx * TX, y0 = (int)by * kTY, z0 = (int)bz * g.zc;
+    // this block's z-range: the columns' planes are split evenly over nbz blocks
+    const int x0 = (int)bx * TX, y0 = (int)by * kTY;
+    const int z0 = (int)(((int64_t)bz * n) / g.nbz);
+    const int zc = (int)((((int64_t)bz + 1) * n) / g.nbz) - z0;
     const size_t nn = (size_t)n * n;
     const int tid = threadIdx.x;
     const int lx = tid % TX, ly0 = tid / TX;
 
-    double acc[NACC > 0 ? NACC : 1];
+    // in-plane offsets of this thread's staged entries (fixed for the block)
+    uint32_t eoff[NE];
+    uint32_t eown = 0;
 #pragma unroll
-    for (int k = 0; k < (NACC > 0 ? NACC : 1); ++k) acc[k] = 0.0;
+    for (int j = 0; j < NE; ++j) {
+        const int e = tid + j * kNT;
+        const int ly = e / PX;
+        const int lxx = e - ly * PX;
+        int gx = x0 + lxx - 1;
+        gx = gx < 0 ? gx + n : (gx >= n ? gx - n : gx);
+        int gy = y0 + ly - 1;
+        gy = gy < 0 ? gy + n : (gy >= n ? gy - n : gy);
+        eoff[j] = (uint32_t)gy * (uint32_t)n + (uint32_t)gx;
+        if (e < PLANE && lxx >= 1 && lxx <= TX && ly >= 1 && ly <= kTY) eown |= 1u << j;
+    }
+    auto zwrap = [n](int z) { return z >= n ? z - n : (z < 0 ? z + n : z); };
+    auto own_index = [&](int z, int k) {
+        return (size_t)z * nn + (size_t)(y0 + ly0 + k * RPT) * n + (size_t)(x0 + lx);
+    };
 
-    auto fill = [&](T* dst, int gz, bool ownz) {
-        const size_t zoff = (size_t)gz * nn;
-        for (int e = tid; e < PLANE; e += kNT) {
-            const int ly = e / PX;
-            const int lxx = e - ly * PX;
-            int gx = x0 + lxx - 1;
-            gx = gx < 0 ? gx + n : (gx >= n ? gx - n : gx);
-            int gy = y0 + ly - 1;
-            gy = gy < 0 ? gy + n : (gy >= n ? gy - n : gy);
-            const bool own = ownz && lxx >= 1 && lxx <= TX && ly >= 1 && ly <= kTY;
-            dst[e] = op.load(zoff + (size_t)gy * n + gx, own);
+    In fin[NE];
+    Own fown[PPT];
+    T zm[PPT];
+    double acc[NACC];
+#pragma unroll
+    for (int k = 0; k < NACC; ++k) acc[k] = 0.0;
+
+    auto fetch_plane = [&](int gz) {
+        const size_t zo = (size_t)gz * nn;
+#pragma unroll
+        for (int j = 0; j < NE; ++j)
+            if (tid + j * kNT < PLANE) fin[j] = op.fetch(zo + eoff[j]);
+    };
+    auto commit_plane = [&](T* dst, int gz, bool ownz) {
+        const size_t zo = (size_t)gz * nn;
+#pragma unroll
+        for (int j = 0; j < NE; ++j) {
+            const int e = tid + j * kNT;
+            if (e < PLANE) dst[e] = op.make(fin[j], zo + eoff[j], ownz && ((eown >> j) & 1u));
         }
     };
 
-    T* sm = ring[0];
-    T* sc = ring[1];
-    T* sp = ring[2];
-    fill(sm, z0 == 0 ? n - 1 : z0 - 1, false);
-    fill(sc, z0, true);
-    for (int i = 0; i < g.zc; ++i) {
-        const int z = z0 + i;
-        fill(sp, z + 1 == n ? 0 : z + 1, i + 1 < g.zc);
-        __syncthreads();
+    // prologue: z-1 values of the own points, planes z0 and z0+1, prefetches
+    {
+        const int zb = zwrap(z0 - 1);
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            const int ly = ly0 + k * RPT;
-            const int e = (ly + 1) * PX + lx + 1;
-            const size_t gi = (size_t)z * nn + (size_t)(y0 + ly) * n + (x0 + lx);
-            op.out(gi, sc[e], sc[e - 1], sc[e + 1], sc[e - PX], sc[e + PX], sm[e], sp[e], acc);
+            const size_t gi = own_index(zb, k);
+            zm[k] = op.make(op.fetch(gi), gi, false);
+        }
+    }
+    fetch_plane(z0);
+    commit_plane(buf[0], z0, true);
+    fetch_plane(zwrap(z0 + 1));
+    commit_plane(buf[1], zwrap(z0 + 1), zc > 1);
+    if (zc >= 2) fetch_plane(zwrap(z0 + 2));
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) fown[k] = op.pre(own_index(z0, k));
+    __syncthreads();
+
+    int cur = 0;
+    for (int i = 0; i < zc; ++i) {
+        const int z = z0 + i;
+        const T* C = buf[cur];
+        const T* Nx = buf[cur ^ 1];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int e = (ly0 + k * RPT + 1) * PX + lx + 1;
+            const T c = C[e];
+            op.out(fown[k], own_index(z, k), c, C[e - 1], C[e + 1], C[e - PX], C[e + PX], zm[k],
+                   Nx[e], acc);
+            zm[k] = c;
+        }
+        if (i + 1 < zc) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) fown[k] = op.pre(own_index(z + 1, k));
         }
         __syncthreads();
-        T* tmp = sm;
-        sm = sc;
-        sc = sp;
-        sp = tmp;
+        if (i + 2 <= zc) commit_plane(buf[cur], zwrap(z + 2), i + 2 < zc);
+        if (i + 3 <= zc) fetch_plane(zwrap(z + 3));
+        __syncthreads();
+        cur ^= 1;
     }
 
-    if constexpr (NACC > 0) {
-        block_sum<kNT, NACC>(acc, red);
-        double* part = op.partials();
-        if (tid == 0) {
+    block_sum<kNT, NACC>(acc, red);
+    double* part = op.partials();
+    if (tid == 0) {
 #pragma unroll
-            for (int k = 0; k < NACC; ++k) part[(size_t)k * g.nb + lb] = acc[k];
-        }
-        if (last_block(op.ticket(), g.nb, &lflag)) {
-            double tot[NACC];
-            sum_partials<kNT, NACC>(part, (int)g.nb, tot, red);
-            if (tid == 0) op.finish(tot);
-        }
+        for (int k = 0; k < NACC; ++k) part[(size_t)k * g.nb + lb] = acc[k];
+    }
+    if (last_block(op.ticket(), g.nb, &lflag)) {
+        double tot[NACC];
+        sum_partials<kNT, NACC>(part, (int)g.nb, tot, red);
+        if (tid == 0) op.finish(tot);
     }
 }
+
+struct Nothing {};
 
 // --------------------------------------------------------------------------
 // The operator at one point, in the oracle's order.
@@ -137,6 +216,8 @@ __device__ __forceinline__ T apply_A(T c, T xm, T xp, T ym, T yp, T zm, T zp, T 
 // ||b|| and the stop threshold); otherwise the check of a candidate.
 struct OpResidual64 {
     using T = double;
+    using In = double;
+    using Own = double;
     static constexpr int NACC = 3;
     const double* b;
     const double* x;
@@ -150,12 +231,13 @@ struct OpResidual64 {
         return init ? true : st->cg.state == CG_CANDIDATE;
     }  // init: 1 = first residual of a solve, 0 = verify a candidate, 2 = report only
     __device__ void prepare() {}
-    __device__ double load(size_t g, bool) const { return x[g]; }
-    __device__ void out(size_t g, double c, double xm, double xp, double ym, double yp, double zm,
-                        double zp, double (&acc)[3]) const {
-        const double bv = b[g];
+    __device__ double fetch(size_t g) const { return x[g]; }
+    __device__ double make(double v, size_t, bool) const { return v; }
+    __device__ double pre(size_t g) const { return ld_own(b + g); }
+    __device__ void out(double bv, size_t g, double c, double xm, double xp, double ym, double yp,
+                        double zm, double zp, double (&acc)[3]) const {
         const double rv = bv - apply_A<double>(c, xm, xp, ym, yp, zm, zp, inv_h2);
-        r[g] = rv;
+        st_own(rv, r + g);
         acc[0] += bv * bv;
         acc[1] += rv * rv;
         acc[2] += rv * (minv * rv);
@@ -203,6 +285,10 @@ struct OpResidual64 {
 template <class V>
 struct OpDir {
     using T = V;
+    struct In {
+        V r, p;
+    };
+    using Own = Nothing;
     static constexpr int NACC = 1;
     const V* r;
     const V* p_old;
@@ -217,13 +303,21 @@ struct OpDir {
         restart = st->cg.restart;
         beta = (V)st->cg.beta;
     }
-    __device__ V load(size_t g, bool own) const {
-        V pn = minv * r[g];
-        if (!restart) pn = pn + beta * p_old[g];
-        if (own) p_new[g] = pn;
+    __device__ In fetch(size_t g) const {
+        In v;
+        v.r = r[g];
+        v.p = restart ? V(0) : p_old[g];
+        return v;
+    }
+    __device__ V make(const In& v, size_t g, bool own) const {
+        V pn = minv * v.r;
+        if (!restart) pn = pn + beta * v.p;
+        if (own) st_own(pn, p_new + g);
         return pn;
     }
-    __device__ void out(size_t, V c, V xm, V xp, V ym, V yp, V zm, V zp, double (&acc)[1]) const {
+    __device__ Nothing pre(size_t) const { return Nothing{}; }
+    __device__ void out(const Nothing&, size_t, V c, V xm, V xp, V ym, V yp, V zm, V zp,
+                        double (&acc)[1]) const {
         const V q = apply_A<V>(c, xm, xp, ym, yp, zm, zp, inv_h2);
         acc[0] += (double)c * (double)q;
     }
@@ -246,6 +340,10 @@ struct OpDir {
 template <class V>
 struct OpUpd {
     using T = V;
+    using In = V;
+    struct Own {
+        V x, r;
+    };
     static constexpr int NACC = 2;
     const V* p;
     V* x;
@@ -256,13 +354,21 @@ struct OpUpd {
     V alpha;
     __device__ bool active() const { return st->cg.state == CG_RUNNING; }
     __device__ void prepare() { alpha = (V)st->cg.alpha; }
-    __device__ V load(size_t g, bool) const { return p[g]; }
-    __device__ void out(size_t g, V c, V xm, V xp, V ym, V yp, V zm, V zp, double (&acc)[2]) const {
+    __device__ V fetch(size_t g) const { return p[g]; }
+    __device__ V make(V v, size_t, bool) const { return v; }
+    __device__ Own pre(size_t g) const {
+        Own o;
+        o.x = ld_own(x + g);
+        o.r = ld_own(r + g);
+        return o;
+    }
+    __device__ void out(const Own& o, size_t g, V c, V xm, V xp, V ym, V yp, V zm, V zp,
+                        double (&acc)[2]) const {
         const V q = apply_A<V>(c, xm, xp, ym, yp, zm, zp, inv_h2);
-        const V xv = x[g] + alpha * c;
-        const V rv = r[g] - alpha * q;
-        x[g] = xv;
-        r[g] = rv;
+        const V xv = o.x + alpha * c;
+        const V rv = o.r - alpha * q;
+        st_own(xv, x + g);
+        st_own(rv, r + g);
         acc[0] += (double)rv * (double)rv;
         acc[1] += (double)rv * (double)(minv * rv);
     }
@@ -293,6 +399,8 @@ struct OpUpd {
 // read that array as their halo.)
 struct OpOuterResid {
     using T = double;
+    using In = double;
+    using Own = double;
     static constexpr int NACC = 1;
     const double* b;
     const double* x;
@@ -303,11 +411,13 @@ struct OpOuterResid {
     double* part;
     __device__ bool active() const { return st->outer_state == CG_RUNNING; }
     __device__ void prepare() {}
-    __device__ double load(size_t g, bool) const { return x[g]; }
-    __device__ void out(size_t g, double c, double xm, double xp, double ym, double yp, double zm,
-                        double zp, double (&acc)[1]) const {
-        const double rv = b[g] - apply_A<double>(c, xm, xp, ym, yp, zm, zp, inv_h2);
-        r[g] = rv;
+    __device__ double fetch(size_t g) const { return x[g]; }
+    __device__ double make(double v, size_t, bool) const { return v; }
+    __device__ double pre(size_t g) const { return ld_own(b + g); }
+    __device__ void out(double bv, size_t g, double c, double xm, double xp, double ym, double yp,
+                        double zm, double zp, double (&acc)[1]) const {
+        const double rv = bv - apply_A<double>(c, xm, xp, ym, yp, zm, zp, inv_h2);
+        st_own(rv, r + g);
         acc[0] += rv * rv;
     }
     __device__ void finish(double (&t)[1]) const {
@@ -326,6 +436,8 @@ struct OpOuterResid {
 // (1/2) h^3 sum Ex^2.  phi itself is shifted by a separate pass afterwards.
 struct OpField {
     using T = double;
+    using In = double;
+    using Own = Nothing;
     static constexpr int NACC = 1;
     const double* phi;
     double* ex;
@@ -336,13 +448,15 @@ struct OpField {
     double* part;
     __device__ bool active() const { return true; }
     __device__ void prepare() { mean = st->mean; }
-    __device__ double load(size_t g, bool) const { return phi[g] - mean; }
-    __device__ void out(size_t g, double, double xm, double xp, double ym, double yp, double zm,
-                        double zp, double (&acc)[1]) const {
+    __device__ double fetch(size_t g) const { return phi[g]; }
+    __device__ double make(double v, size_t, bool) const { return v - mean; }
+    __device__ Nothing pre(size_t) const { return Nothing{}; }
+    __device__ void out(const Nothing&, size_t g, double, double xm, double xp, double ym,
+                        double yp, double zm, double zp, double (&acc)[1]) const {
         const double exv = -(xp - xm) * ehalf;
-        ex[g] = exv;
-        ey[g] = -(yp - ym) * ehalf;
-        ez[g] = -(zp - zm) * ehalf;
+        st_own(exv, ex + g);
+        st_own(-(yp - ym) * ehalf, ey + g);
+        st_own(-(zp - zm) * ehalf, ez + g);
         acc[0] += exv * exv;
     }
     __device__ void finish(double (&t)[1]) const { st->wx = 0.5 * t[0] * h3; }
@@ -438,27 +552,52 @@ __global__ __launch_bounds__(kNT) void fill_kernel(int64_t n, double* __restrict
 SweepGeo make_geo(int n) {
     SweepGeo g;
     g.n = n;
-    const int tx = (n % 64 == 0) ? 64 : 32;
-    g.nbx = (uint32_t)(n / tx);
-    g.nby = (uint32_t)(n / kTY);
-    // choose the z-chunk so that there are enough workgroups to fill 256 CUs
-    int zc = n;
-    while (zc > 4 && (uint64_t)g.nbx * g.nby * (uint64_t)(n / zc) < 2048 && (zc % 2) == 0) zc /= 2;
-    g.zc = zc;
-    g.nbz = (uint32_t)(n / zc);
-    g.nb = g.nbx * g.nby * g.nbz;
+    g.zc = 0;
+    g.nbx = g.nby = g.nbz = g.nb = 0;
     return g;
 }
 
-int partials_per_sweep(const SweepGeo& g) { return (int)g.nb; }
+int max_sweep_blocks() { return kMaxSweepBlocks; }
+
+// Launch one wave of resident workgroups: every (x, y) tile column gets the
+// same number of blocks (nbz), each marching an equal share of the z planes,
+// so all blocks finish together and the z-halo overhead is 2 planes per share.
+template <class Op, int TX>
+static hipError_t launch_sweep_tx(const Op& op, const SweepGeo& gin, hipStream_t s) {
+    static int occ = 0, cus = 0;
+    if (occ == 0) {
+        int o = 0, c = 0, dev = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sweep_kernel<Op, TX>, kNT, 0) !=
+                hipSuccess || o < 1)
+            o = 1;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            c < 1)
+            c = 1;
+        cus = c;
+        occ = o;
+    }
+    const int n = gin.n;
+    SweepGeo g = gin;
+    g.nbx = (uint32_t)(n / TX);
+    g.nby = (uint32_t)(n / kTY);
+    const uint32_t tiles = g.nbx * g.nby;
+    uint32_t nbz = (uint32_t)(occ * cus) / tiles;
+    const uint32_t cap = (uint32_t)kMaxSweepBlocks / tiles;
+    if (nbz > cap) nbz = cap;
+    if (nbz > (uint32_t)(n / 2)) nbz = (uint32_t)(n / 2);
+    if (nbz < 1) nbz = 1;
+    g.nbz = nbz;
+    g.nb = tiles * nbz;
+    g.zc = 0;
+    hipLaunchKernelGGL((sweep_kernel<Op, TX>), dim3(g.nb), dim3(kNT), 0, s, op, g);
+    return hipGetLastError();
+}
 
 template <class Op>
 static hipError_t launch_sweep(const Op& op, const SweepGeo& g, hipStream_t s) {
-    if (g.n % 64 == 0)
-        hipLaunchKernelGGL((sweep_kernel<Op, 64>), dim3(g.nb), dim3(kNT), 0, s, op, g);
-    else
-        hipLaunchKernelGGL((sweep_kernel<Op, 32>), dim3(g.nb), dim3(kNT), 0, s, op, g);
-    return hipGetLastError();
+    if (g.n % 64 == 0) return launch_sweep_tx<Op, 64>(op, g, s);
+    return launch_sweep_tx<Op, 32>(op, g, s);
 }
 
 hipError_t launch_residual64(const SweepGeo& g, const double* b, const double* x, double* r,
