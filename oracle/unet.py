@@ -3,89 +3,83 @@
 Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
 import this module.  The learned warm start / preconditioner is not part of
 the paper: it is this project's extension of the PCG solve of Sec. 3.2.  What
-is computed here is the plain definition of each layer:
+is computed here is the plain definition of each piece:
 
   conv3   y[o,p] = b[o] + sum_c sum_{d in {-1,0,1}^3} W[o,c,d] x[c,(p+d) mod n]
           (cross-correlation with periodic padding)
-  down    y[o,P] = b[o] + sum_c sum_{d in {0,1}^3} W[o,c,d] x[c,2P+d]
-          (2x2x2 stride-2 convolution)
-  up      y[o,2P+d] = b[o] + sum_c W[c,o,d] x[c,P]
-          (2x2x2 stride-2 transposed convolution; W stored [in, out, ...])
+  pool    y[c,P] = (1/8) sum_{d in {0,1}^3} x[c,2P+d]     (2x2x2 average)
+  up      y[c,2P+d] = x[c,P]                             (nearest, x2 per axis)
   relu    max(0, .)
 
-and their adjoints (backward data / backward weight).  BF16 storage of
-weights and activations is emulated by rounding FP64 -> FP32 -> BF16
-(round-to-nearest-even at each step); all arithmetic is FP64 on the rounded
-operands.  Array layout: [C, z, y, x].
+and their adjoints.  BF16 storage of weights, activations and of the
+gradients at each convolution's output is emulated by rounding FP64 -> FP32
+-> BF16 (round-to-nearest-even at each step); all arithmetic is FP64 on the
+rounded operands.  Array layout: [C, z, y, x].
 
-Network (three levels, 16-32-64 channels, 3^3 kernels, periodic padding):
-  e1a = relu(conv3(x, 1->c1));  e1b = relu(conv3(e1a, c1->c1))       level 1
-  d1  = relu(down(e1b, c1->c2)); e2a = relu(conv3(d1, c2->c2))        level 2
-  d2  = relu(down(e2a, c2->c3)); b3a = relu(conv3(d2, c3->c3));
-  b3b = relu(conv3(b3a, c3->c3))                                      level 3
-  u2  = relu(up(b3b, c3->c2) + e2a); e2c = relu(conv3(u2, c2->c2))    level 2
-  u1  = relu(up(e2c, c2->c1) + e1b); e1c = relu(conv3(u1, c1->c1))    level 1
-  out = conv3(e1c, c1->1)                      (linear, not rounded to BF16)
+Network: three levels with 16-32-64 channels, 3^3 periodic convolutions,
+average pooling down and nearest up-sampling, additive skips:
+  e1a = relu(conv3(x, 1->c1));       e1b = relu(conv3(e1a, c1->c1))   level 1
+  p1  = pool(e1b)
+  e2a = relu(conv3(p1, c1->c2));     e2b = relu(conv3(e2a, c2->c2))   level 2
+  p2  = pool(e2b)
+  b3a = relu(conv3(p2, c2->c3));     b3b = relu(conv3(b3a, c3->c2))   level 3
+  u2  = up(b3b)
+  d2a = relu(conv3(u2, c2->c2) + e2b); d2b = relu(conv3(d2a, c2->c1)) level 2
+  u1  = up(d2b)
+  d1a = relu(conv3(u1, c1->c1) + e1b)                                  level 1
+  out = conv3(d1a, c1->1)                      (linear, not rounded to BF16)
 """
 from __future__ import annotations
 
 import numpy as np
 
-# (name, kind, cin, cout) with channel symbols resolved by layer_specs()
+# (name, cin, cout); every weighted layer is a 3^3 periodic convolution
 _ARCH = [
-    ("e1a", "conv3", "1", "c1"),
-    ("e1b", "conv3", "c1", "c1"),
-    ("d1", "down", "c1", "c2"),
-    ("e2a", "conv3", "c2", "c2"),
-    ("d2", "down", "c2", "c3"),
-    ("b3a", "conv3", "c3", "c3"),
-    ("b3b", "conv3", "c3", "c3"),
-    ("u2", "up", "c3", "c2"),
-    ("e2c", "conv3", "c2", "c2"),
-    ("u1", "up", "c2", "c1"),
-    ("e1c", "conv3", "c1", "c1"),
-    ("out", "conv3", "c1", "1"),
+    ("e1a", "1", "c1"),
+    ("e1b", "c1", "c1"),
+    ("e2a", "c1", "c2"),
+    ("e2b", "c2", "c2"),
+    ("b3a", "c2", "c3"),
+    ("b3b", "c3", "c2"),
+    ("d2a", "c2", "c2"),
+    ("d2b", "c2", "c1"),
+    ("d1a", "c1", "c1"),
+    ("out", "c1", "1"),
 ]
 
 
 def layer_specs(c1=16, c2=32, c3=64):
     ch = {"1": 1, "c1": c1, "c2": c2, "c3": c3}
-    return [(n, k, ch[a], ch[b]) for (n, k, a, b) in _ARCH]
+    return [(n, ch[a], ch[b]) for (n, a, b) in _ARCH]
 
 
-def weight_shape(kind, cin, cout):
-    if kind == "conv3":
-        return (cout, cin, 3, 3, 3)
-    if kind == "down":
-        return (cout, cin, 2, 2, 2)
-    return (cin, cout, 2, 2, 2)  # up
+def weight_shape(cin, cout):
+    return (cout, cin, 3, 3, 3)
 
 
 def init_params(seed=0, c1=16, c2=32, c3=64):
     """He-normal weights, zero biases (FP64)."""
     rng = np.random.default_rng(seed)
     params = {}
-    for name, kind, cin, cout in layer_specs(c1, c2, c3):
-        shp = weight_shape(kind, cin, cout)
-        fan_in = cin * (27 if kind == "conv3" else 8 if kind == "down" else 1)
-        params[name + ".W"] = rng.standard_normal(shp) * np.sqrt(2.0 / fan_in)
+    for name, cin, cout in layer_specs(c1, c2, c3):
+        params[name + ".W"] = rng.standard_normal(weight_shape(cin, cout)) * np.sqrt(2.0 / (27 * cin))
         params[name + ".b"] = np.zeros(cout)
     return params
 
 
 def flatten(params, specs):
-    """Canonical flat order: for each layer, W (shape of weight_shape) then b."""
+    """Canonical flat order: for each layer, W [cout][cin][3][3][3] then b [cout]."""
     return np.concatenate([np.concatenate([params[n + ".W"].ravel(), params[n + ".b"].ravel()])
-                           for (n, _, _, _) in specs])
+                           for (n, _, _) in specs])
 
 
 def unflatten(flat, specs):
     params, o = {}, 0
-    for name, kind, cin, cout in specs:
-        shp = weight_shape(kind, cin, cout)
-        n = int(np.prod(shp))
-        params[name + ".W"] = np.asarray(flat[o:o + n], dtype=np.float64).reshape(shp)
-        o += n
+    for name, cin, cout in specs:
+        shp = weight_shape(cin, cout)
+        k = int(np.prod(shp))
+        params[name + ".W"] = np.asarray(flat[o:o + k], dtype=np.float64).reshape(shp)
+        o += k
         params[name + ".b"] = np.asarray(flat[o:o + cout], dtype=np.float64)
         o += cout
     return params
@@ -145,99 +139,83 @@ def _blocks(x):
     return x.reshape(C, m, 2, m, 2, m, 2).transpose(0, 2, 4, 6, 1, 3, 5)
 
 
-def _unblocks(B):
-    C, m = B.shape[0], B.shape[4]
-    return B.transpose(0, 4, 1, 5, 2, 6, 3).reshape(C, 2 * m, 2 * m, 2 * m)
+def pool_fwd(x):
+    return _blocks(x).mean(axis=(1, 2, 3))
 
 
-def down_fwd(x, W, b):
-    return np.tensordot(W, _blocks(x), axes=([1, 2, 3, 4], [0, 1, 2, 3])) + b[:, None, None, None]
+def pool_bwd(g):
+    return up_fwd(g) / 8.0
 
 
-def down_bwd_data(dy, W):
-    return _unblocks(np.tensordot(W, dy, axes=(0, 0)))
+def up_fwd(x):
+    return np.repeat(np.repeat(np.repeat(x, 2, axis=1), 2, axis=2), 2, axis=3)
 
 
-def down_bwd_weight(x, dy):
-    dW = np.tensordot(dy, _blocks(x), axes=([1, 2, 3], [4, 5, 6]))
-    return dW, dy.sum(axis=(1, 2, 3))
-
-
-def up_fwd(x, W, b):
-    # W[c, o, a, b, e]: Y[o, a, b, e, P] = sum_c W[c,o,a,b,e] x[c,P]
-    return _unblocks(np.tensordot(W, x, axes=(0, 0))) + b[:, None, None, None]
-
-
-def up_bwd_data(dy, W):
-    return np.tensordot(W, _blocks(dy), axes=([1, 2, 3, 4], [0, 1, 2, 3]))
-
-
-def up_bwd_weight(x, dy):
-    dW = np.tensordot(x, _blocks(dy), axes=([1, 2, 3], [4, 5, 6]))
-    return dW, dy.sum(axis=(1, 2, 3))
-
-
-_FWD = {"conv3": conv3_fwd, "down": down_fwd, "up": up_fwd}
-_BWD_DATA = {"conv3": conv3_bwd_data, "down": down_bwd_data, "up": up_bwd_data}
-_BWD_W = {"conv3": conv3_bwd_weight, "down": down_bwd_weight, "up": up_bwd_weight}
-
-_SKIP = {"u2": "e2a", "u1": "e1b"}
+def up_bwd(g):
+    return _blocks(g).sum(axis=(1, 2, 3))
 
 
 # ------------------------------------------------------------- network ---
 
+def _ident(a):
+    return np.asarray(a, dtype=np.float64)
+
+
 def forward(params, x, specs, round_bf16=True):
-    """x: [n, n, n] input.  Returns (out [n,n,n], cache of layer inputs/outputs)."""
-    rnd = bf16 if round_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
-    a = rnd(np.asarray(x, dtype=np.float64)[None])
-    acts = {"in": a}
-    cur = a
-    for name, kind, cin, cout in specs:
-        W = rnd(params[name + ".W"])
-        y = _FWD[kind](cur, W, params[name + ".b"])
-        if name in _SKIP:
-            y = y + acts[_SKIP[name]]
-        if name == "out":
-            acts[name] = y
-            cur = y
-            break
-        y = rnd(np.maximum(y, 0.0))
-        acts[name] = y
-        cur = y
-    return cur[0], acts
+    """x: [n, n, n] input.  Returns (out [n,n,n], activations)."""
+    R = bf16 if round_bf16 else _ident
+    A = {"in": R(np.asarray(x, dtype=np.float64)[None])}
+
+    def conv(name, inp, skip=None, relu=True):
+        y = conv3_fwd(inp, R(params[name + ".W"]), params[name + ".b"])
+        if skip is not None:
+            y = y + skip
+        return R(np.maximum(y, 0.0)) if relu else y
+
+    A["e1a"] = conv("e1a", A["in"])
+    A["e1b"] = conv("e1b", A["e1a"])
+    A["p1"] = R(pool_fwd(A["e1b"]))
+    A["e2a"] = conv("e2a", A["p1"])
+    A["e2b"] = conv("e2b", A["e2a"])
+    A["p2"] = R(pool_fwd(A["e2b"]))
+    A["b3a"] = conv("b3a", A["p2"])
+    A["b3b"] = conv("b3b", A["b3a"])
+    A["u2"] = up_fwd(A["b3b"])
+    A["d2a"] = conv("d2a", A["u2"], skip=A["e2b"])
+    A["d2b"] = conv("d2b", A["d2a"])
+    A["u1"] = up_fwd(A["d2b"])
+    A["d1a"] = conv("d1a", A["u1"], skip=A["e1b"])
+    A["out"] = conv("out", A["d1a"], relu=False)
+    return A["out"][0], A
 
 
-def backward(params, acts, dout, specs, round_bf16=True):
-    """Gradients of sum(out * dout) w.r.t. every parameter (and the input).
-    Gradients flowing between layers are rounded to BF16 like activations."""
-    rnd = bf16 if round_bf16 else (lambda a: np.asarray(a, dtype=np.float64))
-    names = [s[0] for s in specs]
-    inputs = {}
-    prev = "in"
-    for name in names:
-        inputs[name] = prev
-        prev = name
+def backward(params, A, dout, specs, round_bf16=True):
+    """Gradients of sum(out * dout) w.r.t. every parameter and the input.
+    Each convolution's output gradient (after the ReLU mask) is rounded to
+    BF16, as the GPU stores it; all other gradients stay unrounded."""
+    R = bf16 if round_bf16 else _ident
     grads = {}
-    g_act = {n: None for n in names}
-    g_act["in"] = None
-    g = rnd(np.asarray(dout, dtype=np.float64)[None])
-    for idx in range(len(specs) - 1, -1, -1):
-        name, kind, cin, cout = specs[idx]
-        if name != "out":
-            g = g if g_act[name] is None else g_act[name]
-            g = rnd(g * (acts[name] > 0.0))
-        if name in _SKIP:
-            s = _SKIP[name]
-            g_act[s] = g if g_act[s] is None else g_act[s] + g
-        W = rnd(params[name + ".W"])
-        x_in = acts[inputs[name]]
-        dW, db = _BWD_W[kind](x_in, g)
+
+    def back(name, g_pre, x_in):
+        g_pre = R(g_pre)
+        dW, db = conv3_bwd_weight(x_in, g_pre)
         grads[name + ".W"], grads[name + ".b"] = dW, db
-        gx = _BWD_DATA[kind](g, W)
-        src = inputs[name]
-        g_act[src] = gx if g_act[src] is None else g_act[src] + gx
-        g = g_act[src]
-    return grads, g_act["in"][0]
+        return conv3_bwd_data(g_pre, R(params[name + ".W"])), g_pre
+
+    def mask(name):
+        return A[name] > 0.0
+
+    g, _ = back("out", np.asarray(dout, dtype=np.float64)[None], A["d1a"])
+    g_u1, skip1 = back("d1a", g * mask("d1a"), A["u1"])
+    g, _ = back("d2b", up_bwd(g_u1) * mask("d2b"), A["d2a"])
+    g_u2, skip2 = back("d2a", g * mask("d2a"), A["u2"])
+    g, _ = back("b3b", up_bwd(g_u2) * mask("b3b"), A["b3a"])
+    g_p2, _ = back("b3a", g * mask("b3a"), A["p2"])
+    g, _ = back("e2b", (pool_bwd(g_p2) + skip2) * mask("e2b"), A["e2a"])
+    g_p1, _ = back("e2a", g * mask("e2a"), A["p1"])
+    g, _ = back("e1b", (pool_bwd(g_p1) + skip1) * mask("e1b"), A["e1a"])
+    g_in, _ = back("e1a", g * mask("e1a"), A["in"])
+    return grads, g_in[0]
 
 
 # --------------------------------------------------------- loss, Adam ---

@@ -32,41 +32,31 @@ def test_conv3_matches_torch_circular():
     assert np.allclose(unet.conv3_fwd(x, W, b), ref, rtol=1e-12, atol=1e-12)
 
 
-def test_down_up_match_torch():
+def test_pool_up_match_torch():
     rng = np.random.default_rng(2)
     x = rng.standard_normal((3, 8, 8, 8))
-    Wd = rng.standard_normal((5, 3, 2, 2, 2))
-    b = rng.standard_normal(5)
-    ref = F.conv3d(_t(x)[None], _t(Wd), _t(b), stride=2)[0].numpy()
-    assert np.allclose(unet.down_fwd(x, Wd, b), ref, rtol=1e-12, atol=1e-12)
+    ref = F.avg_pool3d(_t(x)[None], 2)[0].numpy()
+    assert np.allclose(unet.pool_fwd(x), ref, rtol=1e-13, atol=1e-14)
     xc = rng.standard_normal((5, 4, 4, 4))
-    Wu = rng.standard_normal((5, 3, 2, 2, 2))
-    bu = rng.standard_normal(3)
-    ref = F.conv_transpose3d(_t(xc)[None], _t(Wu), _t(bu), stride=2)[0].numpy()
-    assert np.allclose(unet.up_fwd(xc, Wu, bu), ref, rtol=1e-12, atol=1e-12)
+    ref = F.interpolate(_t(xc)[None], scale_factor=2, mode="nearest")[0].numpy()
+    assert np.array_equal(unet.up_fwd(xc), ref)
 
 
-@pytest.mark.parametrize("kind", ["conv3", "down", "up"])
-def test_adjoint_identities(kind):
+def test_adjoint_identities():
     rng = np.random.default_rng(3)
     ci, co = 3, 4
-    n_in = 8
-    W = rng.standard_normal(unet.weight_shape(kind, ci, co))
-    x = rng.standard_normal((ci, n_in, n_in, n_in))
-    zero = np.zeros(co)
-    fwd = {"conv3": unet.conv3_fwd, "down": unet.down_fwd, "up": unet.up_fwd}[kind]
-    if kind == "up":
-        x = rng.standard_normal((ci, 4, 4, 4))
-    y = fwd(x, W, zero)
+    W = rng.standard_normal(unet.weight_shape(ci, co))
+    x = rng.standard_normal((ci, 8, 8, 8))
+    y = unet.conv3_fwd(x, W, np.zeros(co))
     dy = rng.standard_normal(y.shape)
-    bd = {"conv3": unet.conv3_bwd_data, "down": unet.down_bwd_data, "up": unet.up_bwd_data}[kind]
-    bw = {"conv3": unet.conv3_bwd_weight, "down": unet.down_bwd_weight,
-          "up": unet.up_bwd_weight}[kind]
     lhs = np.sum(y * dy)
-    assert np.isclose(lhs, np.sum(x * bd(dy, W)), rtol=1e-12)
-    dW, db = bw(x, dy)
+    assert np.isclose(lhs, np.sum(x * unet.conv3_bwd_data(dy, W)), rtol=1e-12)
+    dW, db = unet.conv3_bwd_weight(x, dy)
     assert np.isclose(lhs, np.sum(W * dW), rtol=1e-12)
     assert np.allclose(db, dy.sum(axis=(1, 2, 3)))
+    g = rng.standard_normal((ci, 4, 4, 4))
+    assert np.isclose(np.sum(unet.pool_fwd(x) * g), np.sum(x * unet.pool_bwd(g)), rtol=1e-12)
+    assert np.isclose(np.sum(unet.up_fwd(g) * x), np.sum(g * unet.up_bwd(x)), rtol=1e-12)
 
 
 def test_network_gradient_finite_differences():
@@ -85,7 +75,7 @@ def test_network_gradient_finite_differences():
         return np.sum(unet.forward(pp, x, specs, round_bf16=False)[0] * dout)
 
     eps = 1e-6
-    for name in ("e1a.W", "d1.W", "b3a.W", "u2.W", "u1.b", "out.W", "e2c.b", "d2.W"):
+    for name in ("e1a.W", "e2a.W", "b3a.W", "b3b.W", "d2a.b", "out.W", "d2b.b", "d1a.W", "e1b.b"):
         flat = p[name].ravel()
         for j in rng.choice(flat.size, size=min(3, flat.size), replace=False):
             pp = {k: v.copy() for k, v in p.items()}
@@ -140,5 +130,5 @@ def test_flatten_roundtrip_and_sizes():
     flat = unet.flatten(p, specs)
     q = unet.unflatten(flat, specs)
     assert all(np.array_equal(p[k], q[k]) for k in p)
-    n = sum(int(np.prod(unet.weight_shape(k, a, b))) + b for (_, k, a, b) in specs)
+    n = sum(int(np.prod(unet.weight_shape(a, b))) + b for (_, a, b) in specs)
     assert flat.size == n
