@@ -33,6 +33,10 @@ PEAK_HBM_GBS = 8000.0
 # direction sweep reads r, p_old and writes p_new; update sweep reads p, x, r
 # and writes x, r.  (FP32 inner sweeps of the mixed form: half.)
 SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 40)}
+# HBM bytes per launch of the FP64 update sweep at 512^3, from rocprofv3
+# FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
+# (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
+UPDATE_SWEEP_TRAFFIC = {(512, "pcg_fp64"): 5.608e9}
 
 
 def log(*a):
@@ -185,7 +189,7 @@ def main():
                                          "bytes_per_point": bupd, "gbs": gbs_upd}},
         "roofline": {"bound": "hbm", "kernel": "pcg_update_sweep", "achieved": gbs_upd,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs_upd / PEAK_HBM_GBS,
-                     "traffic": None},
+                     "traffic": UPDATE_SWEEP_TRAFFIC.get((N, args.solver))},
     }
     if not args.no_cpu_baseline:
         try:

@@ -72,7 +72,7 @@ typedef struct pic_params {
     int64_t max_inner;    /* mixed: inner iteration cap per refinement step */
     int64_t max_outer;    /* mixed: refinement step cap                     */
     int32_t fcg_window;   /* learned: stall window (iterations)             */
-    int32_t reserved;
+    int32_t reserved;     /* bit 0 set: learned form without network warm start */
 } pic_params;
 
 /* Host-side result of one Poisson solve. */
@@ -204,6 +204,75 @@ int pic_step(pic_ctx *ctx, pic_particles *parts, pic_fields *fields,
  * 1 = update kernel.  Host out.                                            */
 int pic_set_kernel_timing(pic_ctx *ctx, int32_t enable);
 int pic_kernel_time(pic_ctx *ctx, int32_t kernel_id, double *avg_ms, int64_t *count);
+
+/* ---- learned warm start / preconditioner -------------------------------
+ * Not in the paper: this library's extension of the PCG solve of Sec. 3.2.
+ * A three-level 3-D convolutional U-Net (channels 16-32-64, 3^3 periodic
+ * convolutions, 2x2x2 average pooling, nearest up-sampling, additive skips;
+ * BF16 weights and activations, FP32 accumulation on the matrix cores) maps a
+ * residual r to z = s * NN(h^2 r / s) - mean(.), s = rms(h^2 r), an
+ * approximation of A^{-1} r.  PIC_SOLVER_FCG_LEARNED uses it as warm start
+ * (kept only if it lowers ||b - A phi||) and as the preconditioner of
+ * flexible PCG, falling back to Jacobi-PCG when the flexible iteration stalls.
+ * Parameters: FP32, canonical order per layer (e1a 1->16, e1b 16->16,
+ * e2a 16->32, e2b 32->32, b3a 32->64, b3b 64->32, d2a 32->32, d2b 32->16,
+ * d1a 16->16, out 16->1): weights [cout][cin][3][3][3] (taps dz, dy, dx in
+ * -1..1, dx fastest) followed by the bias [cout].                          */
+
+/* Number of FP32 parameters of the network. */
+int64_t pic_unet_param_count(void);
+/* Load parameters (device, FP32, canonical order) into the context; allocates
+ * the context's network buffers on first use (not per call afterwards).     */
+int pic_set_unet(pic_ctx *ctx, const float *params, void *stream);
+/* z = M(r) on the context's grid (device FP64 arrays of N^3). */
+int pic_unet_precondition(pic_ctx *ctx, const double *r, double *z, void *stream);
+
+/* A standalone network on an n^3 grid (n a multiple of 16), for training and
+ * for single-network use.  training != 0 adds gradient and Adam buffers.    */
+typedef struct pic_net pic_net;
+int pic_net_create(int32_t n, int32_t training, pic_net **out);
+int pic_net_destroy(pic_net *net);
+int pic_net_set_params(pic_net *net, const float *params, void *stream);
+int pic_net_get_params(pic_net *net, float *params, void *stream);
+/* out = NN(x): x, out device FP32 n^3 (x is rounded to BF16 on entry). */
+int pic_net_forward(pic_net *net, const float *x, float *out, void *stream);
+/* grads (device FP32, canonical order) of sum(out * dout) at the last
+ * forward's input; dout is rounded to BF16 like every convolution output's
+ * gradient.  Requires training != 0.                                        */
+int pic_net_backward(pic_net *net, const float *dout, float *grads, void *stream);
+/* One Adam step (beta 0.9/0.999, eps 1e-8, FP32 master weights) on
+ *   L = ||NN(rhs) - target||^2/||target||^2 + lam ||A1 NN(rhs) - rhs||^2/||rhs||^2
+ * (A1: unit-spacing periodic 7-point operator); rhs, target device FP32 n^3.
+ * loss (host out, nullable) receives L before the step.                    */
+int pic_net_train_step(pic_net *net, const float *rhs, const float *target, double lam,
+                       double lr, double *loss, void *stream);
+/* z = s NN(h^2 r / s) - mean on the network's grid (r, z device FP64). */
+int pic_net_precondition(pic_net *net, const double *r, double h, double *z, void *stream);
+
+/* ---- single-layer primitives (3^3 periodic convolution, channels-last) ---
+ * x, y, gy: BF16 bit patterns (uint16_t), [z][y][x][C]; gx FP32; weights FP32
+ * [co][ci][27] + bias [co].  ci, co in {16, 32, 64} pairs used by the network:
+ * (16,16) (16,32) (32,32) (32,64) (64,32) (32,16).                         */
+size_t pic_conv3d_frag_elems(int32_t ci, int32_t co);
+/* Pack BF16 MFMA fragments: forward (frag_elems(ci, co)) and backward-data
+ * (frag_elems(co, ci)) layouts.                                             */
+int pic_conv3d_pack(int32_t ci, int32_t co, const float *w, uint16_t *frag_fwd,
+                    uint16_t *frag_bwd, void *stream);
+/* y = relu?(conv(x) + bias (+ skip)) as BF16. */
+int pic_conv3d_fwd(int32_t n, int32_t ci, int32_t co, const uint16_t *x, const uint16_t *frag_fwd,
+                   const float *bias, const uint16_t *skip, int32_t relu, uint16_t *y,
+                   void *stream);
+/* gx (+)= conv^T(gy) in FP32. */
+int pic_conv3d_bwd_data(int32_t n, int32_t ci, int32_t co, const uint16_t *gy,
+                        const uint16_t *frag_bwd, float *gx, int32_t accumulate, void *stream);
+/* grad[co][ci][27] + grad_bias[co] = sum over points (FP32; scratch of
+ * pic_conv3d_wgrad_scratch_elems floats).                                   */
+size_t pic_conv3d_wgrad_scratch_elems(int32_t n, int32_t ci, int32_t co);
+int pic_conv3d_bwd_weight(int32_t n, int32_t ci, int32_t co, const uint16_t *x, const uint16_t *gy,
+                          float *scratch, float *grad, void *stream);
+/* Adam (Kingma & Ba 2015) on len FP32 parameters, bias-corrected, step >= 1. */
+int pic_adam_step(int64_t len, float *theta, float *m, float *v, const float *g, double lr,
+                  double beta1, double beta2, double eps, int32_t step, void *stream);
 
 #ifdef __cplusplus
 }

@@ -80,7 +80,12 @@ _lib = None
 EXPORTS = ["pic_create", "pic_destroy", "pic_workspace_bytes", "pic_last_error",
            "pic_set_solver", "pic_abi_version", "pic_cell_keys", "pic_sort_cells",
            "pic_deposit_cic", "pic_poisson_pcg", "pic_gather_push", "pic_half_kick",
-           "pic_efield", "pic_init", "pic_step", "pic_set_kernel_timing", "pic_kernel_time"]
+           "pic_efield", "pic_init", "pic_step", "pic_set_kernel_timing", "pic_kernel_time",
+           "pic_unet_param_count", "pic_set_unet", "pic_unet_precondition", "pic_net_create",
+           "pic_net_destroy", "pic_net_set_params", "pic_net_get_params", "pic_net_forward",
+           "pic_net_backward", "pic_net_train_step", "pic_net_precondition",
+           "pic_conv3d_frag_elems", "pic_conv3d_pack", "pic_conv3d_fwd", "pic_conv3d_bwd_data",
+           "pic_conv3d_wgrad_scratch_elems", "pic_conv3d_bwd_weight", "pic_adam_step"]
 
 
 def lib():
@@ -113,6 +118,26 @@ def lib():
     L.pic_step.argtypes = L.pic_init.argtypes
     L.pic_set_kernel_timing.argtypes = [vp, i32]
     L.pic_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    L.pic_unet_param_count.restype = i64
+    L.pic_set_unet.argtypes = [vp, vp, vp]
+    L.pic_unet_precondition.argtypes = [vp, vp, vp, vp]
+    L.pic_net_create.argtypes = [i32, i32, ctypes.POINTER(vp)]
+    L.pic_net_destroy.argtypes = [vp]
+    L.pic_net_set_params.argtypes = [vp, vp, vp]
+    L.pic_net_get_params.argtypes = [vp, vp, vp]
+    L.pic_net_forward.argtypes = [vp, vp, vp, vp]
+    L.pic_net_backward.argtypes = [vp, vp, vp, vp]
+    L.pic_net_train_step.argtypes = [vp, vp, vp, dbl, dbl, ctypes.POINTER(dbl), vp]
+    L.pic_net_precondition.argtypes = [vp, vp, dbl, vp, vp]
+    L.pic_conv3d_frag_elems.argtypes = [i32, i32]
+    L.pic_conv3d_frag_elems.restype = ctypes.c_size_t
+    L.pic_conv3d_pack.argtypes = [i32, i32, vp, vp, vp, vp]
+    L.pic_conv3d_fwd.argtypes = [i32, i32, i32, vp, vp, vp, vp, i32, vp, vp]
+    L.pic_conv3d_bwd_data.argtypes = [i32, i32, i32, vp, vp, vp, i32, vp]
+    L.pic_conv3d_wgrad_scratch_elems.argtypes = [i32, i32, i32]
+    L.pic_conv3d_wgrad_scratch_elems.restype = ctypes.c_size_t
+    L.pic_conv3d_bwd_weight.argtypes = [i32, i32, i32, vp, vp, vp, vp, vp]
+    L.pic_adam_step.argtypes = [i64, vp, vp, vp, vp, dbl, dbl, dbl, dbl, i32, vp]
     _lib = L
     return L
 
@@ -231,6 +256,14 @@ class Context:
                                                                             ex, ey, ez)],
                                    _stream(stream)))
 
+    def set_unet(self, params, stream=None):
+        """Load the network's FP32 parameters (device tensor, canonical order)."""
+        import torch
+        _check(lib().pic_set_unet(self._h, _ptr(params, torch.float32, "params"), _stream(stream)))
+
+    def precondition(self, r, z, stream=None):
+        _check(lib().pic_unet_precondition(self._h, _ptr(r), _ptr(z), _stream(stream)))
+
     def set_kernel_timing(self, on=True):
         _check(lib().pic_set_kernel_timing(self._h, 1 if on else 0))
 
@@ -298,3 +331,86 @@ class Simulation:
         d = info.as_dict()
         d["status"] = rc
         return d
+
+
+def unet_param_count() -> int:
+    return int(lib().pic_unet_param_count())
+
+
+class Net:
+    """A standalone network on an n^3 grid (training adds gradient buffers)."""
+
+    def __init__(self, n: int, training: bool = False):
+        self._h = ctypes.c_void_p()
+        _check(lib().pic_net_create(n, 1 if training else 0, ctypes.byref(self._h)))
+        self.n = n
+
+    def close(self):
+        if self._h:
+            lib().pic_net_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, stream=None):
+        import torch
+        _check(lib().pic_net_set_params(self._h, _ptr(params, torch.float32, "params"), _stream(stream)))
+
+    def get_params(self, out, stream=None):
+        import torch
+        _check(lib().pic_net_get_params(self._h, _ptr(out, torch.float32, "params"), _stream(stream)))
+        return out
+
+    def forward(self, x, out, stream=None):
+        _check(lib().pic_net_forward(self._h, _ptr(x), _ptr(out), _stream(stream)))
+        return out
+
+    def backward(self, dout, grads, stream=None):
+        _check(lib().pic_net_backward(self._h, _ptr(dout), _ptr(grads), _stream(stream)))
+        return grads
+
+    def train_step(self, rhs, target, lam=1.0, lr=1e-3, want_loss=True, stream=None):
+        loss = ctypes.c_double(0.0)
+        _check(lib().pic_net_train_step(self._h, _ptr(rhs), _ptr(target), lam, lr,
+                                        ctypes.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def precondition(self, r, h, z, stream=None):
+        _check(lib().pic_net_precondition(self._h, _ptr(r), h, _ptr(z), _stream(stream)))
+        return z
+
+
+def conv3d_frag_elems(ci, co):
+    return int(lib().pic_conv3d_frag_elems(ci, co))
+
+
+def conv3d_pack(ci, co, w, frag_fwd=None, frag_bwd=None, stream=None):
+    _check(lib().pic_conv3d_pack(ci, co, _ptr(w), _ptr(frag_fwd), _ptr(frag_bwd), _stream(stream)))
+
+
+def conv3d_fwd(n, ci, co, x, frag_fwd, bias, y, skip=None, relu=True, stream=None):
+    _check(lib().pic_conv3d_fwd(n, ci, co, _ptr(x), _ptr(frag_fwd), _ptr(bias), _ptr(skip),
+                                1 if relu else 0, _ptr(y), _stream(stream)))
+
+
+def conv3d_bwd_data(n, ci, co, gy, frag_bwd, gx, accumulate=False, stream=None):
+    _check(lib().pic_conv3d_bwd_data(n, ci, co, _ptr(gy), _ptr(frag_bwd), _ptr(gx),
+                                     1 if accumulate else 0, _stream(stream)))
+
+
+def conv3d_wgrad_scratch_elems(n, ci, co):
+    return int(lib().pic_conv3d_wgrad_scratch_elems(n, ci, co))
+
+
+def conv3d_bwd_weight(n, ci, co, x, gy, scratch, grad, stream=None):
+    _check(lib().pic_conv3d_bwd_weight(n, ci, co, _ptr(x), _ptr(gy), _ptr(scratch), _ptr(grad),
+                                       _stream(stream)))
+
+
+def adam_step(theta, m, v, g, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().pic_adam_step(theta.numel(), _ptr(theta), _ptr(m), _ptr(v), _ptr(g), lr, beta1,
+                               beta2, eps, step, _stream(stream)))

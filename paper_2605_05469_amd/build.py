@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic.so")
 
-SOURCES = ["stencil.hip", "particles.hip", "sort.hip", "learned.hip", "capi.hip"]
+SOURCES = ["stencil.hip", "particles.hip", "sort.hip", "net_kernels.hip", "net.hip", "capi.hip",
+           "capi_net.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

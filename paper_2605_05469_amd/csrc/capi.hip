@@ -14,7 +14,7 @@
 #include <vector>
 
 #include "../../include/pic.h"
-#include "learned.hpp"
+#include "net.hpp"
 #include "particles.hpp"
 #include "solver_state.hpp"
 
@@ -32,6 +32,8 @@ static int fail(int code, const char* fmt, ...) {
     g_err = buf;
     return code;
 }
+
+extern "C" int pic_set_error_(int code, const char* msg) { return fail(code, "%s", msg); }
 
 #define HIPCHK(expr)                                                                   \
     do {                                                                               \
@@ -67,7 +69,10 @@ struct pic_ctx {
     float* p32[2] = {nullptr, nullptr};
     void* sort_pool = nullptr;
     SortScratch sort{};
-    Learned* learned = nullptr;
+    net::Net* net = nullptr;       // learned preconditioner (inference buffers at n)
+    double* fz = nullptr;          // flexible CG: z = M(r)
+    double* fq = nullptr;          //              q = A p
+    double* fw = nullptr;          //              warm-start trial / true residual
     std::vector<void*> allocs;
     // kernel timing
     bool timing = false;
@@ -141,10 +146,19 @@ static int ensure_mixed(pic_ctx* c) {
     return PIC_OK;
 }
 
+static size_t learned_bytes(const pic_params* p) {
+    const int64_t n3 = (int64_t)p->n * p->n * p->n;
+    return 3 * vec_bytes(n3, 8);
+}
+
 static int ensure_learned(pic_ctx* c) {
-    if (c->learned) return PIC_OK;
-    int rc = learned_create(&c->learned, c->p.n, c->n3);
-    if (rc != PIC_OK) return fail(rc, "learned solver scratch: %s", learned_last_error());
+    if (c->fz) return PIC_OK;
+    void* m = nullptr;
+    RETCHK(dev_alloc(c, &m, learned_bytes(&c->p)));
+    const size_t vb = vec_bytes(c->n3, 8);
+    c->fz = (double*)m;
+    c->fq = (double*)((char*)m + vb);
+    c->fw = (double*)((char*)m + 2 * vb);
     return PIC_OK;
 }
 
@@ -240,9 +254,11 @@ static int pcg64_iterate(pic_ctx* c, const double* b, double* x, hipStream_t s) 
     }
 }
 
-static int solve_fp64(pic_ctx* c, const double* b, double* x, pic_solve_info* out, hipStream_t s) {
+static int solve_fp64(pic_ctx* c, const double* b, double* x, pic_solve_info* out, hipStream_t s,
+                      int64_t max_iter = -1) {
     const SweepGeo& g = c->geo;
-    HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 1, c->p.rtol, c->p.max_iter, c->st,
+    if (max_iter < 0) max_iter = c->p.max_iter;
+    HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 1, c->p.rtol, max_iter, c->st,
                              c->partials, s));
     RETCHK(read_state(c, s));
     if (c->st_host->cg.state == CG_ZERO_RHS) {
@@ -335,6 +351,144 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
     return PIC_OK;
 }
 
+// -------------------------------------------------- learned (flexible) ----
+// Flexible PCG (Notay 2000; Golub & Ye 1999) with the network preconditioner
+// z = M(r) = s NN(h^2 r / s) - mean, an optional network warm start, and a
+// permanent switch to Jacobi-PCG from the current iterate when the flexible
+// iteration stalls: (z.r) <= 0, anything non-finite, or no 1% improvement of
+// the best ||r|| over `fcg_window` iterations.  The PCG residual test decides
+// convergence either way.
+static int fcg_precond(pic_ctx* c, const double* r, double* z, hipStream_t s) {
+    if (!c->net) return fail(PIC_ERR_STATE, "no network loaded (pic_set_unet)");
+    const int rc = net::precondition(c->net, r, c->h * c->h, z, s);
+    if (rc) return fail(PIC_ERR_HIP, "network: %s", net::last_error());
+    return PIC_OK;
+}
+
+static int solve_learned(pic_ctx* c, const double* b, double* x, pic_solve_info* out,
+                         hipStream_t s) {
+    RETCHK(ensure_learned(c));
+    if (!c->net) return fail(PIC_ERR_STATE, "no network loaded (pic_set_unet)");
+    const SweepGeo& g = c->geo;
+    const int64_t n3 = c->n3;
+    // r = b - A x, ||b||, threshold (the residual kernel's init mode)
+    HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 1, c->p.rtol, c->p.max_iter, c->st,
+                             c->partials, s));
+    RETCHK(read_state(c, s));
+    const double nb = c->st_host->cg.nb, tol = c->st_host->cg.tol;
+    out->norm_b = nb;
+    if (c->st_host->cg.state == CG_ZERO_RHS) {
+        HIPCHK(launch_fill(n3, x, 0.0, s));
+        out->converged = 1;
+        return PIC_OK;
+    }
+    double rn = c->st_host->cg.true_rn;
+    if (rn <= tol) {
+        out->converged = 1;
+        out->rel_res = rn / nb;
+        return PIC_OK;
+    }
+    // warm start: x + M(r), kept only if it lowers the true residual
+    if (!(c->p.reserved & 1)) {
+        RETCHK(fcg_precond(c, c->r, c->fz, s));
+        HIPCHK(launch_axpy_copy(n3, x, c->fz, c->fw, s));
+        HIPCHK(launch_resid_norm(g, b, c->fw, c->fq, c->inv_h2, c->st, c->partials, s));
+        RETCHK(read_state(c, s));
+        const double rw = c->st_host->out_nr;
+        if (std::isfinite(rw) && rw < rn) {
+            HIPCHK(launch_copy(n3, c->fw, x, s));
+            HIPCHK(launch_copy(n3, c->fq, c->r, s));
+            rn = rw;
+            out->warm_start_used = 1;
+            if (rn <= tol) {
+                out->converged = 1;
+                out->rel_res = rn / nb;
+                return PIC_OK;
+            }
+        }
+    }
+    double* p = c->p2[0];
+    int64_t it = 0;
+    bool flexible = true;
+    double best = rn;
+    int since = 0;
+    RETCHK(fcg_precond(c, c->r, c->fz, s));
+    HIPCHK(launch_fcg_dots(n3, c->fz, c->r, c->r, c->st, c->partials, s));
+    RETCHK(read_state(c, s));
+    double rz = c->st_host->flex_zr;
+    if (!(rz > 0.0) || !std::isfinite(rz)) flexible = false;
+    if (flexible) HIPCHK(launch_copy(n3, c->fz, p, s));
+    while (flexible && it < c->p.max_iter) {
+        HIPCHK(launch_aq(g, p, c->fq, c->inv_h2, c->st, c->partials, s));
+        RETCHK(read_state(c, s));
+        const double pq = c->st_host->flex_pq;
+        const double alpha = rz / pq;
+        if (!std::isfinite(alpha) || !(pq > 0.0)) {
+            flexible = false;
+            break;
+        }
+        HIPCHK(launch_fcg_update(n3, x, c->r, p, c->fq, alpha, c->st, c->partials, s));
+        RETCHK(read_state(c, s));
+        ++it;
+        double rr = std::sqrt(c->st_host->flex_rr);
+        if (!std::isfinite(rr)) {
+            flexible = false;
+            break;
+        }
+        if (rr <= tol) {
+            // verify with the true residual (into fw); replace r if it fails
+            HIPCHK(launch_resid_norm(g, b, x, c->fw, c->inv_h2, c->st, c->partials, s));
+            RETCHK(read_state(c, s));
+            if (c->st_host->out_nr <= tol) {
+                out->converged = 1;
+                out->iterations = it;
+                out->flex_iterations = it;
+                out->rel_res = c->st_host->out_nr / nb;
+                return PIC_OK;
+            }
+            HIPCHK(launch_copy(n3, c->fw, c->r, s));
+            rr = c->st_host->out_nr;
+            out->replacements += 1;
+        }
+        if (rr < 0.99 * best) {
+            best = rr;
+            since = 0;
+        } else if (++since >= c->p.fcg_window) {
+            flexible = false;
+            break;
+        }
+        RETCHK(fcg_precond(c, c->r, c->fz, s));
+        HIPCHK(launch_fcg_dots(n3, c->fz, c->r, c->fq, c->st, c->partials, s));
+        RETCHK(read_state(c, s));
+        const double zr = c->st_host->flex_zr, zq = c->st_host->flex_zq;
+        if (!(zr > 0.0) || !std::isfinite(zr) || !std::isfinite(zq)) {
+            flexible = false;
+            break;
+        }
+        HIPCHK(launch_xpby(n3, c->fz, p, -zq / pq, s));
+        rz = zr;
+    }
+    out->flex_iterations = it;
+    if (it >= c->p.max_iter) {
+        HIPCHK(launch_resid_norm(g, b, x, c->fw, c->inv_h2, c->st, c->partials, s));
+        RETCHK(read_state(c, s));
+        out->iterations = it;
+        out->rel_res = c->st_host->out_nr / nb;
+        out->converged = out->rel_res <= c->p.rtol;
+        return PIC_OK;
+    }
+    // fallback: Jacobi-PCG from the current iterate, with the remaining budget
+    out->fell_back = 1;
+    pic_solve_info pi;
+    std::memset(&pi, 0, sizeof pi);
+    RETCHK(solve_fp64(c, b, x, &pi, s, c->p.max_iter - it));
+    out->iterations = it + pi.iterations;
+    out->replacements += pi.replacements;
+    out->rel_res = pi.rel_res;
+    out->converged = pi.converged;
+    return PIC_OK;
+}
+
 // ------------------------------------------------------------------ field --
 
 static int field(pic_ctx* c, double* phi, double* ex, double* ey, double* ez, hipStream_t s) {
@@ -356,7 +510,7 @@ size_t pic_workspace_bytes(const pic_params* p) {
     size_t b = base_bytes(p);
     if (p->np_max > 0) b += sort_scratch_bytes(p->np_max);
     if (p->solver == PIC_SOLVER_PCG_MIXED) b += mixed_bytes(p);
-    if (p->solver == PIC_SOLVER_FCG_LEARNED) b += learned_bytes(p->n);
+    if (p->solver == PIC_SOLVER_FCG_LEARNED) b += learned_bytes(p);
     return b;
 }
 
@@ -441,7 +595,7 @@ int pic_destroy(pic_ctx* c) {
     for (void* a : c->allocs) (void)hipFree(a);
     if (c->st_host) (void)hipHostFree(c->st_host);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-    if (c->learned) learned_destroy(c->learned);
+    if (c->net) net::destroy(c->net);
     delete c;
     return PIC_OK;
 }
@@ -557,13 +711,7 @@ int pic_poisson_pcg(pic_ctx* c, const double* rho, double* phi, double* ex, doub
     switch (c->p.solver) {
         case PIC_SOLVER_PCG_FP64: RETCHK(solve_fp64(c, rho, phi, &si, s)); break;
         case PIC_SOLVER_PCG_MIXED: RETCHK(solve_mixed(c, rho, phi, &si, s)); break;
-        default: {
-            LearnedEnv env{c->geo, c->n3, c->inv_h2, c->minv, c->h, c->p.rtol, c->p.max_iter,
-                           c->p.check_every, c->p.fcg_window, c->st, c->st_host, c->partials,
-                           c->r, c->p2[0], c->p2[1]};
-            int rc = learned_solve(c->learned, &env, rho, phi, &si, s);
-            if (rc != PIC_OK) return fail(rc, "learned solve: %s", learned_last_error());
-        }
+        default: RETCHK(solve_learned(c, rho, phi, &si, s)); break;
     }
     if (want_e) {
         RETCHK(field(c, phi, ex, ey, ez, s));
@@ -572,6 +720,28 @@ int pic_poisson_pcg(pic_ctx* c, const double* rho, double* phi, double* ex, doub
     }
     if (info) *info = si;
     return si.converged ? PIC_OK : PIC_NOT_CONVERGED;
+}
+
+int pic_set_unet(pic_ctx* c, const float* params, void* stream) {
+    if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
+    if (!params) return fail(PIC_ERR_INVALID, "params is NULL");
+    if (!c->net) {
+        const int rc = net::create(&c->net, c->p.n, false);
+        if (rc) {
+            c->net = nullptr;
+            return fail(rc == -3 ? PIC_ERR_NOMEM : PIC_ERR_HIP, "network buffers: %s", net::last_error());
+        }
+    }
+    if (net::set_params(c->net, params, (hipStream_t)stream))
+        return fail(PIC_ERR_HIP, "network parameters: %s", net::last_error());
+    return PIC_OK;
+}
+
+int pic_unet_precondition(pic_ctx* c, const double* r, double* z, void* stream) {
+    if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
+    NEED(r, "r");
+    NEED(z, "z");
+    return fcg_precond(c, r, z, (hipStream_t)stream);
 }
 
 int pic_gather_push(pic_ctx* c, int64_t np, double* x, double* y, double* z, double* vx,
@@ -687,13 +857,7 @@ int pic_step(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, v
     switch (c->p.solver) {
         case PIC_SOLVER_PCG_FP64: rc = solve_fp64(c, F->rho, F->phi, &si, s); break;
         case PIC_SOLVER_PCG_MIXED: rc = solve_mixed(c, F->rho, F->phi, &si, s); break;
-        default: {
-            LearnedEnv env{c->geo, c->n3, c->inv_h2, c->minv, c->h, c->p.rtol, c->p.max_iter,
-                           c->p.check_every, c->p.fcg_window, c->st, c->st_host, c->partials,
-                           c->r, c->p2[0], c->p2[1]};
-            rc = learned_solve(c->learned, &env, F->rho, F->phi, &si, s);
-            if (rc < 0) return fail(rc, "learned solve: %s", learned_last_error());
-        }
+        default: rc = solve_learned(c, F->rho, F->phi, &si, s);
     }
     if (rc < 0) return rc;
     RETCHK(T.mark(4, s));

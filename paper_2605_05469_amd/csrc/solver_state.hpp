@@ -44,6 +44,8 @@ struct DevState {
     double sum;        // generic reduction result
     double flex_zq;    // learned: z . q
     double flex_zr;    // learned: z . r
+    double flex_pq;    // learned: p . A p
+    double flex_rr;    // learned: r . r
     int32_t outer_state;
     int32_t pad;
     uint32_t tickets[8];
@@ -86,6 +88,21 @@ hipError_t launch_sum(int64_t n3, const double* v, DevState* st, double* partial
 hipError_t launch_field(const SweepGeo& g, double* phi, double* ex, double* ey, double* ez,
                         double ehalf, double h3, DevState* st, double* partials, hipStream_t s);
 hipError_t launch_fill(int64_t n, double* v, double val, hipStream_t s);
+// r = b - A x and st->out_nr = ||r|| (no state change).
+hipError_t launch_resid_norm(const SweepGeo& g, const double* b, const double* x, double* r,
+                             double inv_h2, DevState* st, double* partials, hipStream_t s);
+// Flexible CG pieces (learned preconditioner): q = A p with p.q -> flex_pq;
+// x += a p, r -= a q with r.r -> flex_rr; z.r, z.q -> flex_zr, flex_zq;
+// p = z + b p; w = x + z; dst = src.
+hipError_t launch_aq(const SweepGeo& g, const double* p, double* q, double inv_h2, DevState* st,
+                     double* partials, hipStream_t s);
+hipError_t launch_fcg_update(int64_t n3, double* x, double* r, const double* p, const double* q,
+                             double a, DevState* st, double* partials, hipStream_t s);
+hipError_t launch_fcg_dots(int64_t n3, const double* z, const double* r, const double* q,
+                           DevState* st, double* partials, hipStream_t s);
+hipError_t launch_xpby(int64_t n3, const double* z, double* p, double b, hipStream_t s);
+hipError_t launch_axpy_copy(int64_t n3, const double* x, const double* z, double* w, hipStream_t s);
+hipError_t launch_copy(int64_t n3, const double* src, double* dst, hipStream_t s);
 
 // Upper bound on the workgroups of one sweep (size of the partials array).
 int max_sweep_blocks();

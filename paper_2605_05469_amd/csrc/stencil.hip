@@ -407,9 +407,10 @@ struct OpOuterResid {
     double* r;
     double inv_h2;
     double tol;  // outer stop threshold rtol * ||b||
+    int gate;    // 1: run only while the outer state is RUNNING and update it
     DevState* st;
     double* part;
-    __device__ bool active() const { return st->outer_state == CG_RUNNING; }
+    __device__ bool active() const { return !gate || st->outer_state == CG_RUNNING; }
     __device__ void prepare() {}
     __device__ double fetch(size_t g) const { return x[g]; }
     __device__ double make(double v, size_t, bool) const { return v; }
@@ -424,11 +425,39 @@ struct OpOuterResid {
         const double nr = sqrt(t[0]);
         st->out_nr = nr;
         st->out_sc = 1.0 / nr;
+        if (!gate) return;
         st->cg.true_rn = nr;
         if (!isfinite(nr)) st->outer_state = CG_BREAKDOWN;
         else if (nr <= tol) st->outer_state = CG_CONVERGED;
     }
     __device__ uint32_t* ticket() const { return &st->tickets[3]; }
+    __device__ double* partials() const { return part; }
+};
+
+// Flexible CG: q = A p (stored), reduce p . q.
+struct OpAq {
+    using T = double;
+    using In = double;
+    using Own = Nothing;
+    static constexpr int NACC = 1;
+    const double* p;
+    double* q;
+    double inv_h2;
+    DevState* st;
+    double* part;
+    __device__ bool active() const { return true; }
+    __device__ void prepare() {}
+    __device__ double fetch(size_t g) const { return p[g]; }
+    __device__ double make(double v, size_t, bool) const { return v; }
+    __device__ Nothing pre(size_t) const { return Nothing{}; }
+    __device__ void out(const Nothing&, size_t g, double c, double xm, double xp, double ym,
+                        double yp, double zm, double zp, double (&acc)[1]) const {
+        const double qv = apply_A<double>(c, xm, xp, ym, yp, zm, zp, inv_h2);
+        st_own(qv, q + g);
+        acc[0] += c * qv;
+    }
+    __device__ void finish(double (&t)[1]) const { st->flex_pq = t[0]; }
+    __device__ uint32_t* ticket() const { return &st->tickets[1]; }
     __device__ double* partials() const { return part; }
 };
 
@@ -634,7 +663,13 @@ hipError_t launch_upd32(const SweepGeo& g, const float* p_new, float* d, float* 
 hipError_t launch_outer_resid(const SweepGeo& g, const double* b, const double* x, double* r,
                               double inv_h2, DevState* st, double* partials, double tol,
                               hipStream_t s) {
-    OpOuterResid op{b, x, r, inv_h2, tol, st, partials};
+    OpOuterResid op{b, x, r, inv_h2, tol, 1, st, partials};
+    return launch_sweep(op, g, s);
+}
+
+hipError_t launch_resid_norm(const SweepGeo& g, const double* b, const double* x, double* r,
+                             double inv_h2, DevState* st, double* partials, hipStream_t s) {
+    OpOuterResid op{b, x, r, inv_h2, 0.0, 0, st, partials};
     return launch_sweep(op, g, s);
 }
 
@@ -687,6 +722,106 @@ hipError_t launch_sum(int64_t n3, const double* v, DevState* st, double* partial
 
 hipError_t launch_fill(int64_t n, double* v, double val, hipStream_t s) {
     hipLaunchKernelGGL(fill_kernel, dim3(stream_blocks(n)), dim3(kNT), 0, s, n, v, val);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- flexible CG streams ----
+__global__ __launch_bounds__(kNT) void fcg_update_kernel(int64_t n3, double* __restrict__ x,
+                                                         double* __restrict__ r,
+                                                         const double* __restrict__ p,
+                                                         const double* __restrict__ q, double a,
+                                                         DevState* st, double* part) {
+    __shared__ double red[kNT / kWave];
+    __shared__ int lflag;
+    double acc[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT) {
+        x[i] = x[i] + a * p[i];
+        const double rv = r[i] - a * q[i];
+        r[i] = rv;
+        acc[0] += rv * rv;
+    }
+    block_sum<kNT, 1>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+    if (last_block(&st->tickets[5], gridDim.x, &lflag)) {
+        double t[1];
+        sum_partials<kNT, 1>(part, gridDim.x, t, red);
+        if (threadIdx.x == 0) st->flex_rr = t[0];
+    }
+}
+
+__global__ __launch_bounds__(kNT) void fcg_dots_kernel(int64_t n3, const double* __restrict__ z,
+                                                       const double* __restrict__ r,
+                                                       const double* __restrict__ q, DevState* st,
+                                                       double* part) {
+    __shared__ double red[2 * (kNT / kWave)];
+    __shared__ int lflag;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT) {
+        const double zv = z[i];
+        acc[0] += zv * r[i];
+        acc[1] += zv * q[i];
+    }
+    block_sum<kNT, 2>(acc, red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc[0];
+        part[gridDim.x + blockIdx.x] = acc[1];
+    }
+    if (last_block(&st->tickets[5], gridDim.x, &lflag)) {
+        double t[2];
+        sum_partials<kNT, 2>(part, gridDim.x, t, red);
+        if (threadIdx.x == 0) {
+            st->flex_zr = t[0];
+            st->flex_zq = t[1];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kNT) void xpby_kernel(int64_t n3, const double* __restrict__ z,
+                                                   double* __restrict__ p, double b) {
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
+        p[i] = z[i] + b * p[i];
+}
+
+__global__ __launch_bounds__(kNT) void axpy_copy_kernel(int64_t n3, const double* __restrict__ x,
+                                                        const double* __restrict__ z,
+                                                        double* __restrict__ w) {
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
+        w[i] = x[i] + z[i];
+}
+
+__global__ __launch_bounds__(kNT) void copy_kernel(int64_t n3, const double* __restrict__ a,
+                                                   double* __restrict__ b) {
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
+        b[i] = a[i];
+}
+
+hipError_t launch_aq(const SweepGeo& g, const double* p, double* q, double inv_h2, DevState* st,
+                     double* partials, hipStream_t s) {
+    OpAq op{p, q, inv_h2, st, partials};
+    return launch_sweep(op, g, s);
+}
+hipError_t launch_fcg_update(int64_t n3, double* x, double* r, const double* p, const double* q,
+                             double a, DevState* st, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL(fcg_update_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, x, r, p, q, a,
+                       st, partials);
+    return hipGetLastError();
+}
+hipError_t launch_fcg_dots(int64_t n3, const double* z, const double* r, const double* q,
+                           DevState* st, double* partials, hipStream_t s) {
+    hipLaunchKernelGGL(fcg_dots_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, z, r, q, st,
+                       partials);
+    return hipGetLastError();
+}
+hipError_t launch_xpby(int64_t n3, const double* z, double* p, double b, hipStream_t s) {
+    hipLaunchKernelGGL(xpby_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, z, p, b);
+    return hipGetLastError();
+}
+hipError_t launch_axpy_copy(int64_t n3, const double* x, const double* z, double* w, hipStream_t s) {
+    hipLaunchKernelGGL(axpy_copy_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, x, z, w);
+    return hipGetLastError();
+}
+hipError_t launch_copy(int64_t n3, const double* src, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL(copy_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, src, dst);
     return hipGetLastError();
 }
 
