@@ -96,6 +96,102 @@ def cpu_baseline(N, ppc, p, sim, iters_per_step, budget_s):
             "sample": sample}
 
 
+def load_weights(ctx, path):
+    import numpy as np
+    import torch
+
+    if path is None:
+        path = os.path.join(ROOT, "paper_2605_05469_amd", "weights", "unet_landau128.npy")
+    w = np.load(path, allow_pickle=False).astype(np.float32)
+    ctx.set_unet(torch.from_numpy(w).cuda())
+
+
+def accuracy_vs_fp64(args, sim, p):
+    """Re-run warm-up + timed steps from the same seeded state with the FP64
+    solver; report the differences of phi, E and positions."""
+    import torch
+
+    import paper_2605_05469_amd as P
+    from paper_2605_05469_amd import synth
+
+    q = P.landau_params(args.grid, args.ppc, rtol=args.rtol, solver="pcg_fp64", check_every=32)
+    ctx = P.Context(q)
+    parts = synth.landau_particles_torch(args.grid, args.ppc, seed=args.seed, device="cuda")
+    ref = P.Simulation(ctx, *parts)
+    del parts
+    ref.init()
+    for _ in range(args.warmup + args.steps):
+        ref.step(timed=False)
+    h = p.length / args.grid
+
+    def rel(a, b):
+        return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+    dx = max(float(torch.max(torch.abs(torch.remainder(a - b + 0.5 * p.length, p.length)
+                                      - 0.5 * p.length))) for a, b in
+             zip(sim.particles[:3], ref.particles[:3]))
+    res = {"phi_rel_l2": rel(sim.phi, ref.phi),
+           "E_rel_l2": max(rel(a, b) for a, b in ((sim.ex, ref.ex), (sim.ey, ref.ey),
+                                                   (sim.ez, ref.ez))),
+           "max_position_diff_over_h": dx / h,
+           "steps": args.warmup + args.steps}
+    del ref, ctx
+    return res
+
+
+def bench_poisson(args):
+    """Standalone solves of the deposit of Landau particles (1 ppc by default
+    at 1024^3): cold start, each solver form, timed."""
+    import torch
+
+    import paper_2605_05469_amd as P
+    from paper_2605_05469_amd import synth
+
+    N, ppc = args.grid, args.ppc
+    p = P.landau_params(N, ppc, rtol=args.rtol, solver="pcg_fp64", check_every=32,
+                        inner_rtol=args.inner_rtol)
+    if args.no_warm_start:
+        p.reserved = 1
+    ctx = P.Context(p)
+    parts = synth.landau_particles_torch(N, ppc, seed=args.seed, device="cuda")
+    rho = torch.empty(N ** 3, dtype=torch.float64, device="cuda")
+    ctx.deposit(parts[0], parts[1], parts[2], None, rho)
+    del parts
+    torch.cuda.synchronize()
+    forms = {}
+    for solver in ("pcg_fp64", "pcg_mixed", "fcg_learned"):
+        if solver == "fcg_learned":
+            try:
+                load_weights(ctx, args.weights)
+            except (OSError, ValueError) as e:
+                forms[solver] = {"skipped": repr(e)}
+                continue
+        ctx.set_solver(solver)
+        phi = torch.zeros_like(rho)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ctx.poisson(rho, phi)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        forms[solver] = {"s_per_solve": dt, "iterations": info["iterations"],
+                         "outer_iterations": info["outer_iterations"],
+                         "flex_iterations": info["flex_iterations"],
+                         "fell_back": info["fell_back"], "warm_start_used": info["warm_start_used"],
+                         "rel_res": info["rel_res"], "converged": bool(info["converged"])}
+        log("%s: %.3f s, %d iterations, rel_res %.2e" % (solver, dt, info["iterations"],
+                                                         info["rel_res"]))
+    sel = forms.get(args.solver, {})
+    n3 = N ** 3
+    out = {"metric": METRIC, "value": sel.get("s_per_solve"), "unit": "s/solve", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": 1e3 * sel.get("s_per_solve", float("nan")),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": "poisson_solve_%d^3_rhs_%dppc_landau" % (N, ppc), "grid": N,
+                      "ppc": ppc, "rtol": args.rtol, "solver": args.solver},
+           "forms": forms}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +204,14 @@ def main():
     ap.add_argument("--seed", type=int, default=20262)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--weights", default=None,
+                    help="FP32 network parameters (.npy, canonical order) for fcg_learned")
+    ap.add_argument("--inner-rtol", type=float, default=1e-3)
+    ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--accuracy-vs-fp64", action="store_true",
+                    help="rerun the same steps with the FP64 solver and report the differences")
+    ap.add_argument("--workload", default="pic", choices=["pic", "poisson"],
+                    help="pic: full PIC steps; poisson: standalone solves of a deposited rho")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -121,9 +225,16 @@ def main():
     from paper_2605_05469_amd import synth
 
     torch.cuda.set_device(0)
+    if args.workload == "poisson":
+        return bench_poisson(args)
     N, ppc = args.grid, args.ppc
-    p = P.landau_params(N, ppc, rtol=args.rtol, solver=args.solver, check_every=32)
+    p = P.landau_params(N, ppc, rtol=args.rtol, solver=args.solver, check_every=32,
+                        inner_rtol=args.inner_rtol)
+    if args.no_warm_start:
+        p.reserved = 1
     ctx = P.Context(p)
+    if args.solver == "fcg_learned":
+        load_weights(ctx, args.weights)
     t0 = time.perf_counter()
     parts = synth.landau_particles_torch(N, ppc, seed=args.seed, device="cuda")
     sim = P.Simulation(ctx, *parts)
@@ -191,6 +302,8 @@ def main():
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs_upd / PEAK_HBM_GBS,
                      "traffic": UPDATE_SWEEP_TRAFFIC.get((N, args.solver))},
     }
+    if args.accuracy_vs_fp64 and args.solver != "pcg_fp64":
+        out["accuracy_vs_fp64"] = accuracy_vs_fp64(args, sim, p)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(N, ppc, p, sim, iters, args.cpu_budget)

@@ -24,7 +24,7 @@
  *     the last iterate); or a negative error code with a message available
  *     from pic_last_error().  No exception or abort crosses the ABI.
  *   - One context per stream; a context is not safe for concurrent use.
- *   - Requirements checked on entry: N a multiple of 32, 32 <= N <= 2048,
+ *   - Requirements checked on entry: N a multiple of 32, 32 <= N <= 1024,
  *     N^3 < 2^32, 0 <= np <= np_max, non-NULL required pointers, 8-byte
  *     aligned arrays.  Violations return PIC_ERR_INVALID and launch nothing.
  */

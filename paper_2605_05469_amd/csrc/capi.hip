@@ -64,6 +64,7 @@ struct pic_ctx {
     int npartials = 0;
     double* r = nullptr;
     double* p2[2] = {nullptr, nullptr};
+    double* t3 = nullptr;  // 4th scratch vector; r, p2[0], p2[1], t3 also serve the deposit
     float* r32 = nullptr;
     float* d32 = nullptr;
     float* p32[2] = {nullptr, nullptr};
@@ -112,7 +113,7 @@ static size_t base_bytes(const pic_params* p) {
     size_t b = 0;
     b += 4096;                               // DevState
     b += (size_t)4 * np * sizeof(double);    // partials
-    b += 3 * vec_bytes(n3, 8);               // r, p[2]
+    b += 4 * vec_bytes(n3, 8);               // r, p[2], t3
     return b;
 }
 
@@ -161,6 +162,13 @@ static int ensure_learned(pic_ctx* c) {
     c->fw = (double*)((char*)m + 2 * vb);
     return PIC_OK;
 }
+
+// The deposit's four n^3 scratch arrays: the solver vectors, free between solves.
+struct DepScratch {
+    double* t[4];
+    operator double* const*() const { return t; }
+};
+static DepScratch dep_scratch(pic_ctx* c) { return DepScratch{{c->r, c->p2[0], c->p2[1], c->t3}}; }
 
 static int read_state(pic_ctx* c, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(c->st_host, c->st, sizeof(DevState), hipMemcpyDeviceToHost, s));
@@ -563,6 +571,7 @@ int pic_create(const pic_params* params, pic_ctx** out) {
         c->r = (double*)q;
         c->p2[0] = (double*)(q + vb);
         c->p2[1] = (double*)(q + 2 * vb);
+        c->t3 = (double*)(q + 3 * vb);
         if (hipHostMalloc((void**)&c->st_host, sizeof(DevState), hipHostMallocDefault) != hipSuccess) {
             rc = fail(PIC_ERR_NOMEM, "pinned host allocation failed");
             break;
@@ -676,7 +685,7 @@ int pic_deposit_cic(pic_ctx* c, int64_t np, const double* x, const double* y, co
     if (np > 0) { NEED(x, "x"); NEED(y, "y"); NEED(z, "z"); }
     hipStream_t s = (hipStream_t)stream;
     HIPCHK(launch_deposit(np, x, y, z, np > 0 ? cell_start : nullptr, rho, c->p.n, c->inv_h,
-                          c->qh3, c->p.rho_bg, c->st, c->partials, s));
+                          c->qh3, c->p.rho_bg, c->st, c->partials, dep_scratch(c), s));
     if (norm_b) {
         RETCHK(read_state(c, s));
         *norm_b = std::sqrt(c->st_host->bb);
@@ -822,7 +831,7 @@ int pic_init(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, v
     if (P->np > 0) HIPCHK(launch_keys(P->np, P->cur.x, P->cur.y, P->cur.z, P->key, c->p.n, c->inv_h, s));
     RETCHK(sort_swap(c, P, s));
     HIPCHK(launch_deposit(P->np, P->cur.x, P->cur.y, P->cur.z, P->np > 0 ? P->cell_start : nullptr,
-                          F->rho, c->p.n, c->inv_h, c->qh3, c->p.rho_bg, c->st, c->partials, s));
+                          F->rho, c->p.n, c->inv_h, c->qh3, c->p.rho_bg, c->st, c->partials, dep_scratch(c), s));
     pic_solve_info si;
     int rc = pic_poisson_pcg(c, F->rho, F->phi, F->ex, F->ey, F->ez, &si, stream);
     if (rc < 0) return rc;
@@ -849,7 +858,7 @@ int pic_step(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, v
     RETCHK(sort_swap(c, P, s));
     RETCHK(T.mark(2, s));
     HIPCHK(launch_deposit(P->np, P->cur.x, P->cur.y, P->cur.z, P->np > 0 ? P->cell_start : nullptr,
-                          F->rho, c->p.n, c->inv_h, c->qh3, c->p.rho_bg, c->st, c->partials, s));
+                          F->rho, c->p.n, c->inv_h, c->qh3, c->p.rho_bg, c->st, c->partials, dep_scratch(c), s));
     RETCHK(T.mark(3, s));
     pic_solve_info si;
     std::memset(&si, 0, sizeof si);

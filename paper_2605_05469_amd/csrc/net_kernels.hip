@@ -86,6 +86,37 @@ __global__ void pack_kernel(const float* __restrict__ W, int ci_n, int co_n, int
     }
 }
 
+// Plane-major fragments of the z-marching kernel: for tap plane dzi (the
+// input plane z + dzi - 1), K-chunk s of that plane and output block cb,
+// lane l holds A[m = 16 cb + l%16][k = 32 s + 8 (l/16) + i], k = u*cin + c
+// over the 9 in-plane taps u = 3 (dy+1) + (dx+1), zero-padded to whole
+// chunks.  Same transposition as above for the backward-data weights.
+__global__ void pack_zm_kernel(const float* __restrict__ W, int ci_n, int co_n, int bwd,
+                               uint16_t* __restrict__ frag) {
+    const int cin = bwd ? co_n : ci_n;
+    const int cout = bwd ? ci_n : co_n;
+    const int ksp = (9 * cin + 31) / 32;
+    const int ncb = cout / 16;
+    const int nfrag = 3 * ksp * ncb * 64 * 8;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nfrag; e += gridDim.x * blockDim.x) {
+        const int i = e & 7;
+        const int lane = (e >> 3) & 63;
+        const int f = e >> 9;  // ((dzi * ksp + s) * ncb + cb)
+        const int cb = f % ncb;
+        const int s = (f / ncb) % ksp;
+        const int dzi = f / (ncb * ksp);
+        const int m = cb * 16 + (lane & 15);
+        const int k = 32 * s + 8 * (lane >> 4) + i;
+        float v = 0.f;
+        if (k < 9 * cin) {
+            const int t = 9 * dzi + k / cin, c = k % cin;
+            if (!bwd) v = W[((size_t)m * ci_n + c) * 27 + t];
+            else v = W[((size_t)c * ci_n + m) * 27 + (26 - t)];
+        }
+        frag[e] = f2bf(v);
+    }
+}
+
 // ------------------------------------------------------- MFMA conv (gather) --
 // MODE 0: forward, Y = relu?(acc + bias (+ skip)) in BF16.
 // MODE 1: backward data, Yf = acc (+ Yf if accumulate) in FP32.
@@ -181,6 +212,173 @@ __global__ __launch_bounds__(kNT) void conv_mfma_kernel(int n, const uint16_t* _
                 }
             }
         }
+    }
+}
+
+// ------------------------------------------------ MFMA conv (z-marching) --
+// Same contraction as above, organised for reuse.  A block owns a 64 x TY
+// column of output points over a z range [zb, zb + zlen) and marches up it
+// one input plane at a time.  Each input plane (with a one-point periodic
+// halo in x and y) is staged once into LDS as [channel group][y][x] 16-byte
+// records, so the B fragment of a 16-point row and 8 channels is one
+// conflict-free 16-byte LDS read per lane; the next plane is loaded into
+// registers while the current one is consumed.  Every B fragment feeds the
+// three output planes it touches (taps dz = -1, 0, +1) through three rolling
+// accumulator sets, and each wave keeps all 27 taps of its output block's
+// weights in registers, so the only LDS traffic is one read per fragment.
+// Output plane z is complete (and stored, with the MODE 0/1 epilogue of the
+// gather kernel) once input plane z + 1 has been consumed.
+// Wave w computes output block w % NCB for the point tiles q, q + WQ, ... of
+// the plane (q = w / NCB, WQ = 4 / NCB).  Requires n % 64 == 0, n % TY == 0.
+template <int CI, int CO, int TY, int MODE>
+__global__ __launch_bounds__(kNT) void conv_zm_kernel(int n, int zlen, const uint16_t* __restrict__ X,
+                                                      const uint16_t* __restrict__ fragz,
+                                                      const float* __restrict__ bias,
+                                                      const uint16_t* __restrict__ skip, int relu,
+                                                      uint16_t* __restrict__ Yb,
+                                                      float* __restrict__ Yf, int accumulate) {
+    constexpr int TX = 64, SX = TX + 2, SY = TY + 2;
+    constexpr int CG = CI / 8;
+    constexpr int KSP = (9 * CI + 31) / 32;
+    constexpr int NCB = CO / 16;
+    static_assert(NCB == 1 || NCB == 2 || NCB == 4, "output blocks per block");
+    constexpr int WQ = 4 / NCB;
+    constexpr int NTILE = 4 * TY;
+    constexpr int PW = NTILE / WQ;
+    constexpr int NCH = SY * SX * CG;  // 16-byte records per staged plane
+    constexpr int NPT = (NCH + kNT - 1) / kNT;
+    __shared__ bf16x8 lds[2 * NCH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int cb = wave % NCB, q = wave / NCB;
+    const int ntx = n / TX;
+    const int ncol = ntx * (n / TY);
+    const int bid = (int)remap_xcd(blockIdx.x, gridDim.x);
+    const int col = bid % ncol;
+    const int zb = (bid / ncol) * zlen, ze = zb + zlen;
+    const int x0 = (col % ntx) * TX, y0 = (col / ntx) * TY;
+
+    bf16x8 w[3][KSP];
+    const bf16x8* fz = reinterpret_cast<const bf16x8*>(fragz);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int s = 0; s < KSP; ++s) w[d][s] = fz[((d * KSP + s) * NCB + cb) * 64 + lane];
+    // LDS offset (in records, within a plane buffer) of this lane's B row
+    // for each K-chunk, before the tile offset; -1 = zero padding
+    int boff[KSP];
+#pragma unroll
+    for (int s = 0; s < KSP; ++s) {
+        const int k0 = 32 * s + 8 * g;
+        const int u = k0 / CI, c0 = k0 - u * CI;
+        boff[s] = u < 9 ? ((c0 / 8) * SY + u / 3) * SX + (u % 3) + m : -1;
+    }
+    float bv[4] = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (MODE == 0) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bv[i] = bias[16 * cb + 4 * g + i];
+    }
+
+    bf16x8 stg[NPT];
+    auto load_plane = [&](int zp) {
+        const int zz = zp < 0 ? zp + n : (zp >= n ? zp - n : zp);
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int c = threadIdx.x + kNT * i;
+            if (c < NCH) {
+                const int cg = c % CG, pt = c / CG;
+                const int xx = pt % SX, yy = pt / SX;
+                const int x = wrapi(x0 - 1 + xx, n), y = wrapi(y0 - 1 + yy, n);
+                stg[i] = *reinterpret_cast<const bf16x8*>(
+                    X + (((int64_t)zz * n + y) * n + x) * CI + cg * 8);
+            }
+        }
+    };
+    auto store_plane = [&](int b) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int c = threadIdx.x + kNT * i;
+            if (c < NCH) {
+                const int cg = c % CG, pt = c / CG;
+                const int xx = pt % SX, yy = pt / SX;
+                lds[b * NCH + (cg * SY + yy) * SX + xx] = stg[i];
+            }
+        }
+    };
+
+    f32x4 acc[3][PW];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int j = 0; j < PW; ++j) acc[a][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    load_plane(zb - 1);
+    store_plane(0);
+    __syncthreads();
+    int buf = 0;
+    for (int zp = zb - 1; zp <= ze; ++zp) {
+        if (zp < ze) load_plane(zp + 1);
+        const bool lo = zp - 1 >= zb;  // output plane zp - 1 is ours
+        const bool mid = zp >= zb && zp < ze;
+        const bool hi = zp + 1 < ze;
+        const bf16x8* L = lds + buf * NCH;
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            const int T = q + WQ * j;
+            const int toff = (T >> 2) * SX + 16 * (T & 3);
+#pragma unroll
+            for (int s = 0; s < KSP; ++s) {
+                const bf16x8 b = boff[s] >= 0 ? L[boff[s] + toff] : bf16x8{};
+                if (hi) acc[2][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0][s], b, acc[2][j], 0, 0, 0);
+                if (mid) acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1][s], b, acc[1][j], 0, 0, 0);
+                if (lo) acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[2][s], b, acc[0][j], 0, 0, 0);
+            }
+        }
+        if (lo) {
+            const int z = zp - 1;
+#pragma unroll
+            for (int j = 0; j < PW; ++j) {
+                const int T = q + WQ * j;
+                const int64_t p = ((int64_t)z * n + y0 + (T >> 2)) * n + x0 + 16 * (T & 3) + m;
+                const int co0 = 16 * cb + 4 * g;
+                if constexpr (MODE == 0) {
+                    float y[4];
+                    uint2 sk = make_uint2(0u, 0u);
+                    if (skip) sk = *reinterpret_cast<const uint2*>(skip + p * CO + co0);
+                    const uint16_t* sh = reinterpret_cast<const uint16_t*>(&sk);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        y[i] = acc[0][j][i] + bv[i];
+                        if (skip) y[i] += bf2f(sh[i]);
+                        if (relu) y[i] = y[i] > 0.f ? y[i] : 0.f;
+                    }
+                    uint2 o;
+                    o.x = (uint32_t)f2bf(y[0]) | ((uint32_t)f2bf(y[1]) << 16);
+                    o.y = (uint32_t)f2bf(y[2]) | ((uint32_t)f2bf(y[3]) << 16);
+                    *reinterpret_cast<uint2*>(Yb + p * CO + co0) = o;
+                } else {
+                    float4 o = make_float4(acc[0][j][0], acc[0][j][1], acc[0][j][2], acc[0][j][3]);
+                    float4* dst = reinterpret_cast<float4*>(Yf + p * CO + co0);
+                    if (accumulate) {
+                        const float4 prev = *dst;
+                        o.x += prev.x;
+                        o.y += prev.y;
+                        o.z += prev.z;
+                        o.w += prev.w;
+                    }
+                    *dst = o;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            acc[0][j] = acc[1][j];
+            acc[1][j] = acc[2][j];
+            acc[2][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        if (zp < ze) store_plane(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
 }
 
@@ -708,14 +906,49 @@ static int blocks_for(int64_t work, int per = kNT, int cap = 4096) {
     return (int)(b < cap ? b : cap);
 }
 
+// A fragment buffer holds the gather kernel's fragments, followed (for
+// 16 or 32 gathered channels) by the z-marching kernel's plane-major ones.
+static size_t gather_frag_elems(int cin, int cout) {
+    return (size_t)((27 * cin + 31) / 32) * (cout / 16) * 512;
+}
+static bool zm_channels(int cin) { return cin == 16 || cin == 32; }
+static size_t zm_frag_elems(int cin, int cout) {
+    return zm_channels(cin) ? (size_t)3 * ((9 * cin + 31) / 32) * (cout / 16) * 512 : 0;
+}
+
 hipError_t pack(const float* W, int ci, int co, int bwd, uint16_t* frag, hipStream_t s) {
     const int cin = bwd ? co : ci, cout = bwd ? ci : co;
-    const int nfrag = ((27 * cin + 31) / 32) * (cout / 16) * 512;
+    const int64_t nfrag = (int64_t)gather_frag_elems(cin, cout);
     hipLaunchKernelGGL(pack_kernel, dim3(blocks_for(nfrag)), dim3(kNT), 0, s, W, ci, co, bwd, frag);
+    const int64_t nz = (int64_t)zm_frag_elems(cin, cout);
+    if (nz > 0)
+        hipLaunchKernelGGL(pack_zm_kernel, dim3(blocks_for(nz)), dim3(kNT), 0, s, W, ci, co, bwd,
+                           frag + nfrag);
     return hipGetLastError();
 }
 
-size_t frag_elems(int cin, int cout) { return (size_t)((27 * cin + 31) / 32) * (cout / 16) * 512; }
+size_t frag_elems(int cin, int cout) { return gather_frag_elems(cin, cout) + zm_frag_elems(cin, cout); }
+
+// z-split of the z-marching kernel: the largest divisor of n that keeps at
+// least 8 planes per block and gives at most 4096 blocks.
+static int zm_zsplit(int n, int ncol) {
+    int best = 1;
+    for (int zs = 1; zs <= n / 8; ++zs)
+        if (n % zs == 0 && (int64_t)ncol * zs <= 4096) best = zs;
+    return best;
+}
+
+template <int CI, int CO, int TY, int MODE>
+static hipError_t zm_launch(int n, const uint16_t* X, const uint16_t* frag, const float* bias,
+                            const uint16_t* skip, int relu, uint16_t* Yb, float* Yf, int acc,
+                            hipStream_t s) {
+    const int ncol = (n / 64) * (n / TY);
+    const int zs = zm_zsplit(n, ncol);
+    const uint16_t* fz = frag + gather_frag_elems(CI, CO);
+    hipLaunchKernelGGL((conv_zm_kernel<CI, CO, TY, MODE>), dim3(ncol * zs), dim3(kNT), 0, s, n,
+                       n / zs, X, fz, bias, skip, relu, Yb, Yf, acc);
+    return hipGetLastError();
+}
 
 template <int CI, int CO, int NG, int MODE>
 static hipError_t conv_launch(int n, const uint16_t* X, const uint16_t* frag, const float* bias,
@@ -731,6 +964,16 @@ static hipError_t conv_launch(int n, const uint16_t* X, const uint16_t* frag, co
 // NG (output blocks per launch) keeps the staged weights under 64 KB of LDS.
 hipError_t conv_fwd(int n, int ci, int co, const uint16_t* X, const uint16_t* frag,
                     const float* bias, const uint16_t* skip, int relu, uint16_t* Y, hipStream_t s) {
+    if (n % 64 == 0) {
+#define ZF(A, B, T) \
+    if (ci == A && co == B) return zm_launch<A, B, T, 0>(n, X, frag, bias, skip, relu, Y, nullptr, 0, s)
+        ZF(16, 16, 8);
+        ZF(16, 32, 4);
+        ZF(32, 32, 4);
+        ZF(32, 64, 2);
+        ZF(32, 16, 4);
+#undef ZF
+    }
 #define CF(A, B, G) \
     if (ci == A && co == B) return conv_launch<A, B, G, 0>(n, X, frag, bias, skip, relu, Y, nullptr, 0, s)
     CF(16, 16, 1);
@@ -746,6 +989,16 @@ hipError_t conv_fwd(int n, int ci, int co, const uint16_t* X, const uint16_t* fr
 hipError_t conv_bwd_data(int n, int ci, int co, const uint16_t* G, const uint16_t* frag_bwd,
                          float* dX, int accumulate, hipStream_t s) {
     // gathers the layer's output gradient (co channels), produces ci channels
+    if (n % 64 == 0) {
+#define ZB(A, B, T) \
+    if (ci == A && co == B) return zm_launch<B, A, T, 1>(n, G, frag_bwd, nullptr, nullptr, 0, nullptr, dX, accumulate, s)
+        ZB(16, 16, 8);
+        ZB(32, 16, 4);
+        ZB(16, 32, 4);
+        ZB(64, 32, 2);
+        ZB(32, 32, 4);
+#undef ZB
+    }
 #define CB(A, B, G2) \
     if (ci == A && co == B) return conv_launch<B, A, G2, 1>(n, G, frag_bwd, nullptr, nullptr, 0, nullptr, dX, accumulate, s)
     CB(16, 16, 1);

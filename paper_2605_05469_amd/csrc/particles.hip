@@ -136,55 +136,96 @@ __global__ __launch_bounds__(kPT) void half_kick_kernel(
     }
 }
 
-// Deterministic deposit on sorted particles: one thread per vertex.
-// rho[v] = (sum of CIC weights) * (q/h^3) + rho_bg; partial sums of rho.
-__global__ __launch_bounds__(kPT) void deposit_sorted_kernel(
+// Deterministic deposit on sorted particles, two passes.
+// Pass 1, one lane per cell, one wave per 63 cells of a row (lane 0 takes
+// the cell before the segment): each lane sums its cell's particles in sorted
+// order into the eight CIC corner sums S[a][b][c]; lanes then combine the two
+// cells of a row that touch vertex x (cell x-1 with a = 1, cell x with a = 0)
+// and store T[2c+b][(z, y) row][x]: the contribution of cell row (y, z) to
+// vertex (x, y+b, z+c).  Every particle is read once.
+__global__ __launch_bounds__(kPT) void deposit_cells_kernel(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
-    const uint32_t* __restrict__ cs, double* __restrict__ rho, int n, double inv_h, double qh3,
-    double rho_bg, double* part, DevState* st) {
+    const uint32_t* __restrict__ cs, int n, double inv_h, double* __restrict__ T0,
+    double* __restrict__ T1, double* __restrict__ T2, double* __restrict__ T3) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = ((int64_t)blockIdx.x * kPT + threadIdx.x) >> 6;
+    const int segs = (n + 62) / 63;
+    const int64_t rows = (int64_t)n * n;
+    if (wid >= rows * segs) return;  // uniform per wave
+    const int64_t row = wid / segs;
+    const int xl = (int)(wid % segs) * 63 + lane - 1;  // this lane's cell x (lane 0: x0 - 1)
+    const bool active = xl < n;
+    const int cx = xl < 0 ? n - 1 : xl;
+    double s[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) s[a][b][c] = 0.0;
+    if (active) {
+        const size_t cell = (size_t)row * n + cx;
+        const uint32_t pe = cs[cell + 1];
+        for (uint32_t p = cs[cell]; p < pe; ++p) {
+            int i0;
+            double w0, w1, w2;
+            locate(x[p], n, inv_h, i0, w0);
+            locate(y[p], n, inv_h, i0, w1);
+            locate(z[p], n, inv_h, i0, w2);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const double wz = c ? w2 : 1.0 - w2;
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const double wy = b ? w1 : 1.0 - w1;
+                    s[0][b][c] += (wz * wy) * (1.0 - w0);
+                    s[1][b][c] += (wz * wy) * w0;
+                }
+            }
+        }
+    }
+    double* T[4] = {T0, T1, T2, T3};
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const double left = __shfl_up(s[1][b][c], 1, 64);  // cell x-1, a = 1
+            if (lane >= 1 && active) T[2 * c + b][(size_t)row * n + xl] = left + s[0][b][c];
+        }
+}
+
+// Pass 2, one thread per vertex: rho[v] = (sum of the four cell-row
+// contributions, rows in increasing key order) * (q/h^3) + rho_bg; partial
+// sums of rho for the mean.
+__global__ __launch_bounds__(kPT) void deposit_vertices_kernel(
+    const double* __restrict__ T0, const double* __restrict__ T1, const double* __restrict__ T2,
+    const double* __restrict__ T3, double* __restrict__ rho, int n, double qh3, double rho_bg,
+    double* part, DevState* st) {
     __shared__ double red[kPT / kWave];
+    __shared__ int lflag;
+    const double* T[4] = {T0, T1, T2, T3};
     const int64_t n3 = (int64_t)n * n * n;
     double acc[1] = {0.0};
     for (int64_t v = (int64_t)blockIdx.x * kPT + threadIdx.x; v < n3; v += (int64_t)gridDim.x * kPT) {
         const int ix = (int)(v % n);
         const int iy = (int)((v / n) % n);
         const int iz = (int)(v / ((int64_t)n * n));
-        double s = 0.0;
-        // Cells around the vertex in increasing key order: per axis the cell
-        // below (offset 1) precedes the cell at the vertex (offset 0), except
-        // at index 0 where the periodic image n-1 sorts last.
+        double sum = 0.0;
         for (int kc = 0; kc < 2; ++kc) {
             const int c = (iz == 0) ? kc : 1 - kc;
             const int cz = iz - c < 0 ? n - 1 : iz - c;
             for (int kb = 0; kb < 2; ++kb) {
                 const int b = (iy == 0) ? kb : 1 - kb;
                 const int cy = iy - b < 0 ? n - 1 : iy - b;
-                for (int ka = 0; ka < 2; ++ka) {
-                    const int a = (ix == 0) ? ka : 1 - ka;
-                    const int cx = ix - a < 0 ? n - 1 : ix - a;
-                    const size_t cell = ((size_t)cz * n + cy) * n + cx;
-                    const uint32_t pe = cs[cell + 1];
-                    for (uint32_t p = cs[cell]; p < pe; ++p) {
-                        int i0;
-                        double w0, w1, w2;
-                        locate(x[p], n, inv_h, i0, w0);
-                        locate(y[p], n, inv_h, i0, w1);
-                        locate(z[p], n, inv_h, i0, w2);
-                        const double wz = c ? w2 : 1.0 - w2;
-                        const double wy = b ? w1 : 1.0 - w1;
-                        const double wx = a ? w0 : 1.0 - w0;
-                        s += (wz * wy) * wx;
-                    }
-                }
+                sum += T[2 * c + b][((size_t)cz * n + cy) * n + ix];
             }
         }
-        const double rv = s * qh3 + rho_bg;
+        const double rv = sum * qh3 + rho_bg;
         rho[v] = rv;
         acc[0] += rv;
     }
     block_sum<kPT, 1>(acc, red);
     if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
-    __shared__ int lflag;
     if (last_block(&st->tickets[7], gridDim.x, &lflag)) {
         double t[1];
         sum_partials<kPT, 1>(part, gridDim.x, t, red);
@@ -304,12 +345,18 @@ int deposit_partials() { return 4096; }
 
 hipError_t launch_deposit(int64_t np, const double* x, const double* y, const double* z,
                           const uint32_t* cs, double* rho, int n, double inv_h, double qh3,
-                          double rho_bg, DevState* st, double* part, hipStream_t s) {
+                          double rho_bg, DevState* st, double* part, double* const T[4],
+                          hipStream_t s) {
     const int64_t n3 = (int64_t)n * n * n;
     const int nb = pblocks(n3, deposit_partials());
     if (cs) {
-        hipLaunchKernelGGL(deposit_sorted_kernel, dim3(nb), dim3(kPT), 0, s, x, y, z, cs, rho, n,
-                           inv_h, qh3, rho_bg, part, st);
+        const int64_t waves = (int64_t)n * n * ((n + 62) / 63);
+        const int64_t blocks = (waves * 64 + kPT - 1) / kPT;
+        hipLaunchKernelGGL(deposit_cells_kernel, dim3((uint32_t)blocks), dim3(kPT), 0, s, x, y, z, cs,
+                           n, inv_h, T[0], T[1], T[2], T[3]);
+        hipLaunchKernelGGL(deposit_vertices_kernel, dim3(nb), dim3(kPT), 0, s, (const double*)T[0],
+                           (const double*)T[1], (const double*)T[2], (const double*)T[3], rho, n, qh3,
+                           rho_bg, part, st);
     } else {
         hipError_t e = launch_fill(n3, rho, 0.0, s);
         if (e != hipSuccess) return e;

@@ -21,9 +21,12 @@ hipError_t launch_half_kick(int64_t np, const double* x, const double* y, const 
 // Deposit + background + zero-mean projection; st->bb receives ||b||^2.
 // part must hold 2 * deposit_partials() doubles.
 int deposit_partials();
+// With cs (sorted particles) the four n^3 FP64 scratch arrays T hold the
+// per-cell-row partial sums between the two passes.
 hipError_t launch_deposit(int64_t np, const double* x, const double* y, const double* z,
                           const uint32_t* cs, double* rho, int n, double inv_h, double qh3,
-                          double rho_bg, DevState* st, double* part, hipStream_t s);
+                          double rho_bg, DevState* st, double* part, double* const T[4],
+                          hipStream_t s);
 
 // Stable LSD radix sort of cell keys (internal scratch sized by sort_scratch_bytes).
 struct SortScratch {

@@ -208,25 +208,21 @@ __global__ __launch_bounds__(256) void cell_start_kernel(int64_t np, int64_t nce
     }
 }
 
-__global__ __launch_bounds__(256) void permute_kernel(int64_t np, const uint32_t* __restrict__ perm,
-                                                      const double* __restrict__ s0,
-                                                      const double* __restrict__ s1,
-                                                      const double* __restrict__ s2,
-                                                      const double* __restrict__ s3,
-                                                      const double* __restrict__ s4,
-                                                      const double* __restrict__ s5,
-                                                      double* __restrict__ d0, double* __restrict__ d1,
-                                                      double* __restrict__ d2, double* __restrict__ d3,
-                                                      double* __restrict__ d4,
-                                                      double* __restrict__ d5) {
-    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < np; j += (int64_t)gridDim.x * 256) {
-        const uint32_t p = perm[j];
-        d0[j] = s0[p];
-        d1[j] = s1[p];
-        d2[j] = s2[p];
-        d3[j] = s3[p];
-        d4[j] = s4[p];
-        d5[j] = s5[p];
+// One payload array per launch: dst[j] = src[perm[j]].  Each workgroup
+// gathers one contiguous chunk of the sorted order; chunk ids are remapped so
+// that each XCD walks a contiguous range, whose sources (the particles of
+// neighbouring cells before the push) then stay in that XCD's L2 while the
+// rows around it are gathered.  Stores bypass L2 retention.
+constexpr int kPermChunk = 4096;
+__global__ __launch_bounds__(256) void permute1_kernel(int64_t np, const uint32_t* __restrict__ perm,
+                                                       const double* __restrict__ src,
+                                                       double* __restrict__ dst) {
+    const uint32_t lb = remap_xcd(blockIdx.x, gridDim.x);
+    const int64_t base = (int64_t)lb * kPermChunk;
+#pragma unroll 4
+    for (int k = threadIdx.x; k < kPermChunk; k += 256) {
+        const int64_t j = base + k;
+        if (j < np) __builtin_nontemporal_store(src[perm[j]], dst + j);
     }
 }
 
@@ -264,8 +260,9 @@ hipError_t launch_sort_cells(int64_t np, int64_t ncell, const uint32_t* key,
     hipLaunchKernelGGL(cell_start_kernel, dim3(nbc), dim3(256), 0, s, np, ncell, kin, cell_start);
     if (np > 0) {
         const int nbp = (int)((np + 255) / 256 < 16384 ? (np + 255) / 256 : 16384);
-        hipLaunchKernelGGL(permute_kernel, dim3(nbp), dim3(256), 0, s, np, iin, src[0], src[1], src[2],
-                           src[3], src[4], src[5], dst[0], dst[1], dst[2], dst[3], dst[4], dst[5]);
+        const uint32_t nchunk = (uint32_t)((np + kPermChunk - 1) / kPermChunk);
+        for (int a = 0; a < 6; ++a)
+            hipLaunchKernelGGL(permute1_kernel, dim3(nchunk), dim3(256), 0, s, np, iin, src[a], dst[a]);
         if (perm_out)
             hipLaunchKernelGGL(copy_u32_kernel, dim3(nbp), dim3(256), 0, s, np, iin, perm_out);
     }

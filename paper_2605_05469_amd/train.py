@@ -27,8 +27,11 @@ def log(*a):
 
 
 def generate_pairs(N=128, ppc=8, alphas=None, ks=(0.5, 1.0), steps=100, seed=5000, dt=0.05,
-                   rtol=1e-10, device="cuda", stride=1):
-    """Run the plain solver and keep (r_hat, e_hat) FP32 pairs on the device."""
+                   rtol=1e-10, device="cuda", stride=1, diffs=True):
+    """Run the plain solver and keep (r_hat, e_hat) FP32 pairs on the device.
+    With `diffs`, the step-to-step changes (b_t - b_{t-1}, phi_t - phi_{t-1})
+    are kept too: by linearity they are exact pairs as well, and they look like
+    the residual corrections the preconditioner sees inside the solve."""
     import torch
 
     import paper_2605_05469_amd as P
@@ -48,6 +51,7 @@ def generate_pairs(N=128, ppc=8, alphas=None, ks=(0.5, 1.0), steps=100, seed=500
             del parts
             sim.init()
             h = p.length / N
+            prev = None
             for s in range(steps):
                 info = sim.step(timed=False)
                 if s % stride:
@@ -56,6 +60,13 @@ def generate_pairs(N=128, ppc=8, alphas=None, ks=(0.5, 1.0), steps=100, seed=500
                 sc = torch.sqrt(torch.mean(b * b))
                 rhs.append((b / sc).float())
                 tgt.append((sim.phi / sc).float())
+                if diffs and prev is not None:
+                    db, dphi = b - prev[0], sim.phi - prev[1]
+                    sd = torch.sqrt(torch.mean(db * db))
+                    if float(sd) > 0:
+                        rhs.append((db / sd).float())
+                        tgt.append((dphi / sd).float())
+                prev = (b, sim.phi.clone()) if diffs else None
             log("run %d (k=%.2f alpha=%.3f): %d pairs, last solve %d iterations"
                 % (run, k, a, len(rhs), info["iterations"]))
             run += 1
@@ -63,8 +74,10 @@ def generate_pairs(N=128, ppc=8, alphas=None, ks=(0.5, 1.0), steps=100, seed=500
     return rhs, tgt
 
 
-def train(net, rhs, tgt, epochs=10, lr=1e-3, lam=1.0, seed=0, holdout=0.1, log_every=200):
-    """Adam over shuffled pairs; returns (train losses, held-out losses)."""
+def train(net, rhs, tgt, epochs=10, lr=1e-3, lam=1.0, seed=0, holdout=0.1, log_every=200,
+          max_seconds=None, on_epoch=None):
+    """Adam over shuffled pairs; returns (train losses, held-out losses).
+    Stops early (after the current pair) once `max_seconds` have passed."""
     rng = np.random.default_rng(seed)
     n = len(rhs)
     idx = rng.permutation(n)
@@ -78,6 +91,8 @@ def train(net, rhs, tgt, epochs=10, lr=1e-3, lam=1.0, seed=0, holdout=0.1, log_e
         order = rng.permutation(tr)
         for i in order:
             frac = step / max(1, total)
+            if max_seconds is not None:
+                frac = min(1.0, max(frac, (time.time() - t0) / max_seconds))
             cur_lr = lr * (0.5 * (1 + math.cos(math.pi * frac)) * 0.9 + 0.1)
             want = (step % log_every) == 0
             L = net.train_step(rhs[i], tgt[i], lam=lam, lr=cur_lr, want_loss=want)
@@ -86,8 +101,15 @@ def train(net, rhs, tgt, epochs=10, lr=1e-3, lam=1.0, seed=0, holdout=0.1, log_e
                 log("step %d/%d  loss %.4e  lr %.2e  %.1f s" % (step, total, L, cur_lr,
                                                                  time.time() - t0))
             step += 1
+            if max_seconds is not None and time.time() - t0 > max_seconds:
+                break
         hout.append(evaluate(net, rhs, tgt, hold, lam))
-        log("epoch %d: held-out loss %.4e" % (ep, hout[-1]))
+        log("epoch %d: held-out loss %.4e  (%d steps, %.1f s)" % (ep, hout[-1], step,
+                                                                 time.time() - t0))
+        if on_epoch is not None:
+            on_epoch(ep)
+        if max_seconds is not None and time.time() - t0 > max_seconds:
+            break
     return hist, hout
 
 
@@ -111,10 +133,15 @@ def evaluate(net, rhs, tgt, which, lam=1.0):
     return tot / max(1, len(which))
 
 
+# (name, in channels, out channels) in the library's parameter order: for each
+# layer the weights [cout][cin][3][3][3], then the biases [cout]
+LAYERS = [("e1a", 1, 16), ("e1b", 16, 16), ("e2a", 16, 32), ("e2b", 32, 32),
+          ("b3a", 32, 64), ("b3b", 64, 32), ("d2a", 32, 32), ("d2b", 32, 16),
+          ("d1a", 16, 16), ("out", 16, 1)]
+
+
 def init_params(seed=0):
     """He-normal weights, zero biases, canonical order (FP32 numpy)."""
-    from paper_2605_05469_amd import LAYERS
-
     rng = np.random.default_rng(seed)
     chunks = []
     for _, ci, co in LAYERS:
@@ -133,6 +160,10 @@ def main():
     ap.add_argument("--lam", type=float, default=1.0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default="unet_landau.npy")
+    ap.add_argument("--max-seconds", type=float, default=None,
+                    help="stop training after this many seconds (weights saved every epoch)")
+    ap.add_argument("--no-diffs", action="store_true",
+                    help="do not add the step-to-step difference pairs")
     args = ap.parse_args()
 
     import torch
@@ -141,17 +172,23 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.time()
-    rhs, tgt = generate_pairs(N=args.grid, ppc=args.ppc, steps=args.steps)
+    rhs, tgt = generate_pairs(N=args.grid, ppc=args.ppc, steps=args.steps,
+                              diffs=not args.no_diffs)
     log("generated %d pairs in %.1f s" % (len(rhs), time.time() - t0))
     net = P.Net(args.grid, training=True)
     net.set_params(torch.from_numpy(init_params(args.seed)).cuda())
-    t0 = time.time()
-    hist, hout = train(net, rhs, tgt, epochs=args.epochs, lr=args.lr, lam=args.lam, seed=args.seed)
-    log("trained in %.1f s" % (time.time() - t0))
     params = torch.empty(P.unet_param_count(), dtype=torch.float32, device="cuda")
-    net.get_params(params)
-    np.save(args.out, params.cpu().numpy())
-    log("saved %s" % args.out)
+
+    def save(ep):
+        net.get_params(params)
+        np.save(args.out, params.cpu().numpy())
+        log("saved %s after epoch %d" % (args.out, ep))
+
+    t0 = time.time()
+    hist, hout = train(net, rhs, tgt, epochs=args.epochs, lr=args.lr, lam=args.lam, seed=args.seed,
+                       max_seconds=args.max_seconds, on_epoch=save)
+    log("trained in %.1f s; held-out losses %s" % (time.time() - t0,
+                                                   " ".join("%.3e" % v for v in hout)))
 
 
 if __name__ == "__main__":

@@ -83,6 +83,36 @@ def test_conv3d_forward_backward_parity(pic, ci, co):
     assert rel(g[27 * ci * co:], db) <= 1e-5
 
 
+@pytest.mark.parametrize("n,ci,co", [(64, a, b) for a, b in PAIRS] + [(128, 16, 16), (128, 32, 16)])
+def test_conv3d_zmarch_parity(pic, n, ci, co):
+    """Grids that are multiples of 64 take the z-marching kernels (several
+    column tiles, z ranges and periodic wraps at these sizes)."""
+    rng = np.random.default_rng(n + ci * 100 + co)
+    x, W, b = _layer(rng, ci, co, n)
+    skip = unet.bf16(rng.standard_normal((co, n, n, n)))
+    Wd = f32dev(W.reshape(co, ci, 27))
+    ff = torch.empty(pic.conv3d_frag_elems(ci, co), dtype=torch.int16, device="cuda")
+    fb = torch.empty(pic.conv3d_frag_elems(co, ci), dtype=torch.int16, device="cuda")
+    pic.conv3d_pack(ci, co, Wd, ff, fb)
+    y = torch.empty((n, n, n, co), dtype=torch.bfloat16, device="cuda")
+    pic.conv3d_fwd(n, ci, co, cl_bf16(x), ff, f32dev(b), y, skip=cl_bf16(skip), relu=True)
+    ref = np.maximum(unet.conv3_fwd(x, unet.bf16(W), b) + skip, 0.0)
+    got = from_cl(y)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-6 * np.abs(ref).max())
+    # linear output (no relu, no skip) must keep negative values
+    pic.conv3d_fwd(n, ci, co, cl_bf16(x), ff, f32dev(b), y, relu=False)
+    ref = unet.conv3_fwd(x, unet.bf16(W), b)
+    got = from_cl(y)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-6 * np.abs(ref).max())
+    gy = unet.bf16(rng.standard_normal((co, n, n, n)))
+    gx = torch.empty((n, n, n, ci), dtype=torch.float32, device="cuda")
+    pic.conv3d_bwd_data(n, ci, co, cl_bf16(gy), fb, gx)
+    refx = unet.conv3_bwd_data(gy, unet.bf16(W))
+    assert rel(from_cl(gx), refx) <= 1e-5
+    pic.conv3d_bwd_data(n, ci, co, cl_bf16(gy), fb, gx, accumulate=True)
+    assert rel(from_cl(gx), 2 * refx) <= 1e-5
+
+
 def test_conv3d_rejects_unsupported(pic):
     assert pic.conv3d_frag_elems(8, 16) == 0
     w = torch.zeros(27 * 16 * 8, dtype=torch.float32, device="cuda")
@@ -113,8 +143,8 @@ def _params(seed):
     return p
 
 
-def test_network_forward_backward_parity(pic):
-    n = 16
+@pytest.mark.parametrize("n", [16, 64])
+def test_network_forward_backward_parity(pic, n):
     specs = unet.layer_specs()
     p = _params(5)
     flat = unet.flatten(p, specs)
