@@ -58,7 +58,6 @@ struct Net {
              *e2b = nullptr, *p2 = nullptr, *b3a = nullptr, *b3b = nullptr, *u2 = nullptr,
              *d2a = nullptr, *d2b = nullptr, *u1 = nullptr, *d1a = nullptr;
     float* out = nullptr;
-    float* xin = nullptr;       // FP32 staging of the input
     double* red = nullptr;      // reduction partials (+ tail for scalars)
     double* scal = nullptr;     // device scalars (s)
     double* zbuf = nullptr;
@@ -125,7 +124,9 @@ int create(Net** out, int n, bool training) {
     NALLOC(net->in, n1 * B);
     NALLOC(net->e1a, n1 * 16 * B);
     NALLOC(net->e1b, n1 * 16 * B);
-    NALLOC(net->d1a, n1 * 16 * B);
+    // inference with the fused up-sampling: d1a reuses e1a (dead after e1b)
+    if (training || !conv_up_fused(n, 16, 16)) NALLOC(net->d1a, n1 * 16 * B);
+    else net->d1a = net->e1a;
     NALLOC(net->p1, n2 * 16 * B);
     NALLOC(net->e2a, n2 * 32 * B);
     NALLOC(net->e2b, n2 * 32 * B);
@@ -138,12 +139,12 @@ int create(Net** out, int n, bool training) {
         NALLOC(net->u1, n1 * 16 * B);
         NALLOC(net->u2, n2 * 32 * B);
     } else {
-        // inference: u1 reuses e1a (dead after e1b); u2 reuses e2a (dead after e2b)
+        // inference: u1 reuses e1a (dead after e1b; unused when the
+        // up-sampling is fused); u2 reuses e2a (dead after e2b)
         net->u1 = net->e1a;
         net->u2 = net->e2a;
     }
     NALLOC(net->out, n1 * F);
-    NALLOC(net->xin, n1 * F);
     NALLOC(net->red, (size_t)(2 * loss_parts(n) + 2 * pre_parts(n1) + 64) * sizeof(double));
     NALLOC(net->scal, 64 * sizeof(double));
     if (training) {
@@ -223,11 +224,21 @@ static int fwd(Net* net, hipStream_t s) {
     NCHK(pool_fwd(q, 32, net->e2b, net->p2, s));
     NCHK(conv_fwd(q, 32, 64, net->p2, net->ffrag[B3A], Bi(B3A), nullptr, 1, net->b3a, s));
     NCHK(conv_fwd(q, 64, 32, net->b3a, net->ffrag[B3B], Bi(B3B), nullptr, 1, net->b3b, s));
-    NCHK(up_fwd(h, 32, net->b3b, net->u2, s));
-    NCHK(conv_fwd(h, 32, 32, net->u2, net->ffrag[D2A], Bi(D2A), net->e2b, 1, net->d2a, s));
+    // training keeps the up-sampled inputs (the weight gradients read them);
+    // inference up-samples inside the convolution's staging where it can
+    if (!net->training && conv_up_fused(h, 32, 32)) {
+        NCHK(conv_fwd_up(h, 32, 32, net->b3b, net->ffrag[D2A], Bi(D2A), net->e2b, 1, net->d2a, s));
+    } else {
+        NCHK(up_fwd(h, 32, net->b3b, net->u2, s));
+        NCHK(conv_fwd(h, 32, 32, net->u2, net->ffrag[D2A], Bi(D2A), net->e2b, 1, net->d2a, s));
+    }
     NCHK(conv_fwd(h, 32, 16, net->d2a, net->ffrag[D2B], Bi(D2B), nullptr, 1, net->d2b, s));
-    NCHK(up_fwd(n, 16, net->d2b, net->u1, s));
-    NCHK(conv_fwd(n, 16, 16, net->u1, net->ffrag[D1A], Bi(D1A), net->e1b, 1, net->d1a, s));
+    if (!net->training && conv_up_fused(n, 16, 16)) {
+        NCHK(conv_fwd_up(n, 16, 16, net->d2b, net->ffrag[D1A], Bi(D1A), net->e1b, 1, net->d1a, s));
+    } else {
+        NCHK(up_fwd(n, 16, net->d2b, net->u1, s));
+        NCHK(conv_fwd(n, 16, 16, net->u1, net->ffrag[D1A], Bi(D1A), net->e1b, 1, net->d1a, s));
+    }
     NCHK(conv_out_fwd(n, net->d1a, W(OUT), Bi(OUT), net->out, s));
     return 0;
 }

@@ -14,6 +14,12 @@ size_t frag_elems(int cin, int cout);
 hipError_t pack(const float* W, int ci, int co, int bwd, uint16_t* frag, hipStream_t s);
 hipError_t conv_fwd(int n, int ci, int co, const uint16_t* X, const uint16_t* frag,
                     const float* bias, const uint16_t* skip, int relu, uint16_t* Y, hipStream_t s);
+// Y = conv(up(Xc)) with Xc on the n/2 grid, up = nearest-neighbour 2x
+// up-sampling applied while staging (z-marching kernel only).
+bool conv_up_fused(int n, int ci, int co);
+hipError_t conv_fwd_up(int n, int ci, int co, const uint16_t* Xc, const uint16_t* frag,
+                       const float* bias, const uint16_t* skip, int relu, uint16_t* Y,
+                       hipStream_t s);
 hipError_t conv_bwd_data(int n, int ci, int co, const uint16_t* G, const uint16_t* frag_bwd,
                          float* dX, int accumulate, hipStream_t s);
 hipError_t conv_dw(int n, int ci, int co, const uint16_t* X, const uint16_t* G, float* part,

@@ -230,7 +230,9 @@ __global__ __launch_bounds__(kNT) void conv_mfma_kernel(int n, const uint16_t* _
 // gather kernel) once input plane z + 1 has been consumed.
 // Wave w computes output block w % NCB for the point tiles q, q + WQ, ... of
 // the plane (q = w / NCB, WQ = 4 / NCB).  Requires n % 64 == 0, n % TY == 0.
-template <int CI, int CO, int TY, int MODE>
+// UP: X is given on the n/2 grid and nearest-neighbour up-sampled while it is
+// staged (the decoder's up-sampling never materialises).
+template <int CI, int CO, int TY, int MODE, bool UP = false>
 __global__ __launch_bounds__(kNT) void conv_zm_kernel(int n, int zlen, const uint16_t* __restrict__ X,
                                                       const uint16_t* __restrict__ fragz,
                                                       const float* __restrict__ bias,
@@ -280,17 +282,23 @@ __global__ __launch_bounds__(kNT) void conv_zm_kernel(int n, int zlen, const uin
     }
 
     bf16x8 stg[NPT];
+    const int ns = UP ? n / 2 : n;  // grid of X
     auto load_plane = [&](int zp) {
-        const int zz = zp < 0 ? zp + n : (zp >= n ? zp - n : zp);
+        int zz = zp < 0 ? zp + n : (zp >= n ? zp - n : zp);
+        if constexpr (UP) zz >>= 1;
 #pragma unroll
         for (int i = 0; i < NPT; ++i) {
             const int c = threadIdx.x + kNT * i;
             if (c < NCH) {
                 const int cg = c % CG, pt = c / CG;
                 const int xx = pt % SX, yy = pt / SX;
-                const int x = wrapi(x0 - 1 + xx, n), y = wrapi(y0 - 1 + yy, n);
+                int x = wrapi(x0 - 1 + xx, n), y = wrapi(y0 - 1 + yy, n);
+                if constexpr (UP) {
+                    x >>= 1;
+                    y >>= 1;
+                }
                 stg[i] = *reinterpret_cast<const bf16x8*>(
-                    X + (((int64_t)zz * n + y) * n + x) * CI + cg * 8);
+                    X + (((int64_t)zz * ns + y) * ns + x) * CI + cg * 8);
             }
         }
     };
@@ -938,16 +946,28 @@ static int zm_zsplit(int n, int ncol) {
     return best;
 }
 
-template <int CI, int CO, int TY, int MODE>
+template <int CI, int CO, int TY, int MODE, bool UP = false>
 static hipError_t zm_launch(int n, const uint16_t* X, const uint16_t* frag, const float* bias,
                             const uint16_t* skip, int relu, uint16_t* Yb, float* Yf, int acc,
                             hipStream_t s) {
     const int ncol = (n / 64) * (n / TY);
     const int zs = zm_zsplit(n, ncol);
     const uint16_t* fz = frag + gather_frag_elems(CI, CO);
-    hipLaunchKernelGGL((conv_zm_kernel<CI, CO, TY, MODE>), dim3(ncol * zs), dim3(kNT), 0, s, n,
+    hipLaunchKernelGGL((conv_zm_kernel<CI, CO, TY, MODE, UP>), dim3(ncol * zs), dim3(kNT), 0, s, n,
                        n / zs, X, fz, bias, skip, relu, Yb, Yf, acc);
     return hipGetLastError();
+}
+
+bool conv_up_fused(int n, int ci, int co) {
+    return n % 64 == 0 && ((ci == 16 && co == 16) || (ci == 32 && co == 32));
+}
+
+hipError_t conv_fwd_up(int n, int ci, int co, const uint16_t* Xc, const uint16_t* frag,
+                       const float* bias, const uint16_t* skip, int relu, uint16_t* Y,
+                       hipStream_t s) {
+    if (!conv_up_fused(n, ci, co)) return hipErrorInvalidValue;
+    if (ci == 16) return zm_launch<16, 16, 8, 0, true>(n, Xc, frag, bias, skip, relu, Y, nullptr, 0, s);
+    return zm_launch<32, 32, 4, 0, true>(n, Xc, frag, bias, skip, relu, Y, nullptr, 0, s);
 }
 
 template <int CI, int CO, int NG, int MODE>

@@ -194,8 +194,10 @@ def test_train_step_loss_and_descent(pic):
     assert losses[-1] < 0.9 * L0
 
 
-def test_preconditioner_parity_and_homogeneity(pic):
-    n = 16
+@pytest.mark.parametrize("n", [16, 64, 128])
+def test_preconditioner_parity_and_homogeneity(pic, n):
+    """Inference network (at 64^3 and 128^3 the decoder up-sampling is fused
+    into the convolutions' staging and buffers are shared)."""
     specs = unet.layer_specs()
     p = _params(9)
     net = pic.Net(n)
