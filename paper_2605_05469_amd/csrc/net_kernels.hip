@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "net.hpp"
 
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(kNT) void conv_mfma_kernel(int n, const uint16_t* _
 // UP: X is given on the n/2 grid and nearest-neighbour up-sampled while it is
 // staged (the decoder's up-sampling never materialises).
 template <int CI, int CO, int TY, int MODE, bool UP = false>
-__global__ __launch_bounds__(kNT) void conv_zm_kernel(int n, int zlen, const uint16_t* __restrict__ X,
+__global__ __launch_bounds__(kNT, (CI == 16 && MODE == 0) ? 2 : 1) void conv_zm_kernel(int n, int zlen, const uint16_t* __restrict__ X,
                                                       const uint16_t* __restrict__ fragz,
                                                       const float* __restrict__ bias,
                                                       const uint16_t* __restrict__ skip, int relu,
@@ -267,13 +269,14 @@ __global__ __launch_bounds__(kNT) void conv_zm_kernel(int n, int zlen, const uin
 #pragma unroll
         for (int s = 0; s < KSP; ++s) w[d][s] = fz[((d * KSP + s) * NCB + cb) * 64 + lane];
     // LDS offset (in records, within a plane buffer) of this lane's B row
-    // for each K-chunk, before the tile offset; -1 = zero padding
+    // for each K-chunk, before the tile offset
     int boff[KSP];
 #pragma unroll
     for (int s = 0; s < KSP; ++s) {
         const int k0 = 32 * s + 8 * g;
         const int u = k0 / CI, c0 = k0 - u * CI;
-        boff[s] = u < 9 ? ((c0 / 8) * SY + u / 3) * SX + (u % 3) + m : -1;
+        // padded K entries (u >= 9) have zero weights: read any valid record
+        boff[s] = u < 9 ? ((c0 / 8) * SY + u / 3) * SX + (u % 3) + m : m;
     }
     float bv[4] = {0.f, 0.f, 0.f, 0.f};
     if constexpr (MODE == 0) {
@@ -320,15 +323,50 @@ __global__ __launch_bounds__(kNT) void conv_zm_kernel(int n, int zlen, const uin
 #pragma unroll
         for (int j = 0; j < PW; ++j) acc[a][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    load_plane(zb - 1);
-    store_plane(0);
-    __syncthreads();
+    // Output plane z lives in accumulator slot (z - zb + 1) mod 3; the loop
+    // is unrolled by three planes so every slot index is a constant.  The
+    // partial sums of the two planes below zb and of plane ze are computed
+    // and dropped (no branches around the MFMAs).
+    auto epilogue = [&](const f32x4(&a)[PW], int z) {
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            const int T = q + WQ * j;
+            const int64_t p = ((int64_t)z * n + y0 + (T >> 2)) * n + x0 + 16 * (T & 3) + m;
+            const int co0 = 16 * cb + 4 * g;
+            if constexpr (MODE == 0) {
+                float y[4];
+                uint2 sk = make_uint2(0u, 0u);
+                if (skip) sk = *reinterpret_cast<const uint2*>(skip + p * CO + co0);
+                const uint16_t* sh = reinterpret_cast<const uint16_t*>(&sk);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    y[i] = a[j][i] + bv[i];
+                    if (skip) y[i] += bf2f(sh[i]);
+                    if (relu) y[i] = y[i] > 0.f ? y[i] : 0.f;
+                }
+                uint2 o;
+                o.x = (uint32_t)f2bf(y[0]) | ((uint32_t)f2bf(y[1]) << 16);
+                o.y = (uint32_t)f2bf(y[2]) | ((uint32_t)f2bf(y[3]) << 16);
+                *reinterpret_cast<uint2*>(Yb + p * CO + co0) = o;
+            } else {
+                float4 o = make_float4(a[j][0], a[j][1], a[j][2], a[j][3]);
+                float4* dst = reinterpret_cast<float4*>(Yf + p * CO + co0);
+                if (accumulate) {
+                    const float4 prev = *dst;
+                    o.x += prev.x;
+                    o.y += prev.y;
+                    o.z += prev.z;
+                    o.w += prev.w;
+                }
+                *dst = o;
+            }
+        }
+    };
     int buf = 0;
-    for (int zp = zb - 1; zp <= ze; ++zp) {
+    auto step = [&](int zp, auto rc) {
+        constexpr int r = decltype(rc)::value;
+        constexpr int sH = (r + 1) % 3, sM = r, sL = (r + 2) % 3;  // planes zp+1, zp, zp-1
         if (zp < ze) load_plane(zp + 1);
-        const bool lo = zp - 1 >= zb;  // output plane zp - 1 is ours
-        const bool mid = zp >= zb && zp < ze;
-        const bool hi = zp + 1 < ze;
         const bf16x8* L = lds + buf * NCH;
 #pragma unroll
         for (int j = 0; j < PW; ++j) {
@@ -336,57 +374,26 @@ __global__ __launch_bounds__(kNT) void conv_zm_kernel(int n, int zlen, const uin
             const int toff = (T >> 2) * SX + 16 * (T & 3);
 #pragma unroll
             for (int s = 0; s < KSP; ++s) {
-                const bf16x8 b = boff[s] >= 0 ? L[boff[s] + toff] : bf16x8{};
-                if (hi) acc[2][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0][s], b, acc[2][j], 0, 0, 0);
-                if (mid) acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1][s], b, acc[1][j], 0, 0, 0);
-                if (lo) acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[2][s], b, acc[0][j], 0, 0, 0);
+                const bf16x8 b = L[boff[s] + toff];
+                acc[sH][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0][s], b, acc[sH][j], 0, 0, 0);
+                acc[sM][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1][s], b, acc[sM][j], 0, 0, 0);
+                acc[sL][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[2][s], b, acc[sL][j], 0, 0, 0);
             }
         }
-        if (lo) {
-            const int z = zp - 1;
+        if (zp - 1 >= zb) epilogue(acc[sL], zp - 1);
 #pragma unroll
-            for (int j = 0; j < PW; ++j) {
-                const int T = q + WQ * j;
-                const int64_t p = ((int64_t)z * n + y0 + (T >> 2)) * n + x0 + 16 * (T & 3) + m;
-                const int co0 = 16 * cb + 4 * g;
-                if constexpr (MODE == 0) {
-                    float y[4];
-                    uint2 sk = make_uint2(0u, 0u);
-                    if (skip) sk = *reinterpret_cast<const uint2*>(skip + p * CO + co0);
-                    const uint16_t* sh = reinterpret_cast<const uint16_t*>(&sk);
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        y[i] = acc[0][j][i] + bv[i];
-                        if (skip) y[i] += bf2f(sh[i]);
-                        if (relu) y[i] = y[i] > 0.f ? y[i] : 0.f;
-                    }
-                    uint2 o;
-                    o.x = (uint32_t)f2bf(y[0]) | ((uint32_t)f2bf(y[1]) << 16);
-                    o.y = (uint32_t)f2bf(y[2]) | ((uint32_t)f2bf(y[3]) << 16);
-                    *reinterpret_cast<uint2*>(Yb + p * CO + co0) = o;
-                } else {
-                    float4 o = make_float4(acc[0][j][0], acc[0][j][1], acc[0][j][2], acc[0][j][3]);
-                    float4* dst = reinterpret_cast<float4*>(Yf + p * CO + co0);
-                    if (accumulate) {
-                        const float4 prev = *dst;
-                        o.x += prev.x;
-                        o.y += prev.y;
-                        o.z += prev.z;
-                        o.w += prev.w;
-                    }
-                    *dst = o;
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < PW; ++j) {
-            acc[0][j] = acc[1][j];
-            acc[1][j] = acc[2][j];
-            acc[2][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        }
+        for (int j = 0; j < PW; ++j) acc[sL][j] = f32x4{0.f, 0.f, 0.f, 0.f};
         if (zp < ze) store_plane(buf ^ 1);
         __syncthreads();
         buf ^= 1;
+    };
+    load_plane(zb - 1);
+    store_plane(0);
+    __syncthreads();
+    for (int zp = zb - 1; zp <= ze; zp += 3) {
+        step(zp, std::integral_constant<int, 0>{});
+        if (zp + 1 <= ze) step(zp + 1, std::integral_constant<int, 1>{});
+        if (zp + 2 <= ze) step(zp + 2, std::integral_constant<int, 2>{});
     }
 }
 
@@ -506,40 +513,58 @@ __global__ void fill_f32_kernel(int64_t n, float* __restrict__ a, float v) {
 // Weights are rounded to BF16 like the MFMA layers' (emulated in FP32).
 __device__ __forceinline__ float wbf(float w) { return bf2f(f2bf(w)); }
 
-// e1a: y[p][co] = relu(b[co] + sum_t W[co][0][t] x[p + d_t]), 16 outputs.
+// e1a: y[p][co] = relu(b[co] + sum_t W[co][0][t] x[p + d_t]), 16 outputs, on
+// the matrix cores: the 27 taps of the single input channel (zero-padded to
+// 32) are the K dimension of one v_mfma_f32_16x16x32_bf16 per 16 points;
+// lane (m, g) gathers taps 8g..8g+7 of point m (cached 2-byte loads).
 __global__ __launch_bounds__(kNT) void conv_in_fwd_kernel(int n, const uint16_t* __restrict__ x,
                                                           const float* __restrict__ W,
                                                           const float* __restrict__ b,
                                                           uint16_t* __restrict__ y) {
-    __shared__ float ws[16 * 27];
-    __shared__ float bs[16];
-    for (int i = threadIdx.x; i < 16 * 27; i += kNT) ws[i] = wbf(W[i]);
-    if (threadIdx.x < 16) bs[threadIdx.x] = b[threadIdx.x];
-    __syncthreads();
-    const int64_t n3 = (int64_t)n * n * n;
-    for (int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x; p < n3; p += (int64_t)gridDim.x * kNT) {
-        const Pt pt = decomp(p, n);
-        float v[27];
+    constexpr int PT = 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    bf16x8 a;
+    uint16_t* ah = reinterpret_cast<uint16_t*>(&a);
 #pragma unroll
-        for (int t = 0; t < 27; ++t) v[t] = bf2f(x[nbr(pt, t, n)]);
-        uint32_t o[8];
+    for (int i = 0; i < 8; ++i) {
+        const int t = 8 * g + i;
+        ah[i] = t < 27 ? f2bf(W[m * 27 + t]) : (uint16_t)0;
+    }
+    float bv[4];
 #pragma unroll
-        for (int c = 0; c < 16; c += 2) {
-            float a0 = 0.f, a1 = 0.f;
+    for (int i = 0; i < 4; ++i) bv[i] = b[4 * g + i];
+    const int64_t ntiles = (int64_t)n * n * n / 16;
+    for (int64_t t0 = ((int64_t)blockIdx.x * 4 + wave) * PT; t0 < ntiles;
+         t0 += (int64_t)gridDim.x * 4 * PT) {
+        bf16x8 bb[PT];
 #pragma unroll
-            for (int t = 0; t < 27; ++t) {
-                a0 += ws[c * 27 + t] * v[t];
-                a1 += ws[(c + 1) * 27 + t] * v[t];
+        for (int j = 0; j < PT; ++j) {
+            const int64_t tile = t0 + j < ntiles ? t0 + j : t0;
+            const Pt pt = decomp(tile * 16 + m, n);
+            uint16_t* bh = reinterpret_cast<uint16_t*>(&bb[j]);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int t = 8 * g + i;
+                bh[i] = t < 27 ? x[nbr(pt, t, n)] : (uint16_t)0;
             }
-            a0 += bs[c];
-            a1 += bs[c + 1];
-            a0 = a0 > 0.f ? a0 : 0.f;
-            a1 = a1 > 0.f ? a1 : 0.f;
-            o[c / 2] = (uint32_t)f2bf(a0) | ((uint32_t)f2bf(a1) << 16);
         }
-        uint4* dst = reinterpret_cast<uint4*>(y + p * 16);
-        dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
-        dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
+#pragma unroll
+        for (int j = 0; j < PT; ++j) {
+            if (t0 + j >= ntiles) continue;
+            const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bb[j], f32x4{0.f, 0.f, 0.f, 0.f},
+                                                                     0, 0, 0);
+            float v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[i] = acc[i] + bv[i];
+                v[i] = v[i] > 0.f ? v[i] : 0.f;
+            }
+            uint2 o;
+            o.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+            o.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+            *reinterpret_cast<uint2*>(y + ((t0 + j) * 16 + m) * 16 + 4 * g) = o;
+        }
     }
 }
 
@@ -567,6 +592,137 @@ __global__ __launch_bounds__(kNT) void conv_out_fwd_kernel(int n, const uint16_t
             for (int c = 0; c < 8; ++c) s += ws[(c + 8) * 27 + t] * bf2f(h1[c]);
         }
         o[p] = s + bptr[0];
+    }
+}
+
+// out on the matrix cores, z-marching (n % 64 == 0): staging as in
+// conv_zm_kernel<16, ...>; the MFMA's A operand is the staged activations
+// (16 points x 32 of (in-plane tap, channel)), its B operand the weights with
+// one column per output plane, so one MFMA chain per K-chunk serves all three
+// output planes an input plane touches (a third of the work of a 16-output
+// layer).  Column c accumulates the output planes z = c (mod 3): for input
+// plane zp, column c holds tap plane dzi = (zp - c + 1) mod 3 of the weights.
+// After input plane zp, output plane zp - 1 is complete in column
+// (zp - 1) mod 3: its lanes add the bias, store 4 consecutive x (FP32) and
+// clear that column for plane zp + 2.
+template <int TY>
+__global__ __launch_bounds__(kNT, 2) void conv_out_zm_kernel(int n, int zlen,
+                                                          const uint16_t* __restrict__ X,
+                                                          const float* __restrict__ W,
+                                                          const float* __restrict__ bptr,
+                                                          float* __restrict__ o) {
+    constexpr int CI = 16;
+    constexpr int TX = 64, SX = TX + 2, SY = TY + 2;
+    constexpr int CG = CI / 8;
+    constexpr int KSP = (9 * CI + 31) / 32;
+    constexpr int NTILE = 4 * TY;
+    constexpr int PW = NTILE / 4;
+    constexpr int NCH = SY * SX * CG;
+    constexpr int NPT = (NCH + kNT - 1) / kNT;
+    __shared__ bf16x8 lds[2 * NCH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int ntx = n / TX;
+    const int ncol = ntx * (n / TY);
+    const int bid = (int)remap_xcd(blockIdx.x, gridDim.x);
+    const int col = bid % ncol;
+    const int zb = (bid / ncol) * zlen, ze = zb + zlen;
+    const int x0 = (col % ntx) * TX, y0 = (col / ntx) * TY;
+
+    // B fragments: wf[ph][s], lane (m, g): B[k = 32 s + 8 g + i][column m]
+    bf16x8 wf[3][KSP];
+#pragma unroll
+    for (int ph = 0; ph < 3; ++ph)
+#pragma unroll
+        for (int s2 = 0; s2 < KSP; ++s2) {
+            uint16_t* wh = reinterpret_cast<uint16_t*>(&wf[ph][s2]);
+            const int dzi = (ph - m + 1 + 3 * 16) % 3;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int k = 32 * s2 + 8 * g + i;
+                const int u = k / CI, c = k - u * CI;
+                wh[i] = (m < 3 && u < 9) ? f2bf(W[c * 27 + 9 * dzi + u]) : (uint16_t)0;
+            }
+        }
+    int boff[KSP];
+#pragma unroll
+    for (int s2 = 0; s2 < KSP; ++s2) {
+        const int k0 = 32 * s2 + 8 * g;
+        const int u = k0 / CI, c0 = k0 - u * CI;
+        boff[s2] = u < 9 ? ((c0 / 8) * SY + u / 3) * SX + (u % 3) + m : m;  // padding: weight 0
+    }
+    const float bias = bptr[0];
+
+    bf16x8 stg[NPT];
+    auto load_plane = [&](int zp) {
+        const int zz = zp < 0 ? zp + n : (zp >= n ? zp - n : zp);
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int c = threadIdx.x + kNT * i;
+            if (c < NCH) {
+                const int cg = c % CG, pt = c / CG;
+                const int xx = pt % SX, yy = pt / SX;
+                const int x = wrapi(x0 - 1 + xx, n), y = wrapi(y0 - 1 + yy, n);
+                stg[i] = *reinterpret_cast<const bf16x8*>(
+                    X + (((int64_t)zz * n + y) * n + x) * CI + cg * 8);
+            }
+        }
+    };
+    auto store_plane = [&](int b) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int c = threadIdx.x + kNT * i;
+            if (c < NCH) {
+                const int cg = c % CG, pt = c / CG;
+                const int xx = pt % SX, yy = pt / SX;
+                lds[b * NCH + (cg * SY + yy) * SX + xx] = stg[i];
+            }
+        }
+    };
+
+    f32x4 acc[PW];
+#pragma unroll
+    for (int j = 0; j < PW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    load_plane(zb - 1);
+    store_plane(0);
+    __syncthreads();
+    int buf = 0;
+    for (int zp = zb - 1; zp <= ze; ++zp) {
+        if (zp < ze) load_plane(zp + 1);
+        const int ph = (zp + 3) % 3;
+        const bf16x8* L = lds + buf * NCH;
+        auto plane = [&](const bf16x8(&w)[KSP]) {
+#pragma unroll
+            for (int j = 0; j < PW; ++j) {
+                const int T = wave + 4 * j;
+                const int toff = (T >> 2) * SX + 16 * (T & 3);
+#pragma unroll
+                for (int s2 = 0; s2 < KSP; ++s2) {
+                    const bf16x8 av = L[boff[s2] + toff];
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w[s2], acc[j], 0, 0, 0);
+                }
+            }
+        };
+        if (ph == 0) plane(wf[0]);
+        else if (ph == 1) plane(wf[1]);
+        else plane(wf[2]);
+        const int co = (zp + 2) % 3;  // column of output plane zp - 1
+        if (m == co) {
+            const int z = zp - 1;
+#pragma unroll
+            for (int j = 0; j < PW; ++j) {
+                if (z >= zb) {
+                    const int T = wave + 4 * j;
+                    const int64_t p = ((int64_t)z * n + y0 + (T >> 2)) * n + x0 + 16 * (T & 3) + 4 * g;
+                    *reinterpret_cast<float4*>(o + p) =
+                        make_float4(acc[j][0] + bias, acc[j][1] + bias, acc[j][2] + bias, acc[j][3] + bias);
+                }
+                acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+        }
+        if (zp < ze) store_plane(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
 }
 
@@ -1072,13 +1228,22 @@ size_t dw_part_elems(int n, int ci, int co) {
 
 hipError_t conv_in_fwd(int n, const uint16_t* x, const float* W, const float* b, uint16_t* y,
                        hipStream_t s) {
-    hipLaunchKernelGGL(conv_in_fwd_kernel, dim3(blocks_for((int64_t)n * n * n)), dim3(kNT), 0, s, n,
+    const int64_t ntiles = (int64_t)n * n * n / 16;
+    hipLaunchKernelGGL(conv_in_fwd_kernel, dim3(blocks_for(ntiles, 16, 8192)), dim3(kNT), 0, s, n,
                        x, W, b, y);
     return hipGetLastError();
 }
 
 hipError_t conv_out_fwd(int n, const uint16_t* a, const float* W, const float* b, float* o,
                         hipStream_t s) {
+    if (n % 64 == 0) {
+        constexpr int TY = 8;
+        const int ncol = (n / 64) * (n / TY);
+        const int zs = zm_zsplit(n, ncol);
+        hipLaunchKernelGGL(conv_out_zm_kernel<TY>, dim3(ncol * zs), dim3(kNT), 0, s, n, n / zs, a, W,
+                           b, o);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(conv_out_fwd_kernel, dim3(blocks_for((int64_t)n * n * n)), dim3(kNT), 0, s, n,
                        a, W, b, o);
     return hipGetLastError();

@@ -53,7 +53,7 @@ def generate_pairs(N=128, ppc=8, alphas=None, ks=(0.5, 1.0), steps=100, seed=500
             h = p.length / N
             prev = None
             for s in range(steps):
-                info = sim.step(timed=False)
+                info = sim.step()
                 if s % stride:
                     continue
                 b = sim.rho * (h * h)
@@ -141,11 +141,19 @@ LAYERS = [("e1a", 1, 16), ("e1b", 16, 16), ("e2a", 16, 32), ("e2b", 32, 32),
 
 
 def init_params(seed=0):
-    """He-normal weights, zero biases, canonical order (FP32 numpy)."""
+    """He-normal weights, zero biases, canonical order (FP32 numpy).  The
+    output layer starts at zero: the network's first output is 0 (loss 2), and
+    its gradient reaches the hidden layers only after the first steps.  With a
+    random output layer the first losses are O(10) (the A-term amplifies a
+    random output by up to 12x) and Adam at batch size 1 drives every ReLU of a
+    layer dead within a few hundred steps (the loss then stays at exactly 2)."""
     rng = np.random.default_rng(seed)
     chunks = []
-    for _, ci, co in LAYERS:
-        chunks.append((rng.standard_normal(27 * ci * co) * math.sqrt(2.0 / (27 * ci))).astype(np.float32))
+    for name, ci, co in LAYERS:
+        w = (rng.standard_normal(27 * ci * co) * math.sqrt(2.0 / (27 * ci))).astype(np.float32)
+        if name == "out":
+            w[:] = 0.0
+        chunks.append(w)
         chunks.append(np.zeros(co, dtype=np.float32))
     return np.concatenate(chunks)
 
