@@ -151,21 +151,25 @@ def bench_poisson(args):
     p = P.landau_params(N, ppc, rtol=args.rtol, solver="pcg_fp64", check_every=32,
                         inner_rtol=args.inner_rtol)
     if args.no_warm_start:
-        p.reserved = 1
+        p.flags = P.FLAG_NO_WARM_START
     ctx = P.Context(p)
     parts = synth.landau_particles_torch(N, ppc, seed=args.seed, device="cuda")
     rho = torch.empty(N ** 3, dtype=torch.float64, device="cuda")
     ctx.deposit(parts[0], parts[1], parts[2], None, rho)
     del parts
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # the library allocates the network outside torch
     forms = {}
-    for solver in ("pcg_fp64", "pcg_mixed", "fcg_learned"):
+    for form in ("pcg_fp64", "pcg_mixed", "fcg_learned", "learned_warm_start_only"):
+        solver = "fcg_learned" if form.startswith("learned") else form
         if solver == "fcg_learned":
             try:
                 load_weights(ctx, args.weights)
             except (OSError, ValueError) as e:
-                forms[solver] = {"skipped": repr(e)}
+                forms[form] = {"skipped": repr(e)}
                 continue
+        ctx.set_flags((P.FLAG_NO_WARM_START if args.no_warm_start else 0)
+                      | (P.FLAG_WARM_START_ONLY if form.startswith("learned_") else 0))
         ctx.set_solver(solver)
         phi = torch.zeros_like(rho)
         torch.cuda.synchronize()
@@ -173,12 +177,12 @@ def bench_poisson(args):
         info = ctx.poisson(rho, phi)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        forms[solver] = {"s_per_solve": dt, "iterations": info["iterations"],
+        forms[form] = {"s_per_solve": dt, "iterations": info["iterations"],
                          "outer_iterations": info["outer_iterations"],
                          "flex_iterations": info["flex_iterations"],
                          "fell_back": info["fell_back"], "warm_start_used": info["warm_start_used"],
                          "rel_res": info["rel_res"], "converged": bool(info["converged"])}
-        log("%s: %.3f s, %d iterations, rel_res %.2e" % (solver, dt, info["iterations"],
+        log("%s: %.3f s, %d iterations, rel_res %.2e" % (form, dt, info["iterations"],
                                                          info["rel_res"]))
     sel = forms.get(args.solver, {})
     n3 = N ** 3
@@ -208,6 +212,8 @@ def main():
                     help="FP32 network parameters (.npy, canonical order) for fcg_learned")
     ap.add_argument("--inner-rtol", type=float, default=1e-3)
     ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--warm-start-only", action="store_true",
+                    help="learned form: network warm start, then Jacobi-PCG")
     ap.add_argument("--accuracy-vs-fp64", action="store_true",
                     help="rerun the same steps with the FP64 solver and report the differences")
     ap.add_argument("--workload", default="pic", choices=["pic", "poisson"],
@@ -231,7 +237,9 @@ def main():
     p = P.landau_params(N, ppc, rtol=args.rtol, solver=args.solver, check_every=32,
                         inner_rtol=args.inner_rtol)
     if args.no_warm_start:
-        p.reserved = 1
+        p.flags |= P.FLAG_NO_WARM_START
+    if args.warm_start_only:
+        p.flags |= P.FLAG_WARM_START_ONLY
     ctx = P.Context(p)
     if args.solver == "fcg_learned":
         load_weights(ctx, args.weights)

@@ -55,6 +55,11 @@ enum {
 };
 
 /* Problem statement (Sec. 2 and 2.1; tolerance as in Sec. 4). */
+/* pic_params.flags (learned form): */
+#define PIC_FLAG_NO_WARM_START 1   /* no network warm start */
+#define PIC_FLAG_WARM_START_ONLY 2 /* warm start, then Jacobi-PCG (no flexible
+                                      preconditioning) */
+
 typedef struct pic_params {
     int32_t n;            /* grid points per axis N                         */
     int32_t ppc;          /* particles per cell (informational)             */
@@ -72,7 +77,7 @@ typedef struct pic_params {
     int64_t max_inner;    /* mixed: inner iteration cap per refinement step */
     int64_t max_outer;    /* mixed: refinement step cap                     */
     int32_t fcg_window;   /* learned: stall window (iterations)             */
-    int32_t reserved;     /* bit 0 set: learned form without network warm start */
+    int32_t flags;        /* learned form only: PIC_FLAG_* bits (above) */
 } pic_params;
 
 /* Host-side result of one Poisson solve. */
@@ -129,6 +134,8 @@ size_t pic_workspace_bytes(const pic_params *params);
 const char *pic_last_error(void);
 /* Change the solver form (allocates the extra scratch it needs, once). */
 int pic_set_solver(pic_ctx *ctx, int32_t solver);
+/* Replace pic_params.flags. */
+int pic_set_flags(pic_ctx *ctx, int32_t flags);
 /* Library ABI version. */
 int pic_abi_version(void);
 

@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 PIC_OK, PIC_NOT_CONVERGED = 0, 1
 PIC_ERR_INVALID, PIC_ERR_HIP, PIC_ERR_NOMEM, PIC_ERR_STATE = -1, -2, -3, -4
 SOLVERS = {"pcg_fp64": 0, "pcg_mixed": 1, "fcg_learned": 2}
+FLAG_NO_WARM_START = 1
+FLAG_WARM_START_ONLY = 2
 
 
 class PicError(RuntimeError):
@@ -34,7 +36,7 @@ class pic_params(ctypes.Structure):
                 ("solver", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("max_inner", ctypes.c_int64),
                 ("max_outer", ctypes.c_int64), ("fcg_window", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("flags", ctypes.c_int32)]
 
 
 class pic_solve_info(ctypes.Structure):
@@ -78,7 +80,7 @@ _lib = None
 
 # every entry point declared in include/pic.h
 EXPORTS = ["pic_create", "pic_destroy", "pic_workspace_bytes", "pic_last_error",
-           "pic_set_solver", "pic_abi_version", "pic_cell_keys", "pic_sort_cells",
+           "pic_set_solver", "pic_set_flags", "pic_abi_version", "pic_cell_keys", "pic_sort_cells",
            "pic_deposit_cic", "pic_poisson_pcg", "pic_gather_push", "pic_half_kick",
            "pic_efield", "pic_init", "pic_step", "pic_set_kernel_timing", "pic_kernel_time",
            "pic_unet_param_count", "pic_set_unet", "pic_unet_precondition", "pic_net_create",
@@ -106,6 +108,7 @@ def lib():
     L.pic_workspace_bytes.restype = ctypes.c_size_t
     L.pic_last_error.restype = ctypes.c_char_p
     L.pic_set_solver.argtypes = [vp, i32]
+    L.pic_set_flags.argtypes = [vp, i32]
     L.pic_cell_keys.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     L.pic_sort_cells.argtypes = [vp, i64, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]
     L.pic_deposit_cic.argtypes = [vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]
@@ -212,6 +215,10 @@ class Context:
     def set_solver(self, solver):
         s = SOLVERS[solver] if isinstance(solver, str) else int(solver)
         _check(lib().pic_set_solver(self._h, s))
+
+    def set_flags(self, flags: int):
+        """FLAG_NO_WARM_START | FLAG_WARM_START_ONLY (learned form)."""
+        _check(lib().pic_set_flags(self._h, int(flags)))
 
     def cell_keys(self, x, y, z, key, stream=None):
         import torch

@@ -101,6 +101,8 @@ static int validate_params(const pic_params* p) {
     if (!std::isfinite(p->charge) || !std::isfinite(p->qm) || !std::isfinite(p->dt) ||
         !std::isfinite(p->rho_bg))
         return fail(PIC_ERR_INVALID, "charge, qm, dt and rho_bg must be finite");
+    if (p->flags & ~(PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY))
+        return fail(PIC_ERR_INVALID, "unknown flags 0x%x", p->flags);
     return PIC_OK;
 }
 
@@ -397,7 +399,7 @@ static int solve_learned(pic_ctx* c, const double* b, double* x, pic_solve_info*
         return PIC_OK;
     }
     // warm start: x + M(r), kept only if it lowers the true residual
-    if (!(c->p.reserved & 1)) {
+    if (!(c->p.flags & PIC_FLAG_NO_WARM_START)) {
         RETCHK(fcg_precond(c, c->r, c->fz, s));
         HIPCHK(launch_axpy_copy(n3, x, c->fz, c->fw, s));
         HIPCHK(launch_resid_norm(g, b, c->fw, c->fq, c->inv_h2, c->st, c->partials, s));
@@ -414,6 +416,17 @@ static int solve_learned(pic_ctx* c, const double* b, double* x, pic_solve_info*
                 return PIC_OK;
             }
         }
+    }
+    if (c->p.flags & PIC_FLAG_WARM_START_ONLY) {
+        // warm start only: Jacobi-PCG from the (possibly corrected) iterate
+        pic_solve_info pi;
+        std::memset(&pi, 0, sizeof pi);
+        RETCHK(solve_fp64(c, b, x, &pi, s, c->p.max_iter));
+        out->iterations = pi.iterations;
+        out->replacements += pi.replacements;
+        out->rel_res = pi.rel_res;
+        out->converged = pi.converged;
+        return PIC_OK;
     }
     double* p = c->p2[0];
     int64_t it = 0;
@@ -616,6 +629,14 @@ int pic_set_solver(pic_ctx* c, int32_t solver) {
     if (solver == PIC_SOLVER_PCG_MIXED) RETCHK(ensure_mixed(c));
     if (solver == PIC_SOLVER_FCG_LEARNED) RETCHK(ensure_learned(c));
     c->p.solver = solver;
+    return PIC_OK;
+}
+
+int pic_set_flags(pic_ctx* c, int32_t flags) {
+    if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
+    if (flags & ~(PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY))
+        return fail(PIC_ERR_INVALID, "unknown flags 0x%x", flags);
+    c->p.flags = flags;
     return PIC_OK;
 }
 

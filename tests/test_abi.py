@@ -49,7 +49,7 @@ def test_abi_version_and_errors_without_gpu(lib):
     assert lib.pic_workspace_bytes(ctypes.byref(p)) > 3 * 8 * 32 ** 3
     h = ctypes.c_void_p()
     for field, bad in (("n", 33), ("n", 16), ("n", 2048), ("rtol", 0.0), ("length", -1.0),
-                       ("solver", 7), ("np_max", -5)):
+                       ("solver", 7), ("np_max", -5), ("flags", 4)):
         q = P.landau_params(32, 8)
         setattr(q, field, bad)
         assert lib.pic_workspace_bytes(ctypes.byref(q)) == 0
@@ -61,6 +61,7 @@ def test_abi_version_and_errors_without_gpu(lib):
     assert lib.pic_poisson_pcg(None, None, None, None, None, None, None, None) == P.PIC_ERR_INVALID
     assert lib.pic_gather_push(None, 0, *([None] * 10), None) == P.PIC_ERR_INVALID
     assert lib.pic_deposit_cic(None, 0, None, None, None, None, None, None, None) == P.PIC_ERR_INVALID
+    assert lib.pic_set_flags(None, 0) == P.PIC_ERR_INVALID
 
 
 def test_single_hip_runtime_is_loaded(lib):

@@ -242,7 +242,7 @@ def test_learned_fcg_converges_and_matches_oracle(pic, orc):
     p = _params(11)
     P, b = _landau_rhs(orc, N, 12)
     prm = pic.landau_params(N, 8, np_max=0, solver="fcg_learned", max_iter=2000)
-    prm.reserved = 1  # no warm start: the oracle's flexible CG has none
+    prm.flags = pic.FLAG_NO_WARM_START  # the oracle's flexible CG has no warm start
     ctx = pic.Context(prm)
     ctx.set_unet(f32dev(unet.flatten(p, specs)))
     x = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
@@ -271,3 +271,24 @@ def test_learned_fcg_falls_back_on_a_useless_network(pic, orc):
     assert orc.residual_norm(N, P.L, b, x.cpu().numpy()) <= 1.0001e-10 * np.linalg.norm(b)
     _, pinfo = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 5000)
     assert abs(info["iterations"] - pinfo["iters"]) <= 1
+
+
+def test_learned_warm_start_only(pic, orc):
+    """FLAG_WARM_START_ONLY: the network warm start (kept only if it lowers
+    the residual), then Jacobi-PCG; the residual test still decides."""
+    N = 32
+    specs = unet.layer_specs()
+    P, b = _landau_rhs(orc, N, 14)
+    prm = pic.landau_params(N, 8, np_max=0, solver="fcg_learned", max_iter=5000)
+    prm.flags = pic.FLAG_WARM_START_ONLY
+    ctx = pic.Context(prm)
+    ctx.set_unet(f32dev(unet.flatten(_params(15), specs)))
+    x = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.poisson(torch.from_numpy(b).cuda(), x)
+    assert info["converged"] and info["flex_iterations"] == 0 and not info["fell_back"]
+    assert orc.residual_norm(N, P.L, b, x.cpu().numpy()) <= 1.0001e-10 * np.linalg.norm(b)
+    if not info["warm_start_used"]:
+        _, pinfo = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 5000)
+        assert abs(info["iterations"] - pinfo["iters"]) <= 1
+    with pytest.raises(pic.PicError):
+        ctx.set_flags(8)
