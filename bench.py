@@ -160,8 +160,10 @@ def bench_poisson(args):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()  # the library allocates the network outside torch
     forms = {}
-    for form in ("pcg_fp64", "pcg_mixed", "fcg_learned", "learned_warm_start_only"):
-        solver = "fcg_learned" if form.startswith("learned") else form
+    for form in ("pcg_fp64", "pcg_mixed", "pcg_mixed_reliable", "fcg_learned",
+                 "learned_warm_start_only"):
+        solver = ("fcg_learned" if form.startswith("learned") else
+                  "pcg_mixed" if form.startswith("pcg_mixed") else form)
         if solver == "fcg_learned":
             try:
                 load_weights(ctx, args.weights)
@@ -169,7 +171,8 @@ def bench_poisson(args):
                 forms[form] = {"skipped": repr(e)}
                 continue
         ctx.set_flags((P.FLAG_NO_WARM_START if args.no_warm_start else 0)
-                      | (P.FLAG_WARM_START_ONLY if form.startswith("learned_") else 0))
+                      | (P.FLAG_WARM_START_ONLY if form.startswith("learned_") else 0)
+                      | (P.FLAG_MIXED_RELIABLE if form == "pcg_mixed_reliable" else 0))
         ctx.set_solver(solver)
         phi = torch.zeros_like(rho)
         torch.cuda.synchronize()
@@ -184,7 +187,12 @@ def bench_poisson(args):
                          "rel_res": info["rel_res"], "converged": bool(info["converged"])}
         log("%s: %.3f s, %d iterations, rel_res %.2e" % (form, dt, info["iterations"],
                                                          info["rel_res"]))
-    sel = forms.get(args.solver, {})
+    name = args.solver
+    if name == "pcg_mixed" and args.mixed_reliable:
+        name = "pcg_mixed_reliable"
+    if name == "fcg_learned" and args.warm_start_only:
+        name = "learned_warm_start_only"
+    sel = forms.get(name, {})
     n3 = N ** 3
     out = {"metric": METRIC, "value": sel.get("s_per_solve"), "unit": "s/solve", "n_gpus": 1,
            "steps": 1, "warmup": 0, "ms_per_step": 1e3 * sel.get("s_per_solve", float("nan")),
@@ -212,6 +220,8 @@ def main():
                     help="FP32 network parameters (.npy, canonical order) for fcg_learned")
     ap.add_argument("--inner-rtol", type=float, default=1e-3)
     ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--mixed-reliable", action="store_true",
+                    help="mixed form: keep the inner direction across refinements")
     ap.add_argument("--warm-start-only", action="store_true",
                     help="learned form: network warm start, then Jacobi-PCG")
     ap.add_argument("--accuracy-vs-fp64", action="store_true",
@@ -240,6 +250,8 @@ def main():
         p.flags |= P.FLAG_NO_WARM_START
     if args.warm_start_only:
         p.flags |= P.FLAG_WARM_START_ONLY
+    if args.mixed_reliable:
+        p.flags |= P.FLAG_MIXED_RELIABLE
     ctx = P.Context(p)
     if args.solver == "fcg_learned":
         load_weights(ctx, args.weights)

@@ -55,10 +55,13 @@ enum {
 };
 
 /* Problem statement (Sec. 2 and 2.1; tolerance as in Sec. 4). */
-/* pic_params.flags (learned form): */
-#define PIC_FLAG_NO_WARM_START 1   /* no network warm start */
-#define PIC_FLAG_WARM_START_ONLY 2 /* warm start, then Jacobi-PCG (no flexible
-                                      preconditioning) */
+/* pic_params.flags */
+#define PIC_FLAG_NO_WARM_START 1   /* learned form: no network warm start */
+#define PIC_FLAG_WARM_START_ONLY 2 /* learned form: warm start, then Jacobi-PCG
+                                      (no flexible preconditioning) */
+#define PIC_FLAG_MIXED_RELIABLE 4  /* mixed form: keep the inner direction across
+                                      refinements (reliable updates) instead of
+                                      restarting each inner solve */
 
 typedef struct pic_params {
     int32_t n;            /* grid points per axis N                         */
@@ -77,7 +80,7 @@ typedef struct pic_params {
     int64_t max_inner;    /* mixed: inner iteration cap per refinement step */
     int64_t max_outer;    /* mixed: refinement step cap                     */
     int32_t fcg_window;   /* learned: stall window (iterations)             */
-    int32_t flags;        /* learned form only: PIC_FLAG_* bits (above) */
+    int32_t flags;        /* PIC_FLAG_* bits (above) */
 } pic_params;
 
 /* Host-side result of one Poisson solve. */

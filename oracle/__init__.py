@@ -71,6 +71,8 @@ def lib():
                                    _dp, _dp, _dp, _dp, _dp, _dp]
         L.or_gather_scalar.argtypes = [c_i64, c_int, c_dbl, _dp, _dp, _dp, _dp, _dp]
         L.or_mixed_pcg.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_dbl, c_i64, _dp]
+        L.or_mixed_pcg_ex.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_dbl, c_i64,
+                                      ctypes.c_int, _dp]
         L.or_deposit_vertices.argtypes = [c_i64, c_int, c_dbl, c_dbl, _dp, _dp, _dp, c_i64, _i64p, _dp]
         L.or_fcg.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_int, PRECOND_FN,
                              ctypes.c_void_p, _dp]
@@ -182,11 +184,15 @@ def gather_scalar(N, L, x, y, z, F) -> np.ndarray:
     return out
 
 
-def mixed_pcg(N, L, b, x0, rtol, max_outer=50, inner_rtol=1e-3, max_inner=20000):
+def mixed_pcg(N, L, b, x0, rtol, max_outer=50, inner_rtol=1e-3, max_inner=20000,
+              reliable=False):
+    """FP32-inner / FP64-outer refinement; `reliable` keeps the inner
+    direction across refinements (reliable updates) instead of restarting."""
     b = _f64(b).reshape(-1)
     x = _f64(x0).reshape(-1).copy()
     info = np.zeros(4)
-    lib().or_mixed_pcg(N, L, b, x, rtol, max_outer, inner_rtol, max_inner, info)
+    lib().or_mixed_pcg_ex(N, L, b, x, rtol, max_outer, inner_rtol, max_inner,
+                          1 if reliable else 0, info)
     return x, dict(outer=int(info[0]), inner=int(info[1]), true_rel_res=info[2],
                    converged=bool(info[3]))
 

@@ -443,7 +443,9 @@ static double or_dot32(int64_t n, const float *a, const float *b)
 }
 
 /* Mixed-precision solve (not in the paper; classical iterative refinement,
- * Wilkinson / Moler, as analysed by Carson & Higham 2018):
+ * Wilkinson / Moler, as analysed by Carson & Higham 2018; with `reliable`,
+ * the inner Krylov space is kept across refinements -- "reliable updates",
+ * Sleijpen & van der Vorst 1996, as used by Clark et al. 2010):
  *   outer, FP64:  r = b - A x;  stop when ||r|| <= rtol ||b||;
  *   inner, FP32 vectors / FP32 operator / FP32 Jacobi, dot products
  *   accumulated in FP64:  Jacobi-PCG on A d = r from d = 0, stopped when
@@ -451,10 +453,20 @@ static double or_dot32(int64_t n, const float *a, const float *b)
  *   outer, FP64:  x <- x + d.
  * The inner right-hand side is r scaled by 1/||r|| before rounding to FP32
  * (and d scaled back), so FP32 range never limits the refinement.
+ * Reliable form: an inner solve that ended at its tolerance or its step cap
+ * hands its last direction p_j to the next one instead of restarting from
+ * p = M r.  In true (unscaled) units the next direction is CG's,
+ *   p' = M r' + beta p_j,  beta = (r'.M r') / (r_j.M r_j),
+ * with r' = b - A x the recomputed residual standing in for the recursive
+ * r_{j+1} (residual replacement) and r_j the residual p_j was built from.  In
+ * the scaled variables of each inner solve (r / ||r||) this is
+ *   p~' = M r~' + beta~ p~_j,  beta~ = (nr' / nr) (r~'.M r~') / (r~_j.M r~_j),
+ * nr, nr' the outer residual norms before and after the refinement.
  * info: [0]=outer steps, [1]=total inner iterations, [2]=true rel. residual,
  *       [3]=converged.                                                    */
-void or_mixed_pcg(int N, double L, const double *b, double *x, double rtol,
-                  int64_t max_outer, double inner_rtol, int64_t max_inner, double *info)
+void or_mixed_pcg_ex(int N, double L, const double *b, double *x, double rtol,
+                     int64_t max_outer, double inner_rtol, int64_t max_inner, int reliable,
+                     double *info)
 {
     int64_t n3 = (int64_t)N * N * N;
     double inv_h = (double)N / L;
@@ -476,6 +488,8 @@ void or_mixed_pcg(int N, double L, const double *b, double *x, double rtol,
         free(r); free(ri); free(d); free(p); free(q); free(zz);
         return;
     }
+    int have_dir = 0;        /* reliable form: p holds the last direction */
+    double rz_last = 0.0, nr_prev = 0.0;
     for (;;) {
         double nr = or_true_residual(N, L, b, x, r);
         trel = nr / nb;
@@ -485,11 +499,21 @@ void or_mixed_pcg(int N, double L, const double *b, double *x, double rtol,
         double sc = 1.0 / nr;
         for (int64_t i = 0; i < n3; ++i) { ri[i] = (float)(r[i] * sc); d[i] = 0.0f; }
         double n0 = sqrt(or_dot32(n3, ri, ri));
-        for (int64_t i = 0; i < n3; ++i) { zz[i] = minvf * ri[i]; p[i] = zz[i]; }
+        for (int64_t i = 0; i < n3; ++i) zz[i] = minvf * ri[i];
         double rz = or_dot32(n3, ri, zz);
+        double bc = reliable && have_dir ? (nr / nr_prev) * (rz / rz_last) : 0.0;
+        if (reliable && have_dir && isfinite(bc)) {
+            float bf = (float)bc;
+            for (int64_t i = 0; i < n3; ++i) p[i] = zz[i] + bf * p[i];
+        } else {
+            for (int64_t i = 0; i < n3; ++i) p[i] = zz[i];
+        }
+        have_dir = 0;
         for (int64_t k = 0; k < max_inner; ++k) {
             or_apply_A32(N, inv_h2f, p, q);
-            double alpha = rz / or_dot32(n3, p, q);
+            double pq = or_dot32(n3, p, q);
+            double alpha = rz / pq;
+            if (!isfinite(alpha) || !(pq > 0.0)) break; /* FP32 breakdown */
             float af = (float)alpha;
             for (int64_t i = 0; i < n3; ++i) {
                 d[i] = d[i] + af * p[i];
@@ -497,17 +521,28 @@ void or_mixed_pcg(int N, double L, const double *b, double *x, double rtol,
             }
             ++inner_total;
             double rn = sqrt(or_dot32(n3, ri, ri));
-            if (rn <= inner_rtol * n0) break;
             for (int64_t i = 0; i < n3; ++i) zz[i] = minvf * ri[i];
             double rz_new = or_dot32(n3, ri, zz);
+            if (rn <= inner_rtol * n0 || k + 1 == max_inner) {
+                rz_last = rz; /* r_j.M r_j of the residual p_j was built from */
+                have_dir = isfinite(rn);
+                break;
+            }
             float bf = (float)(rz_new / rz);
             rz = rz_new;
             for (int64_t i = 0; i < n3; ++i) p[i] = zz[i] + bf * p[i];
         }
         for (int64_t i = 0; i < n3; ++i) x[i] = x[i] + nr * (double)d[i];
+        nr_prev = nr;
     }
     info[0] = (double)outer; info[1] = (double)inner_total; info[2] = trel; info[3] = converged;
     free(r); free(ri); free(d); free(p); free(q); free(zz);
+}
+
+void or_mixed_pcg(int N, double L, const double *b, double *x, double rtol,
+                  int64_t max_outer, double inner_rtol, int64_t max_inner, double *info)
+{
+    or_mixed_pcg_ex(N, L, b, x, rtol, max_outer, inner_rtol, max_inner, 0, info);
 }
 
 /* ------------------------------------------------------------------------ */

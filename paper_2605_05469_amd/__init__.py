@@ -20,6 +20,7 @@ PIC_ERR_INVALID, PIC_ERR_HIP, PIC_ERR_NOMEM, PIC_ERR_STATE = -1, -2, -3, -4
 SOLVERS = {"pcg_fp64": 0, "pcg_mixed": 1, "fcg_learned": 2}
 FLAG_NO_WARM_START = 1
 FLAG_WARM_START_ONLY = 2
+FLAG_MIXED_RELIABLE = 4
 
 
 class PicError(RuntimeError):
@@ -217,7 +218,8 @@ class Context:
         _check(lib().pic_set_solver(self._h, s))
 
     def set_flags(self, flags: int):
-        """FLAG_NO_WARM_START | FLAG_WARM_START_ONLY (learned form)."""
+        """FLAG_NO_WARM_START | FLAG_WARM_START_ONLY (learned form),
+        FLAG_MIXED_RELIABLE (mixed form)."""
         _check(lib().pic_set_flags(self._h, int(flags)))
 
     def cell_keys(self, x, y, z, key, stream=None):

@@ -86,6 +86,9 @@ struct pic_ctx {
 
 static bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 
+constexpr int32_t kKnownFlags =
+    PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY | PIC_FLAG_MIXED_RELIABLE;
+
 static int validate_params(const pic_params* p) {
     if (!p) return fail(PIC_ERR_INVALID, "params is NULL");
     if (p->n < 32 || p->n > 1024 || (p->n % 32) != 0)
@@ -101,8 +104,7 @@ static int validate_params(const pic_params* p) {
     if (!std::isfinite(p->charge) || !std::isfinite(p->qm) || !std::isfinite(p->dt) ||
         !std::isfinite(p->rho_bg))
         return fail(PIC_ERR_INVALID, "charge, qm, dt and rho_bg must be finite");
-    if (p->flags & ~(PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY))
-        return fail(PIC_ERR_INVALID, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~kKnownFlags) return fail(PIC_ERR_INVALID, "unknown flags 0x%x", p->flags);
     return PIC_OK;
 }
 
@@ -328,9 +330,11 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
         }
         if (outer >= c->p.max_outer) break;
         ++outer;
-        HIPCHK(launch_convert32(c->n3, c->r, c->r32, c->d32, c->minvf, c->p.inner_rtol,
+        HIPCHK(launch_convert32(c->n3, c->r, c->r32, c->d32, c->minvf,
+                                (c->p.flags & PIC_FLAG_MIXED_RELIABLE) ? 1 : 0, c->p.inner_rtol,
                                 c->p.max_inner, c->st, c->partials, s));
         RETCHK(read_state(c, s));
+        const int cur0 = cur;
         while (c->st_host->cg.state == CG_RUNNING) {
             const int64_t it0 = c->st_host->cg.iter;
             for (int k = 0; k < K; ++k) {
@@ -350,6 +354,9 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
                 return fail(PIC_ERR_STATE, "inner solver made no progress");
         }
         inner_total += c->st_host->cg.iter;
+        // the last direction written (the next inner solve may continue it):
+        // each active iteration's direction sweep wrote p32[cur ^ 1]
+        cur = cur0 ^ (int)(c->st_host->cg.iter & 1);
         if (c->st_host->cg.state == CG_BREAKDOWN) {
             // an FP32 breakdown still leaves a usable correction; the next outer
             // residual decides, and the step cap bounds the loop
@@ -634,8 +641,7 @@ int pic_set_solver(pic_ctx* c, int32_t solver) {
 
 int pic_set_flags(pic_ctx* c, int32_t flags) {
     if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
-    if (flags & ~(PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY))
-        return fail(PIC_ERR_INVALID, "unknown flags 0x%x", flags);
+    if (flags & ~kKnownFlags) return fail(PIC_ERR_INVALID, "unknown flags 0x%x", flags);
     c->p.flags = flags;
     return PIC_OK;
 }

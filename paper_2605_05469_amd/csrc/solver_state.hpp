@@ -26,6 +26,7 @@ struct CgScalars {
     double tol;       // stop threshold on ||r||
     double true_rn;   // last true residual norm
     double pq;        // last p . A p
+    double rz_prev;   // r . M^{-1} r of the residual the last direction was built from
     int64_t iter;
     int64_t max_iter;
     int32_t state;
@@ -46,6 +47,7 @@ struct DevState {
     double flex_zr;    // learned: z . r
     double flex_pq;    // learned: p . A p
     double flex_rr;    // learned: r . r
+    double prev_nr;    // mixed: ||r|| of the previous outer step (reliable updates)
     int32_t outer_state;
     int32_t pad;
     uint32_t tickets[8];
@@ -74,7 +76,7 @@ hipError_t launch_upd64(const SweepGeo& g, const double* p_new, double* x, doubl
 hipError_t launch_outer_resid(const SweepGeo& g, const double* b, const double* x, double* r,
                               double inv_h2, DevState* st, double* partials, double tol,
                               hipStream_t s);
-hipError_t launch_convert32(int64_t n3, const double* r, float* r32, float* d32, float minvf,
+hipError_t launch_convert32(int64_t n3, const double* r, float* r32, float* d32, float minvf, int reliable,
                             double inner_rtol, int64_t max_inner, DevState* st,
                             double* partials, hipStream_t s);
 hipError_t launch_dir32(const SweepGeo& g, const float* r, const float* p_old, float* p_new,

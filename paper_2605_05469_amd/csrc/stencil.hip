@@ -374,6 +374,7 @@ struct OpUpd {
     }
     __device__ void finish(double (&t)[2]) const {
         CgScalars& cg = st->cg;
+        cg.rz_prev = cg.rz;
         cg.iter += 1;
         cg.rr = t[0];
         const double rn = sqrt(t[0]);
@@ -499,11 +500,17 @@ constexpr int kStreamBlocks = 2048;
 
 // r32 = (float)(r * (1/||r||)), d = 0; reduce r32.r32 and r32.(minv r32); the
 // last block starts the inner solve.
+// Reliable form (`reliable`): when the previous inner solve ended at its
+// tolerance or step cap, its last direction p_j carries over instead of a
+// restart: p~' = M r~' + beta~ p~_j with beta~ = (nr' / nr) (r~'.M r~') /
+// (r~_j.M r~_j) in the scaled variables (CG's recurrence with the residual
+// replaced by b - A x; nr, nr' the outer residual norms before and after).
 __global__ __launch_bounds__(kNT) void convert32_kernel(int64_t n3, const double* __restrict__ r,
                                                         float* __restrict__ r32,
                                                         float* __restrict__ d32, float minvf,
-                                                        double inner_rtol, int64_t max_inner,
-                                                        DevState* st, double* part) {
+                                                        int reliable, double inner_rtol,
+                                                        int64_t max_inner, DevState* st,
+                                                        double* part) {
     __shared__ double red[2 * (kNT / kWave)];
     __shared__ int lflag;
     if (st->outer_state != CG_RUNNING) return;
@@ -527,23 +534,29 @@ __global__ __launch_bounds__(kNT) void convert32_kernel(int64_t n3, const double
         if (threadIdx.x == 0) {
             CgScalars& cg = st->cg;
             const double n0 = sqrt(tot[0]);
+            const bool cont = reliable && (cg.state == CG_CANDIDATE || cg.state == CG_MAXIT) &&
+                              st->prev_nr > 0.0;
+            const double bt = cont ? (st->out_nr / st->prev_nr) * (tot[1] / cg.rz_prev) : 0.0;
             cg.nb = n0;
             cg.tol = inner_rtol * n0;
             cg.rz = tot[1];
             cg.rr = tot[0];
             cg.iter = 0;
             cg.max_iter = max_inner;
-            cg.restart = 1;
+            cg.restart = (cont && isfinite(bt)) ? 0 : 1;
+            cg.beta = cg.restart ? 0.0 : bt;
             cg.state = (n0 == 0.0 || !isfinite(n0)) ? CG_BREAKDOWN : CG_RUNNING;
         }
     }
 }
 
-// x += ||r|| * d: the refinement step's correction, before the next residual.
+// x += ||r|| * d: the refinement step's correction, before the next residual
+// (which overwrites out_nr; its value is kept as prev_nr).
 __global__ __launch_bounds__(kNT) void update_x_kernel(int64_t n3, double* __restrict__ x,
                                                        const float* __restrict__ d,
-                                                       const DevState* st) {
+                                                       DevState* st) {
     const double s = st->out_nr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->prev_nr = s;
     for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
         x[i] = x[i] + s * (double)d[i];
 }
@@ -700,16 +713,15 @@ static int stream_blocks(int64_t n) {
 }
 
 hipError_t launch_convert32(int64_t n3, const double* r, float* r32, float* d32, float minvf,
-                            double inner_rtol, int64_t max_inner, DevState* st, double* partials,
-                            hipStream_t s) {
+                            int reliable, double inner_rtol, int64_t max_inner, DevState* st,
+                            double* partials, hipStream_t s) {
     hipLaunchKernelGGL(convert32_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, r, r32, d32,
-                       minvf, inner_rtol, max_inner, st, partials);
+                       minvf, reliable, inner_rtol, max_inner, st, partials);
     return hipGetLastError();
 }
 
 hipError_t launch_update_x(int64_t n3, double* x, const float* d, DevState* st, hipStream_t s) {
-    hipLaunchKernelGGL(update_x_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, x, d,
-                       (const DevState*)st);
+    hipLaunchKernelGGL(update_x_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, x, d, st);
     return hipGetLastError();
 }
 

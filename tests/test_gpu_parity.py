@@ -293,6 +293,26 @@ def test_mixed_precision_reaches_tolerance(pic, orc):
     assert abs(minfo["inner"] - info["iterations"]) <= 2 * info["outer_iterations"]
 
 
+@pytest.mark.parametrize("N,inner_rtol", [(64, 1e-1), (96, 1e-2)])
+def test_mixed_reliable_matches_oracle(pic, orc, N, inner_rtol):
+    """Reliable updates: the inner direction carries over between refinements;
+    same refinement count as the oracle, inner count within a few per step."""
+    ctx, p = _ctx(pic, N, 8, np_max=0, solver="pcg_mixed", inner_rtol=inner_rtol)
+    ctx.set_flags(pic.FLAG_MIXED_RELIABLE)
+    b = _rhs(orc, N, 8, 6400 + N)
+    dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.poisson(_dev(b), dx)
+    assert info["converged"], info
+    assert orc.residual_norm(N, p.length, b, _host(dx)) <= p.rtol * np.linalg.norm(b)
+    _, minfo = orc.mixed_pcg(N, p.length, b, np.zeros(N ** 3), p.rtol, inner_rtol=inner_rtol,
+                             max_inner=p.max_inner, reliable=True)
+    assert minfo["converged"]
+    assert abs(minfo["outer"] - info["outer_iterations"]) <= 1
+    assert abs(minfo["inner"] - info["iterations"]) <= 3 * info["outer_iterations"] + 2
+    _, pinfo = orc.pcg(N, p.length, b, np.zeros(N ** 3), p.rtol, p.max_iter)
+    assert info["iterations"] <= 1.3 * pinfo["iters"]
+
+
 # ------------------------------------------------------------ full step ----
 
 def test_step_parity_config0(pic, orc):

@@ -203,6 +203,30 @@ def test_mixed_precision_reaches_fp64_tolerance(orc):
     assert info["outer"] <= 5
 
 
+@pytest.mark.parametrize("inner_rtol", [1e-1, 1e-2])
+def test_mixed_reliable_updates_keep_cg_convergence(orc, inner_rtol):
+    """Reliable form: CG's recurrence continues across refinements with the
+    residual replaced, so the total inner count stays near plain CG's (a wrong
+    continuation coefficient costs 2-7x here), while the restarted form pays a
+    fresh Krylov start per refinement; both reach the FP64 tolerance under an
+    operator applied independently of the oracle (FFT)."""
+    N = 32
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=17)
+    b, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    _, pinfo = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 20000)
+    x, rel = orc.mixed_pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, inner_rtol=inner_rtol,
+                           reliable=True)
+    _, rst = orc.mixed_pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, inner_rtol=inner_rtol)
+    assert rel["converged"] and rst["converged"]
+    r = b - _fft_apply(N, P.L, x)
+    assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(b)
+    assert rel["inner"] <= 1.3 * pinfo["iters"]
+    assert rst["inner"] >= 1.3 * rel["inner"]
+    # the refinement count is set by the inner tolerance, not by the form
+    assert abs(rel["outer"] - rst["outer"]) <= 1
+
+
 def _fft_apply(N, L, u):
     h = L / N
     m = np.arange(N)
