@@ -323,49 +323,14 @@ __global__ __launch_bounds__(kNT, (CI == 16 && MODE == 0) ? 2 : 1) void conv_zm_
 #pragma unroll
         for (int j = 0; j < PW; ++j) acc[a][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // Output plane z lives in accumulator slot (z - zb + 1) mod 3; the loop
-    // is unrolled by three planes so every slot index is a constant.  The
-    // partial sums of the two planes below zb and of plane ze are computed
-    // and dropped (no branches around the MFMAs).
-    auto epilogue = [&](const f32x4(&a)[PW], int z) {
-#pragma unroll
-        for (int j = 0; j < PW; ++j) {
-            const int T = q + WQ * j;
-            const int64_t p = ((int64_t)z * n + y0 + (T >> 2)) * n + x0 + 16 * (T & 3) + m;
-            const int co0 = 16 * cb + 4 * g;
-            if constexpr (MODE == 0) {
-                float y[4];
-                uint2 sk = make_uint2(0u, 0u);
-                if (skip) sk = *reinterpret_cast<const uint2*>(skip + p * CO + co0);
-                const uint16_t* sh = reinterpret_cast<const uint16_t*>(&sk);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    y[i] = a[j][i] + bv[i];
-                    if (skip) y[i] += bf2f(sh[i]);
-                    if (relu) y[i] = y[i] > 0.f ? y[i] : 0.f;
-                }
-                uint2 o;
-                o.x = (uint32_t)f2bf(y[0]) | ((uint32_t)f2bf(y[1]) << 16);
-                o.y = (uint32_t)f2bf(y[2]) | ((uint32_t)f2bf(y[3]) << 16);
-                *reinterpret_cast<uint2*>(Yb + p * CO + co0) = o;
-            } else {
-                float4 o = make_float4(a[j][0], a[j][1], a[j][2], a[j][3]);
-                float4* dst = reinterpret_cast<float4*>(Yf + p * CO + co0);
-                if (accumulate) {
-                    const float4 prev = *dst;
-                    o.x += prev.x;
-                    o.y += prev.y;
-                    o.z += prev.z;
-                    o.w += prev.w;
-                }
-                *dst = o;
-            }
-        }
-    };
+    // acc[0], acc[1], acc[2] hold output planes zp - 1, zp, zp + 1 while input
+    // plane zp is consumed; the partial sums of the two planes below zb and
+    // of plane ze are computed and dropped (no branches around the MFMAs).
+    load_plane(zb - 1);
+    store_plane(0);
+    __syncthreads();
     int buf = 0;
-    auto step = [&](int zp, auto rc) {
-        constexpr int r = decltype(rc)::value;
-        constexpr int sH = (r + 1) % 3, sM = r, sL = (r + 2) % 3;  // planes zp+1, zp, zp-1
+    for (int zp = zb - 1; zp <= ze; ++zp) {
         if (zp < ze) load_plane(zp + 1);
         const bf16x8* L = lds + buf * NCH;
 #pragma unroll
@@ -375,25 +340,56 @@ __global__ __launch_bounds__(kNT, (CI == 16 && MODE == 0) ? 2 : 1) void conv_zm_
 #pragma unroll
             for (int s = 0; s < KSP; ++s) {
                 const bf16x8 b = L[boff[s] + toff];
-                acc[sH][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0][s], b, acc[sH][j], 0, 0, 0);
-                acc[sM][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1][s], b, acc[sM][j], 0, 0, 0);
-                acc[sL][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[2][s], b, acc[sL][j], 0, 0, 0);
+                acc[2][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[0][s], b, acc[2][j], 0, 0, 0);
+                acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[1][s], b, acc[1][j], 0, 0, 0);
+                acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[2][s], b, acc[0][j], 0, 0, 0);
             }
         }
-        if (zp - 1 >= zb) epilogue(acc[sL], zp - 1);
+        if (zp - 1 >= zb) {
+            const int z = zp - 1;
 #pragma unroll
-        for (int j = 0; j < PW; ++j) acc[sL][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < PW; ++j) {
+                const int T = q + WQ * j;
+                const int64_t p = ((int64_t)z * n + y0 + (T >> 2)) * n + x0 + 16 * (T & 3) + m;
+                const int co0 = 16 * cb + 4 * g;
+                if constexpr (MODE == 0) {
+                    float y[4];
+                    uint2 sk = make_uint2(0u, 0u);
+                    if (skip) sk = *reinterpret_cast<const uint2*>(skip + p * CO + co0);
+                    const uint16_t* sh = reinterpret_cast<const uint16_t*>(&sk);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        y[i] = acc[0][j][i] + bv[i];
+                        if (skip) y[i] += bf2f(sh[i]);
+                        if (relu) y[i] = y[i] > 0.f ? y[i] : 0.f;
+                    }
+                    uint2 o;
+                    o.x = (uint32_t)f2bf(y[0]) | ((uint32_t)f2bf(y[1]) << 16);
+                    o.y = (uint32_t)f2bf(y[2]) | ((uint32_t)f2bf(y[3]) << 16);
+                    *reinterpret_cast<uint2*>(Yb + p * CO + co0) = o;
+                } else {
+                    float4 o = make_float4(acc[0][j][0], acc[0][j][1], acc[0][j][2], acc[0][j][3]);
+                    float4* dst = reinterpret_cast<float4*>(Yf + p * CO + co0);
+                    if (accumulate) {
+                        const float4 prev = *dst;
+                        o.x += prev.x;
+                        o.y += prev.y;
+                        o.z += prev.z;
+                        o.w += prev.w;
+                    }
+                    *dst = o;
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            acc[0][j] = acc[1][j];
+            acc[1][j] = acc[2][j];
+            acc[2][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
         if (zp < ze) store_plane(buf ^ 1);
         __syncthreads();
         buf ^= 1;
-    };
-    load_plane(zb - 1);
-    store_plane(0);
-    __syncthreads();
-    for (int zp = zb - 1; zp <= ze; zp += 3) {
-        step(zp, std::integral_constant<int, 0>{});
-        if (zp + 1 <= ze) step(zp + 1, std::integral_constant<int, 1>{});
-        if (zp + 2 <= ze) step(zp + 2, std::integral_constant<int, 2>{});
     }
 }
 
@@ -606,7 +602,7 @@ __global__ __launch_bounds__(kNT) void conv_out_fwd_kernel(int n, const uint16_t
 // (zp - 1) mod 3: its lanes add the bias, store 4 consecutive x (FP32) and
 // clear that column for plane zp + 2.
 template <int TY>
-__global__ __launch_bounds__(kNT, 2) void conv_out_zm_kernel(int n, int zlen,
+__global__ __launch_bounds__(kNT) void conv_out_zm_kernel(int n, int zlen,
                                                           const uint16_t* __restrict__ X,
                                                           const float* __restrict__ W,
                                                           const float* __restrict__ bptr,
@@ -691,7 +687,8 @@ __global__ __launch_bounds__(kNT, 2) void conv_out_zm_kernel(int n, int zlen,
         if (zp < ze) load_plane(zp + 1);
         const int ph = (zp + 3) % 3;
         const bf16x8* L = lds + buf * NCH;
-        auto plane = [&](const bf16x8(&w)[KSP]) {
+        auto plane = [&](auto phase) {
+            constexpr int PH = decltype(phase)::value;
 #pragma unroll
             for (int j = 0; j < PW; ++j) {
                 const int T = wave + 4 * j;
@@ -699,13 +696,13 @@ __global__ __launch_bounds__(kNT, 2) void conv_out_zm_kernel(int n, int zlen,
 #pragma unroll
                 for (int s2 = 0; s2 < KSP; ++s2) {
                     const bf16x8 av = L[boff[s2] + toff];
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, w[s2], acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, wf[PH][s2], acc[j], 0, 0, 0);
                 }
             }
         };
-        if (ph == 0) plane(wf[0]);
-        else if (ph == 1) plane(wf[1]);
-        else plane(wf[2]);
+        if (ph == 0) plane(std::integral_constant<int, 0>{});
+        else if (ph == 1) plane(std::integral_constant<int, 1>{});
+        else plane(std::integral_constant<int, 2>{});
         const int co = (zp + 2) % 3;  // column of output plane zp - 1
         if (m == co) {
             const int z = zp - 1;
