@@ -197,7 +197,7 @@ def mixed_pcg(N, L, b, x0, rtol, max_outer=50, inner_rtol=1e-3, max_inner=20000,
                    converged=bool(info[3]))
 
 
-def fcg(N, L, b, x0, rtol, max_iter, precond, window=5):
+def fcg(N, L, b, x0, rtol, max_iter, precond, window=10):
     """Flexible PCG with a Python preconditioner ``precond(r) -> z`` (FP64)."""
     b = _f64(b).reshape(-1)
     x = _f64(x0).reshape(-1).copy()

@@ -173,7 +173,7 @@ def _stream(stream=None):
 
 def landau_params(N, ppc, k=0.5, dt=0.05, qm=-1.0, rtol=1e-10, max_iter=20000,
                   solver="pcg_fp64", np_max=None, check_every=16, inner_rtol=1e-3,
-                  max_inner=20000, max_outer=50, fcg_window=5):
+                  max_inner=20000, max_outer=50, fcg_window=10):
     """Parameters of the Landau-damping box (Sec. 2.1): L = 2 pi / k, unit
     mean density, q = -L^3/Np, background +1."""
     L = 2.0 * math.pi / k

@@ -554,7 +554,7 @@ int pic_create(const pic_params* params, pic_ctx** out) {
     if (c->p.max_outer <= 0) c->p.max_outer = 50;
     if (c->p.max_inner <= 0) c->p.max_inner = 20000;
     if (!(c->p.inner_rtol > 0.0)) c->p.inner_rtol = 1e-3;
-    if (c->p.fcg_window <= 0) c->p.fcg_window = 5;
+    if (c->p.fcg_window <= 0) c->p.fcg_window = 10;
     const int n = c->p.n;
     c->n3 = (int64_t)n * n * n;
     c->geo = make_geo(n);
