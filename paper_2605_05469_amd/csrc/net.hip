@@ -217,11 +217,19 @@ static int fwd(Net* net, hipStream_t s) {
     auto W = [&](int l) { return P + net->woff[l]; };
     auto Bi = [&](int l) { return P + net->boff[l]; };
     NCHK(conv_in_fwd(n, net->in, W(E1A), Bi(E1A), net->e1a, s));
-    NCHK(conv_fwd(n, 16, 16, net->e1a, net->ffrag[E1B], Bi(E1B), nullptr, 1, net->e1b, s));
-    NCHK(pool_fwd(h, 16, net->e1b, net->p1, s));
+    if (conv_pool_fused(n, 16, 16)) {
+        NCHK(conv_fwd_pool(n, 16, 16, net->e1a, net->ffrag[E1B], Bi(E1B), net->e1b, net->p1, s));
+    } else {
+        NCHK(conv_fwd(n, 16, 16, net->e1a, net->ffrag[E1B], Bi(E1B), nullptr, 1, net->e1b, s));
+        NCHK(pool_fwd(h, 16, net->e1b, net->p1, s));
+    }
     NCHK(conv_fwd(h, 16, 32, net->p1, net->ffrag[E2A], Bi(E2A), nullptr, 1, net->e2a, s));
-    NCHK(conv_fwd(h, 32, 32, net->e2a, net->ffrag[E2B], Bi(E2B), nullptr, 1, net->e2b, s));
-    NCHK(pool_fwd(q, 32, net->e2b, net->p2, s));
+    if (conv_pool_fused(h, 32, 32)) {
+        NCHK(conv_fwd_pool(h, 32, 32, net->e2a, net->ffrag[E2B], Bi(E2B), net->e2b, net->p2, s));
+    } else {
+        NCHK(conv_fwd(h, 32, 32, net->e2a, net->ffrag[E2B], Bi(E2B), nullptr, 1, net->e2b, s));
+        NCHK(pool_fwd(q, 32, net->e2b, net->p2, s));
+    }
     NCHK(conv_fwd(q, 32, 64, net->p2, net->ffrag[B3A], Bi(B3A), nullptr, 1, net->b3a, s));
     NCHK(conv_fwd(q, 64, 32, net->b3a, net->ffrag[B3B], Bi(B3B), nullptr, 1, net->b3b, s));
     // training keeps the up-sampled inputs (the weight gradients read them);

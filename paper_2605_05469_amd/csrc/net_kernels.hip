@@ -233,14 +233,19 @@ __global__ __launch_bounds__(kNT) void conv_mfma_kernel(int n, const uint16_t* _
 // Wave w computes output block w % NCB for the point tiles q, q + WQ, ... of
 // the plane (q = w / NCB, WQ = 4 / NCB).  Requires n % 64 == 0, n % TY == 0.
 // UP: X is given on the n/2 grid and nearest-neighbour up-sampled while it is
-// staged (the decoder's up-sampling never materialises).
-template <int CI, int CO, int TY, int MODE, bool UP = false>
+// staged (the decoder's up-sampling never materialises).  SK: a skip input is
+// added before the ReLU.  PL: the 2x2x2 average pool of the (BF16-rounded)
+// output is formed in registers and written to Yp as well (x pairs are
+// neighbouring lanes, y pairs are tiles j and j + NCB of the same wave, z
+// pairs are consecutive planes; requires an even zlen).
+template <int CI, int CO, int TY, int MODE, bool UP = false, bool SK = false, bool PL = false>
 __global__ __launch_bounds__(kNT, (CI == 16 && MODE == 0) ? 2 : 1) void conv_zm_kernel(int n, int zlen, const uint16_t* __restrict__ X,
                                                       const uint16_t* __restrict__ fragz,
                                                       const float* __restrict__ bias,
                                                       const uint16_t* __restrict__ skip, int relu,
                                                       uint16_t* __restrict__ Yb,
-                                                      float* __restrict__ Yf, int accumulate) {
+                                                      float* __restrict__ Yf, int accumulate,
+                                                      uint16_t* __restrict__ Yp) {
     constexpr int TX = 64, SX = TX + 2, SY = TY + 2;
     constexpr int CG = CI / 8;
     constexpr int KSP = (9 * CI + 31) / 32;
@@ -322,6 +327,8 @@ __global__ __launch_bounds__(kNT, (CI == 16 && MODE == 0) ? 2 : 1) void conv_zm_
     for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int j = 0; j < PW; ++j) acc[a][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 rv[PL ? PW : 1];      // rounded outputs of the plane (PL)
+    f32x4 pz[PL ? PW / 2 : 1];  // pooled partial sums of the even plane (PL)
 
     // acc[0], acc[1], acc[2] hold output planes zp - 1, zp, zp + 1 while input
     // plane zp is consumed; the partial sums of the two planes below zb and
@@ -332,6 +339,19 @@ __global__ __launch_bounds__(kNT, (CI == 16 && MODE == 0) ? 2 : 1) void conv_zm_
     int buf = 0;
     for (int zp = zb - 1; zp <= ze; ++zp) {
         if (zp < ze) load_plane(zp + 1);
+        // the skip input of output plane zp - 1, loaded before the MFMAs
+        uint2 skv[PW];
+        if constexpr (MODE == 0 && SK) {
+            if (zp - 1 >= zb) {
+#pragma unroll
+                for (int j = 0; j < PW; ++j) {
+                    const int T = q + WQ * j;
+                    const int64_t p =
+                        ((int64_t)(zp - 1) * n + y0 + (T >> 2)) * n + x0 + 16 * (T & 3) + m;
+                    skv[j] = *reinterpret_cast<const uint2*>(skip + p * CO + 16 * cb + 4 * g);
+                }
+            }
+        }
         const bf16x8* L = lds + buf * NCH;
 #pragma unroll
         for (int j = 0; j < PW; ++j) {
@@ -354,19 +374,21 @@ __global__ __launch_bounds__(kNT, (CI == 16 && MODE == 0) ? 2 : 1) void conv_zm_
                 const int co0 = 16 * cb + 4 * g;
                 if constexpr (MODE == 0) {
                     float y[4];
-                    uint2 sk = make_uint2(0u, 0u);
-                    if (skip) sk = *reinterpret_cast<const uint2*>(skip + p * CO + co0);
-                    const uint16_t* sh = reinterpret_cast<const uint16_t*>(&sk);
+                    const uint16_t* sh = reinterpret_cast<const uint16_t*>(&skv[j]);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         y[i] = acc[0][j][i] + bv[i];
-                        if (skip) y[i] += bf2f(sh[i]);
+                        if constexpr (SK) y[i] += bf2f(sh[i]);
                         if (relu) y[i] = y[i] > 0.f ? y[i] : 0.f;
                     }
                     uint2 o;
                     o.x = (uint32_t)f2bf(y[0]) | ((uint32_t)f2bf(y[1]) << 16);
                     o.y = (uint32_t)f2bf(y[2]) | ((uint32_t)f2bf(y[3]) << 16);
                     *reinterpret_cast<uint2*>(Yb + p * CO + co0) = o;
+                    if constexpr (PL) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) rv[j][i] = bf2f(f2bf(y[i]));
+                    }
                 } else {
                     float4 o = make_float4(acc[0][j][0], acc[0][j][1], acc[0][j][2], acc[0][j][3]);
                     float4* dst = reinterpret_cast<float4*>(Yf + p * CO + co0);
@@ -378,6 +400,36 @@ __global__ __launch_bounds__(kNT, (CI == 16 && MODE == 0) ? 2 : 1) void conv_zm_
                         o.w += prev.w;
                     }
                     *dst = o;
+                }
+            }
+        }
+        if constexpr (MODE == 0 && PL) {
+            if (zp - 1 >= zb) {
+                const int z = zp - 1;
+#pragma unroll
+                for (int jp = 0; jp < PW / 2; ++jp) {
+                    const int j0 = (jp / NCB) * 2 * NCB + (jp % NCB), j1 = j0 + NCB;
+                    f32x4 sxy;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float a0 = rv[j0][i] + __shfl_xor(rv[j0][i], 1);
+                        const float a1 = rv[j1][i] + __shfl_xor(rv[j1][i], 1);
+                        sxy[i] = a0 + a1;
+                    }
+                    if ((z & 1) == 0) {
+                        pz[jp] = sxy;
+                    } else if ((m & 1) == 0) {
+                        const int T = q + WQ * j0;
+                        const int nh = n >> 1;
+                        const int64_t P = ((int64_t)(z >> 1) * nh + ((y0 + (T >> 2)) >> 1)) * nh +
+                                          ((x0 + 16 * (T & 3) + m) >> 1);
+                        uint2 o;
+                        o.x = (uint32_t)f2bf((pz[jp][0] + sxy[0]) * 0.125f) |
+                              ((uint32_t)f2bf((pz[jp][1] + sxy[1]) * 0.125f) << 16);
+                        o.y = (uint32_t)f2bf((pz[jp][2] + sxy[2]) * 0.125f) |
+                              ((uint32_t)f2bf((pz[jp][3] + sxy[3]) * 0.125f) << 16);
+                        *reinterpret_cast<uint2*>(Yp + P * CO + 16 * cb + 4 * g) = o;
+                    }
                 }
             }
         }
@@ -561,6 +613,128 @@ __global__ __launch_bounds__(kNT) void conv_in_fwd_kernel(int n, const uint16_t*
             o.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
             *reinterpret_cast<uint2*>(y + ((t0 + j) * 16 + m) * 16 + 4 * g) = o;
         }
+    }
+}
+
+// e1a, z-marching (n % 64 == 0): the single-channel input planes are staged
+// in LDS (one-point halo); per input plane and 16-point tile, the 9 in-plane
+// taps (zero-padded to K = 16) of v_mfma_f32_16x16x16bf16_1k feed the three
+// output planes the input plane touches (weights of tap planes dz = -1, 0, +1
+// in registers), with rotating accumulators as in conv_zm_kernel.  Every
+// input value is read from HBM once; the kernel is bound by writing the 16
+// output channels.
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
+template <int TY>
+__global__ __launch_bounds__(kNT) void conv_in_zm_kernel(int n, int zlen,
+                                                         const uint16_t* __restrict__ x,
+                                                         const float* __restrict__ W,
+                                                         const float* __restrict__ b,
+                                                         uint16_t* __restrict__ y) {
+    constexpr int TX = 64, SX = TX + 2, SY = TY + 2;
+    constexpr int NCH = SX * SY;
+    constexpr int NPT = (NCH + kNT - 1) / kNT;
+    constexpr int PW = TY;  // 16-point tiles per wave per plane
+    __shared__ uint16_t lds[2 * NCH];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int ntx = n / TX;
+    const int ncol = ntx * (n / TY);
+    const int bid = (int)remap_xcd(blockIdx.x, gridDim.x);
+    const int col = bid % ncol;
+    const int zb = (bid / ncol) * zlen, ze = zb + zlen;
+    const int x0 = (col % ntx) * TX, y0 = (col / ntx) * TY;
+
+    // A: w[dzi], lane (m, g): W[co = m][tap 9 dzi + u], u = 4 g + i < 9
+    s16x4 w[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int u = 4 * g + i;
+            w[d][i] = (short)(u < 9 ? f2bf(W[m * 27 + 9 * d + u]) : (uint16_t)0);
+        }
+    // LDS offsets of this lane's 4 taps (padding reads tap 0; its weight is 0)
+    int toffs[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int u = 4 * g + i;
+        toffs[i] = u < 9 ? (u / 3) * SX + (u % 3) + m : m;
+    }
+    float bv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bv[i] = b[4 * g + i];
+
+    uint16_t stg[NPT];
+    auto load_plane = [&](int zp) {
+        const int zz = zp < 0 ? zp + n : (zp >= n ? zp - n : zp);
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int c = threadIdx.x + kNT * i;
+            if (c < NCH) {
+                const int xx = c % SX, yy = c / SX;
+                stg[i] = x[((int64_t)zz * n + wrapi(y0 - 1 + yy, n)) * n + wrapi(x0 - 1 + xx, n)];
+            }
+        }
+    };
+    auto store_plane = [&](int bb) {
+#pragma unroll
+        for (int i = 0; i < NPT; ++i) {
+            const int c = threadIdx.x + kNT * i;
+            if (c < NCH) lds[bb * NCH + c] = stg[i];
+        }
+    };
+
+    f32x4 acc[3][PW];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int j = 0; j < PW; ++j) acc[a][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    load_plane(zb - 1);
+    store_plane(0);
+    __syncthreads();
+    int buf = 0;
+    for (int zp = zb - 1; zp <= ze; ++zp) {
+        if (zp < ze) load_plane(zp + 1);
+        const uint16_t* L = lds + buf * NCH;
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            const int T = wave + 4 * j;
+            const int toff = (T >> 2) * SX + 16 * (T & 3);
+            s16x4 bb;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bb[i] = (short)L[toffs[i] + toff];
+            acc[2][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[0], bb, acc[2][j], 0, 0, 0);
+            acc[1][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[1], bb, acc[1][j], 0, 0, 0);
+            acc[0][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[2], bb, acc[0][j], 0, 0, 0);
+        }
+        if (zp - 1 >= zb) {
+            const int z = zp - 1;
+#pragma unroll
+            for (int j = 0; j < PW; ++j) {
+                const int T = wave + 4 * j;
+                const int64_t p = ((int64_t)z * n + y0 + (T >> 2)) * n + x0 + 16 * (T & 3) + m;
+                float v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    v[i] = acc[0][j][i] + bv[i];
+                    v[i] = v[i] > 0.f ? v[i] : 0.f;
+                }
+                uint2 o;
+                o.x = (uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16);
+                o.y = (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16);
+                *reinterpret_cast<uint2*>(y + p * 16 + 4 * g) = o;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            acc[0][j] = acc[1][j];
+            acc[1][j] = acc[2][j];
+            acc[2][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        }
+        if (zp < ze) store_plane(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
     }
 }
 
@@ -1099,16 +1273,47 @@ static int zm_zsplit(int n, int ncol) {
     return best;
 }
 
+template <int CI, int CO, int TY, int MODE, bool UP = false, bool SK = false, bool PL = false>
+static hipError_t zm_launch_t(int n, const uint16_t* X, const uint16_t* frag, const float* bias,
+                              const uint16_t* skip, int relu, uint16_t* Yb, float* Yf, int acc,
+                              hipStream_t s, uint16_t* Yp = nullptr) {
+    const int ncol = (n / 64) * (n / TY);
+    const int zs = zm_zsplit(n, ncol);
+    const uint16_t* fz = frag + gather_frag_elems(CI, CO);
+    hipLaunchKernelGGL((conv_zm_kernel<CI, CO, TY, MODE, UP, SK, PL>), dim3(ncol * zs), dim3(kNT), 0,
+                       s, n, n / zs, X, fz, bias, skip, relu, Yb, Yf, acc, Yp);
+    return hipGetLastError();
+}
+
+bool conv_pool_fused(int n, int ci, int co) {
+    if (n % 64 != 0 || (n / zm_zsplit(n, (n / 64) * (n / 4))) % 2 != 0) return false;
+    return (ci == 16 && co == 16) || (ci == 32 && co == 32);
+}
+
+hipError_t conv_fwd_pool(int n, int ci, int co, const uint16_t* X, const uint16_t* frag,
+                         const float* bias, uint16_t* Y, uint16_t* Yp, hipStream_t s) {
+    if (!conv_pool_fused(n, ci, co)) return hipErrorInvalidValue;
+    if (ci == 16)
+        return zm_launch_t<16, 16, 4, 0, false, false, true>(n, X, frag, bias, nullptr, 1, Y, nullptr,
+                                                             0, s, Yp);
+    return zm_launch_t<32, 32, 4, 0, false, false, true>(n, X, frag, bias, nullptr, 1, Y, nullptr, 0,
+                                                         s, Yp);
+}
+
+// With a skip input the 16-channel variants use 4-row tiles (the skip values
+// are held in registers across the MFMAs).
 template <int CI, int CO, int TY, int MODE, bool UP = false>
 static hipError_t zm_launch(int n, const uint16_t* X, const uint16_t* frag, const float* bias,
                             const uint16_t* skip, int relu, uint16_t* Yb, float* Yf, int acc,
                             hipStream_t s) {
-    const int ncol = (n / 64) * (n / TY);
-    const int zs = zm_zsplit(n, ncol);
-    const uint16_t* fz = frag + gather_frag_elems(CI, CO);
-    hipLaunchKernelGGL((conv_zm_kernel<CI, CO, TY, MODE, UP>), dim3(ncol * zs), dim3(kNT), 0, s, n,
-                       n / zs, X, fz, bias, skip, relu, Yb, Yf, acc);
-    return hipGetLastError();
+    if constexpr (MODE == 0) {
+        if (skip) {
+            constexpr int TYS = (CI == 16 && TY > 4) ? 4 : TY;
+            return zm_launch_t<CI, CO, TYS, MODE, UP, true>(n, X, frag, bias, skip, relu, Yb, Yf,
+                                                            acc, s);
+        }
+    }
+    return zm_launch_t<CI, CO, TY, MODE, UP, false>(n, X, frag, bias, nullptr, relu, Yb, Yf, acc, s);
 }
 
 bool conv_up_fused(int n, int ci, int co) {
@@ -1225,6 +1430,14 @@ size_t dw_part_elems(int n, int ci, int co) {
 
 hipError_t conv_in_fwd(int n, const uint16_t* x, const float* W, const float* b, uint16_t* y,
                        hipStream_t s) {
+    if (n % 64 == 0) {
+        constexpr int TY = 8;
+        const int ncol = (n / 64) * (n / TY);
+        const int zs = zm_zsplit(n, ncol);
+        hipLaunchKernelGGL(conv_in_zm_kernel<TY>, dim3(ncol * zs), dim3(kNT), 0, s, n, n / zs, x, W,
+                           b, y);
+        return hipGetLastError();
+    }
     const int64_t ntiles = (int64_t)n * n * n / 16;
     hipLaunchKernelGGL(conv_in_fwd_kernel, dim3(blocks_for(ntiles, 16, 8192)), dim3(kNT), 0, s, n,
                        x, W, b, y);
