@@ -161,7 +161,7 @@ def bench_poisson(args):
     torch.cuda.empty_cache()  # the library allocates the network outside torch
     forms = {}
     for form in ("pcg_fp64", "pcg_mixed", "pcg_mixed_reliable", "fcg_learned",
-                 "learned_warm_start_only"):
+                 "learned_warm_start_only", "learned_warm_start_mixed"):
         solver = ("fcg_learned" if form.startswith("learned") else
                   "pcg_mixed" if form.startswith("pcg_mixed") else form)
         if solver == "fcg_learned":
@@ -172,7 +172,9 @@ def bench_poisson(args):
                 continue
         ctx.set_flags((P.FLAG_NO_WARM_START if args.no_warm_start else 0)
                       | (P.FLAG_WARM_START_ONLY if form.startswith("learned_") else 0)
-                      | (P.FLAG_MIXED_RELIABLE if form == "pcg_mixed_reliable" else 0))
+                      | (P.FLAG_MIXED_RELIABLE if form in ("pcg_mixed_reliable",
+                                                           "learned_warm_start_mixed") else 0)
+                      | (P.FLAG_LEARNED_MIXED if form == "learned_warm_start_mixed" else 0))
         ctx.set_solver(solver)
         phi = torch.zeros_like(rho)
         torch.cuda.synchronize()
@@ -191,7 +193,7 @@ def bench_poisson(args):
     if name == "pcg_mixed" and args.mixed_reliable:
         name = "pcg_mixed_reliable"
     if name == "fcg_learned" and args.warm_start_only:
-        name = "learned_warm_start_only"
+        name = "learned_warm_start_mixed" if args.learned_mixed else "learned_warm_start_only"
     sel = forms.get(name, {})
     n3 = N ** 3
     out = {"metric": METRIC, "value": sel.get("s_per_solve"), "unit": "s/solve", "n_gpus": 1,
@@ -220,6 +222,8 @@ def main():
                     help="FP32 network parameters (.npy, canonical order) for fcg_learned")
     ap.add_argument("--inner-rtol", type=float, default=1e-3)
     ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--learned-mixed", action="store_true",
+                    help="learned form: hand over to the mixed form (not FP64 PCG)")
     ap.add_argument("--mixed-reliable", action="store_true",
                     help="mixed form: keep the inner direction across refinements")
     ap.add_argument("--warm-start-only", action="store_true",
@@ -252,6 +256,8 @@ def main():
         p.flags |= P.FLAG_WARM_START_ONLY
     if args.mixed_reliable:
         p.flags |= P.FLAG_MIXED_RELIABLE
+    if args.learned_mixed:
+        p.flags |= P.FLAG_LEARNED_MIXED
     ctx = P.Context(p)
     if args.solver == "fcg_learned":
         load_weights(ctx, args.weights)

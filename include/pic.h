@@ -62,6 +62,9 @@ enum {
 #define PIC_FLAG_MIXED_RELIABLE 4  /* mixed form: keep the inner direction across
                                       refinements (reliable updates) instead of
                                       restarting each inner solve */
+#define PIC_FLAG_LEARNED_MIXED 8   /* learned form: the solve after the warm start
+                                      (PIC_FLAG_WARM_START_ONLY) or after a
+                                      fallback is the mixed form, not FP64 PCG */
 
 typedef struct pic_params {
     int32_t n;            /* grid points per axis N                         */

@@ -21,6 +21,7 @@ SOLVERS = {"pcg_fp64": 0, "pcg_mixed": 1, "fcg_learned": 2}
 FLAG_NO_WARM_START = 1
 FLAG_WARM_START_ONLY = 2
 FLAG_MIXED_RELIABLE = 4
+FLAG_LEARNED_MIXED = 8
 
 
 class PicError(RuntimeError):
@@ -219,7 +220,7 @@ class Context:
 
     def set_flags(self, flags: int):
         """FLAG_NO_WARM_START | FLAG_WARM_START_ONLY (learned form),
-        FLAG_MIXED_RELIABLE (mixed form)."""
+        FLAG_MIXED_RELIABLE (mixed form), FLAG_LEARNED_MIXED (learned form)."""
         _check(lib().pic_set_flags(self._h, int(flags)))
 
     def cell_keys(self, x, y, z, key, stream=None):

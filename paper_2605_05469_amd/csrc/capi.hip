@@ -86,8 +86,8 @@ struct pic_ctx {
 
 static bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 
-constexpr int32_t kKnownFlags =
-    PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY | PIC_FLAG_MIXED_RELIABLE;
+constexpr int32_t kKnownFlags = PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY |
+                                 PIC_FLAG_MIXED_RELIABLE | PIC_FLAG_LEARNED_MIXED;
 
 static int validate_params(const pic_params* p) {
     if (!p) return fail(PIC_ERR_INVALID, "params is NULL");
@@ -382,6 +382,15 @@ static int fcg_precond(pic_ctx* c, const double* r, double* z, hipStream_t s) {
     return PIC_OK;
 }
 
+// The non-learned solve the learned form hands over to (after the warm start
+// with PIC_FLAG_WARM_START_ONLY, or on fallback): Jacobi-PCG, or the mixed
+// form with PIC_FLAG_LEARNED_MIXED (its step cap is max_outer x max_inner).
+static int continue_plain(pic_ctx* c, const double* b, double* x, pic_solve_info* out,
+                          hipStream_t s, int64_t max_iter) {
+    if (c->p.flags & PIC_FLAG_LEARNED_MIXED) return solve_mixed(c, b, x, out, s);
+    return solve_fp64(c, b, x, out, s, max_iter);
+}
+
 static int solve_learned(pic_ctx* c, const double* b, double* x, pic_solve_info* out,
                          hipStream_t s) {
     RETCHK(ensure_learned(c));
@@ -425,11 +434,12 @@ static int solve_learned(pic_ctx* c, const double* b, double* x, pic_solve_info*
         }
     }
     if (c->p.flags & PIC_FLAG_WARM_START_ONLY) {
-        // warm start only: Jacobi-PCG from the (possibly corrected) iterate
+        // warm start only: Jacobi-PCG (or the mixed form) from the iterate
         pic_solve_info pi;
         std::memset(&pi, 0, sizeof pi);
-        RETCHK(solve_fp64(c, b, x, &pi, s, c->p.max_iter));
+        RETCHK(continue_plain(c, b, x, &pi, s, c->p.max_iter));
         out->iterations = pi.iterations;
+        out->outer_iterations = pi.outer_iterations;
         out->replacements += pi.replacements;
         out->rel_res = pi.rel_res;
         out->converged = pi.converged;
@@ -505,12 +515,13 @@ static int solve_learned(pic_ctx* c, const double* b, double* x, pic_solve_info*
         out->converged = out->rel_res <= c->p.rtol;
         return PIC_OK;
     }
-    // fallback: Jacobi-PCG from the current iterate, with the remaining budget
+    // fallback: Jacobi-PCG (or the mixed form) from the current iterate
     out->fell_back = 1;
     pic_solve_info pi;
     std::memset(&pi, 0, sizeof pi);
-    RETCHK(solve_fp64(c, b, x, &pi, s, c->p.max_iter - it));
+    RETCHK(continue_plain(c, b, x, &pi, s, c->p.max_iter - it));
     out->iterations = it + pi.iterations;
+    out->outer_iterations = pi.outer_iterations;
     out->replacements += pi.replacements;
     out->rel_res = pi.rel_res;
     out->converged = pi.converged;

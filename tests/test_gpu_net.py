@@ -292,3 +292,19 @@ def test_learned_warm_start_only(pic, orc):
         assert abs(info["iterations"] - pinfo["iters"]) <= 1
     with pytest.raises(pic.PicError):
         ctx.set_flags(8)
+
+
+def test_learned_warm_start_then_mixed(pic, orc):
+    """FLAG_LEARNED_MIXED: after the warm start the mixed (reliable-update)
+    form finishes the solve; the FP64 true residual still decides."""
+    N = 64
+    specs = unet.layer_specs()
+    P, b = _landau_rhs(orc, N, 16)
+    prm = pic.landau_params(N, 8, np_max=0, solver="fcg_learned", inner_rtol=0.1)
+    prm.flags = pic.FLAG_WARM_START_ONLY | pic.FLAG_LEARNED_MIXED | pic.FLAG_MIXED_RELIABLE
+    ctx = pic.Context(prm)
+    ctx.set_unet(f32dev(unet.flatten(_params(17), specs)))
+    x = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.poisson(torch.from_numpy(b).cuda(), x)
+    assert info["converged"] and info["outer_iterations"] >= 1 and info["flex_iterations"] == 0
+    assert orc.residual_norm(N, P.L, b, x.cpu().numpy()) <= 1.0001e-10 * np.linalg.norm(b)
