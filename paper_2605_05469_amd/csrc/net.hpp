@@ -18,7 +18,7 @@ hipError_t conv_fwd(int n, int ci, int co, const uint16_t* X, const uint16_t* fr
 // up-sampling applied while staging (z-marching kernel only).
 bool conv_up_fused(int n, int ci, int co);
 // Y = relu(conv(X) + b) and Yp = avgpool2(Y) (BF16) in one pass (z-marching
-// kernel, 16->16 and 32->32, grids that are multiples of 64).
+// kernel, 32->32, grids that are multiples of 64).
 bool conv_pool_fused(int n, int ci, int co);
 hipError_t conv_fwd_pool(int n, int ci, int co, const uint16_t* X, const uint16_t* frag,
                          const float* bias, uint16_t* Y, uint16_t* Yp, hipStream_t s);
