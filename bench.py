@@ -160,8 +160,11 @@ def bench_poisson(args):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()  # the library allocates the network outside torch
     forms = {}
-    for form in ("pcg_fp64", "pcg_mixed", "pcg_mixed_reliable", "fcg_learned",
-                 "learned_warm_start_only", "learned_warm_start_mixed"):
+    all_forms = ("pcg_fp64", "pcg_mixed", "pcg_mixed_reliable", "fcg_learned",
+                 "learned_warm_start_only", "learned_warm_start_mixed")
+    for form in (args.forms.split(",") if args.forms else all_forms):
+        if form not in all_forms:
+            raise SystemExit("unknown form %r (choose from %s)" % (form, ", ".join(all_forms)))
         solver = ("fcg_learned" if form.startswith("learned") else
                   "pcg_mixed" if form.startswith("pcg_mixed") else form)
         if solver == "fcg_learned":
@@ -222,6 +225,8 @@ def main():
                     help="FP32 network parameters (.npy, canonical order) for fcg_learned")
     ap.add_argument("--inner-rtol", type=float, default=1e-3)
     ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--forms", default=None,
+                    help="poisson workload: comma-separated solver forms to time (default: all)")
     ap.add_argument("--learned-mixed", action="store_true",
                     help="learned form: hand over to the mixed form (not FP64 PCG)")
     ap.add_argument("--mixed-reliable", action="store_true",
