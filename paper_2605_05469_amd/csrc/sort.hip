@@ -209,16 +209,17 @@ __global__ __launch_bounds__(256) void cell_start_kernel(int64_t np, int64_t nce
 }
 
 // One payload array per launch: dst[j] = src[perm[j]].  Each workgroup
-// gathers one contiguous chunk of the sorted order; chunk ids are remapped so
-// that each XCD walks a contiguous range, whose sources (the particles of
-// neighbouring cells before the push) then stay in that XCD's L2 while the
-// rows around it are gathered.  Stores bypass L2 retention.
+// gathers one contiguous chunk of the sorted order, in dispatch order, so the
+// whole GPU advances through the output together: the sources of the chunks in
+// flight (the particles of the cells within a step's travel, a band of a few
+// z-planes) stay in the shared last-level cache.  (Giving each XCD its own
+// contiguous eighth of the output puts eight such bands in flight and
+// over-fetched 10x.)  Stores bypass L2 retention.
 constexpr int kPermChunk = 4096;
 __global__ __launch_bounds__(256) void permute1_kernel(int64_t np, const uint32_t* __restrict__ perm,
                                                        const double* __restrict__ src,
                                                        double* __restrict__ dst) {
-    const uint32_t lb = remap_xcd(blockIdx.x, gridDim.x);
-    const int64_t base = (int64_t)lb * kPermChunk;
+    const int64_t base = (int64_t)blockIdx.x * kPermChunk;
 #pragma unroll 4
     for (int k = threadIdx.x; k < kPermChunk; k += 256) {
         const int64_t j = base + k;
