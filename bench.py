@@ -209,6 +209,76 @@ def bench_poisson(args):
     print(json.dumps(out), flush=True)
 
 
+# flops of one network application per fine-grid point: 2 * 27 * ci * co per
+# output point of each 3^3 convolution, levels 1, 2, 3 at 1, 1/8, 1/64 points
+NET_LAYERS = (("e1a", 1, 16, 1), ("e1b", 16, 16, 1), ("e2a", 16, 32, 2), ("e2b", 32, 32, 2),
+              ("b3a", 32, 64, 3), ("b3b", 64, 32, 3), ("d2a", 32, 32, 2), ("d2b", 32, 16, 2),
+              ("d1a", 16, 16, 1), ("out", 16, 1, 1))
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def net_flops(n):
+    return sum(2 * 27 * ci * co * (n >> (lvl - 1)) ** 3 for _, ci, co, lvl in NET_LAYERS)
+
+
+def bench_network(args):
+    """The learned preconditioner's network alone: z = s NN(h^2 r / s) - mean
+    on an n^3 grid (inference), and one training step (forward, loss,
+    backward, Adam) at the training grid; HIP events on the library's stream."""
+    import numpy as np
+    import torch
+
+    import paper_2605_05469_amd as P
+
+    n = args.grid
+    net = P.Net(n)
+    path = args.weights or os.path.join(ROOT, "paper_2605_05469_amd", "weights",
+                                        "unet_landau128.npy")
+    params = torch.from_numpy(np.load(path, allow_pickle=False).astype(np.float32)).cuda()
+    net.set_params(params)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(args.seed)
+    r = torch.randn(n ** 3, device="cuda", dtype=torch.float64, generator=g)
+    z = torch.empty_like(r)
+    h = 4 * math.pi / n
+
+    def timed(fn, reps):
+        for _ in range(args.warmup):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms = timed(lambda: net.precondition(r, h, z), args.steps)
+    fl = net_flops(n)
+    del net
+    torch.cuda.empty_cache()
+    nt = 128
+    tnet = P.Net(nt, training=True)
+    tnet.set_params(params)
+    x = torch.randn(nt ** 3, device="cuda", generator=g)
+    t = torch.randn(nt ** 3, device="cuda", generator=g)
+    ms_train = timed(lambda: tnet.train_step(x, t, lam=1.0, lr=1e-5, want_loss=False), args.steps)
+    tf = fl / (ms * 1e-3) / 1e12
+    out = {"metric": "network preconditioner application time (ms), BF16 MFMA",
+           "value": ms, "unit": "ms/application", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "unet_precondition_%d^3" % n, "grid": n,
+                      "channels": [16, 32, 64], "levels": 3},
+           "tflop_per_application": fl / 1e12,
+           "train_step_ms_128": ms_train,
+           "train_tflops_128": 3 * net_flops(nt) / (ms_train * 1e-3) / 1e12,
+           "roofline": {"bound": "mfma", "kernel": "whole network", "achieved": tf,
+                        "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tf / PEAK_BF16_TFLOPS, "traffic": None}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,8 +305,9 @@ def main():
                     help="learned form: network warm start, then Jacobi-PCG")
     ap.add_argument("--accuracy-vs-fp64", action="store_true",
                     help="rerun the same steps with the FP64 solver and report the differences")
-    ap.add_argument("--workload", default="pic", choices=["pic", "poisson"],
-                    help="pic: full PIC steps; poisson: standalone solves of a deposited rho")
+    ap.add_argument("--workload", default="pic", choices=["pic", "poisson", "network"],
+                    help="pic: full PIC steps; poisson: standalone solves of a deposited rho; "
+                         "network: the learned preconditioner alone")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -252,6 +323,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "poisson":
         return bench_poisson(args)
+    if args.workload == "network":
+        return bench_network(args)
     N, ppc = args.grid, args.ppc
     p = P.landau_params(N, ppc, rtol=args.rtol, solver=args.solver, check_every=32,
                         inner_rtol=args.inner_rtol)
@@ -289,7 +362,9 @@ def main():
     iters = sum(i["iterations"] for i in infos) / len(infos)
     n3 = N ** 3
     npart = ppc * n3
-    bdir, bupd = SWEEP_BYTES[args.solver]
+    # the timed sweeps are the FP32 inner ones when the learned form hands over
+    # to the mixed form
+    bdir, bupd = SWEEP_BYTES["pcg_mixed" if args.learned_mixed else args.solver]
     ms_dir, cnt_dir = P.Context.kernel_time(ctx, 0)
     ms_upd, cnt_upd = P.Context.kernel_time(ctx, 1)
     # (pic_step accumulates the sampled kernel times over all timed steps)
@@ -313,7 +388,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.solver != "pcg_mixed" else "f32+f64",
+        "dtype": "f32+f64" if (args.solver == "pcg_mixed" or args.learned_mixed) else "f64",
         "data": "synthetic",
         "config": {"workload": "landau_damping_%d^3_%dppc_%s" % (N, ppc, args.solver),
                    "grid": N, "ppc": ppc, "particles": npart, "solver": args.solver,

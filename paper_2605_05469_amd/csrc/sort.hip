@@ -140,6 +140,14 @@ static hipError_t exclusive_scan(uint32_t* a, int64_t m, uint32_t* sums, hipStre
 }
 
 // ---------------------------------------------------------------- pass 3 --
+// Stable scatter of one tile.  The tile's items are first ranked in input
+// order within their digit (8 ballots match equal digits inside a wave; LDS
+// running counts carry across waves and rounds) and placed, in digit order,
+// in LDS; a second loop then walks the LDS copy in order, so consecutive
+// threads write consecutive slots of each digit's output run (coalesced
+// stores instead of one 4-byte store per bucket and lane).  The tile's digit
+// counts are differences of consecutive entries of the scanned, digit-major
+// histogram table.
 __global__ __launch_bounds__(kSortNT) void scatter_kernel(int64_t np,
                                                            const uint32_t* __restrict__ kin,
                                                            const uint32_t* __restrict__ iin,
@@ -148,23 +156,48 @@ __global__ __launch_bounds__(kSortNT) void scatter_kernel(int64_t np,
                                                            const uint32_t* __restrict__ hist,
                                                            int64_t tiles) {
     constexpr int NW = kSortNT / kWave;
-    __shared__ uint32_t base_d[kRadix];
+    __shared__ uint32_t gbase[kRadix];  // global first slot of each digit for this tile
+    __shared__ uint32_t loff[kRadix];   // tile-local first slot of each digit
+    __shared__ uint32_t run[kRadix];    // items of each digit placed so far
     __shared__ uint32_t wcnt[NW][kRadix];
+    __shared__ uint32_t wsum[NW];
+    __shared__ uint32_t skey[kTile];
+    __shared__ uint32_t sidx[kTile];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const int64_t t = blockIdx.x;
-    base_d[tid] = hist[(int64_t)tid * tiles + t];
+    const int64_t tbase = t * kTile;
+    const int64_t nvalid64 = np - tbase < kTile ? np - tbase : kTile;
+    const int nvalid = (int)nvalid64;
+    // this tile's count of digit tid, and the exclusive scan over digits
+    const int64_t hi = (int64_t)tid * tiles + t;
+    const uint32_t g0 = hist[hi];
+    const uint32_t g1 = hi + 1 < (int64_t)kRadix * tiles ? hist[hi + 1] : (uint32_t)np;
+    const uint32_t c = g1 - g0;
+    gbase[tid] = g0;
+    uint32_t inc = c;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t v = __shfl_up(inc, off, kWave);
+        if (lane >= off) inc += v;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
 #pragma unroll
     for (int j = 0; j < NW; ++j) wcnt[j][tid] = 0;
+    run[tid] = 0;
     __syncthreads();
+    uint32_t wpre = 0;
+    for (int j = 0; j < w; ++j) wpre += wsum[j];
+    loff[tid] = wpre + inc - c;
+    __syncthreads();
+
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-    const int64_t tbase = t * kTile;
     for (int k = 0; k < kIPT; ++k) {
-        const int64_t i = tbase + (int64_t)k * kSortNT + tid;
-        const bool valid = i < np;
+        const int li = k * kSortNT + tid;
+        const int64_t i = tbase + li;
+        const bool valid = li < nvalid;
         const uint32_t kv = valid ? kin[i] : 0u;
         const uint32_t iv = valid ? (iin ? iin[i] : (uint32_t)i) : 0u;
         const uint32_t d = (kv >> shift) & (kRadix - 1);
-        // lanes of this wave holding the same digit (invalid lanes excluded)
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < 8; ++bit) {
@@ -175,22 +208,26 @@ __global__ __launch_bounds__(kSortNT) void scatter_kernel(int64_t np,
         const bool leader = valid && rank == 0;
         if (leader) wcnt[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
-        uint32_t pre = 0;
         if (valid) {
-            pre = base_d[d];
+            uint32_t pre = loff[d] + run[d];
             for (int j = 0; j < w; ++j) pre += wcnt[j][d];
+            skey[pre + rank] = kv;
+            sidx[pre + rank] = iv;
         }
         uint32_t tot = 0;
 #pragma unroll
         for (int j = 0; j < NW; ++j) tot += wcnt[j][tid];
         __syncthreads();
-        base_d[tid] += tot;
+        run[tid] += tot;
         if (leader) wcnt[w][d] = 0;
-        if (valid) {
-            const uint32_t pos = pre + rank;
-            kout[pos] = kv;
-            iout[pos] = iv;
-        }
+    }
+    __syncthreads();
+    for (int j = tid; j < nvalid; j += kSortNT) {
+        const uint32_t kv = skey[j];
+        const uint32_t d = (kv >> shift) & (kRadix - 1);
+        const uint32_t pos = gbase[d] + ((uint32_t)j - loff[d]);
+        kout[pos] = kv;
+        iout[pos] = sidx[j];
     }
 }
 
@@ -208,23 +245,22 @@ __global__ __launch_bounds__(256) void cell_start_kernel(int64_t np, int64_t nce
     }
 }
 
-// One payload array per launch: dst[j] = src[perm[j]].  Each workgroup
-// gathers one contiguous chunk of the sorted order, in dispatch order, so the
-// whole GPU advances through the output together: the sources of the chunks in
-// flight (the particles of the cells within a step's travel, a band of a few
-// z-planes) stay in the shared last-level cache.  (Giving each XCD its own
-// contiguous eighth of the output puts eight such bands in flight and
-// over-fetched 10x.)  Stores bypass L2 retention.
-constexpr int kPermChunk = 4096;
+// One payload array per launch: dst[j] = src[perm[j]].  A particle moves a
+// few cells per step, so the sources of a run of sorted slots are the
+// particles of the same cells' neighbourhood before the push: about 5 x 5 row
+// segments (+-2 cells in y and z) of the previous order.  Workgroup ids are
+// remapped so each XCD walks a contiguous range of the output in dispatch
+// order, and a workgroup gathers only 256 slots, so the workgroups resident on
+// an XCD at a time cover a few rows, whose source rows fit in that XCD's L2.
+// (With 4096-slot chunks the resident window spanned hundreds of rows and
+// the gather fetched 10x its bytes into L2.)  Stores bypass L2 retention.
+constexpr int kPermChunk = 256;
 __global__ __launch_bounds__(256) void permute1_kernel(int64_t np, const uint32_t* __restrict__ perm,
                                                        const double* __restrict__ src,
                                                        double* __restrict__ dst) {
-    const int64_t base = (int64_t)blockIdx.x * kPermChunk;
-#pragma unroll 4
-    for (int k = threadIdx.x; k < kPermChunk; k += 256) {
-        const int64_t j = base + k;
-        if (j < np) __builtin_nontemporal_store(src[perm[j]], dst + j);
-    }
+    const uint32_t lb = remap_xcd(blockIdx.x, gridDim.x);
+    const int64_t j = (int64_t)lb * kPermChunk + threadIdx.x;
+    if (j < np) __builtin_nontemporal_store(src[perm[j]], dst + j);
 }
 
 __global__ void copy_u32_kernel(int64_t n, const uint32_t* __restrict__ a, uint32_t* __restrict__ b) {
