@@ -32,7 +32,8 @@ PEAK_HBM_GBS = 8000.0
 # algorithmic bytes per grid point of one launch of each PCG sweep (FP64):
 # direction sweep reads r, p_old and writes p_new; update sweep reads p, x, r
 # and writes x, r.  (FP32 inner sweeps of the mixed form: half.)
-SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 40)}
+SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 40),
+               "pcg_ssor": (24, 40)}
 # HBM bytes per launch of the FP64 update sweep at 512^3, from rocprofv3
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
@@ -173,7 +174,7 @@ def bench_poisson(args):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()  # the library allocates the network outside torch
     forms = {}
-    all_forms = ("pcg_fp64", "pcg_mixed", "pcg_mixed_reliable", "fcg_learned",
+    all_forms = ("pcg_fp64", "pcg_mixed", "pcg_mixed_reliable", "pcg_ssor", "fcg_learned",
                  "learned_warm_start_only", "learned_warm_start_mixed")
     for form in (args.forms.split(",") if args.forms else all_forms):
         if form not in all_forms:

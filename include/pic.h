@@ -51,7 +51,9 @@ enum {
 enum {
     PIC_SOLVER_PCG_FP64 = 0,   /* Jacobi-PCG in FP64 (Sec. 3.2)                */
     PIC_SOLVER_PCG_MIXED = 1,  /* FP32 inner PCG inside FP64 refinement        */
-    PIC_SOLVER_FCG_LEARNED = 2 /* flexible PCG, U-Net warm start/precond.      */
+    PIC_SOLVER_FCG_LEARNED = 2, /* flexible PCG, U-Net warm start/precond.     */
+    PIC_SOLVER_PCG_SSOR = 3     /* FP64 PCG with the SSOR preconditioner of the
+                                   paper's runs (Sec. 4.1), see ssor_* below  */
 };
 
 /* Problem statement (Sec. 2 and 2.1; tolerance as in Sec. 4). */
@@ -84,6 +86,14 @@ typedef struct pic_params {
     int64_t max_outer;    /* mixed: refinement step cap                     */
     int32_t fcg_window;   /* learned: stall window (iterations)             */
     int32_t flags;        /* PIC_FLAG_* bits (above) */
+    /* SSOR form (Sec. 4.1: four inner, two outer iterations, damping pi/2).
+     * One application: z = w(2-w) (D + wU)^-1 D (D + wL)^-1 r with each cyclic
+     * "triangular" solve replaced by ssor_inner Jacobi steps (L, U = backward,
+     * forward neighbours); ssor_outer stationary steps z += SSOR(r - A z).
+     * 0 selects the paper's values (w = pi/2, 4, 2). */
+    double ssor_omega;    /* damping w in (0, 2)                            */
+    int32_t ssor_inner;   /* Jacobi steps per triangular solve (>= 1)        */
+    int32_t ssor_outer;   /* stationary SSOR steps per application (>= 1)    */
 } pic_params;
 
 /* Host-side result of one Poisson solve. */

@@ -13,6 +13,7 @@ pieces of the learned preconditioner are in ``oracle.unet`` (NumPy, FP64).
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -71,6 +72,9 @@ def lib():
                                    _dp, _dp, _dp, _dp, _dp, _dp]
         L.or_gather_scalar.argtypes = [c_i64, c_int, c_dbl, _dp, _dp, _dp, _dp, _dp]
         L.or_mixed_pcg.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_dbl, c_i64, _dp]
+        L.or_ssor_apply.argtypes = [c_int, c_dbl, c_dbl, c_int, c_int, _dp, _dp]
+        L.or_ssor_apply.restype = c_int
+        L.or_pcg_ssor.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_dbl, c_int, c_int, _dp]
         L.or_mixed_pcg_ex.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_dbl, c_i64,
                                       ctypes.c_int, _dp]
         L.or_deposit_vertices.argtypes = [c_i64, c_int, c_dbl, c_dbl, _dp, _dp, _dp, c_i64, _i64p, _dp]
@@ -149,6 +153,28 @@ def pcg(N: int, L: float, b, x0, rtol: float, max_iter: int):
     x = _f64(x0).reshape(-1).copy()
     info = np.zeros(5)
     lib().or_pcg(N, L, b, x, rtol, max_iter, info)
+    return x, dict(iters=int(info[0]), rel_res=info[1], true_rel_res=info[2],
+                   converged=bool(info[3]), replacements=int(info[4]))
+
+
+SSOR_OMEGA = math.pi / 2  # the damping factor of the paper's PCG runs (Sec. 4.1)
+
+
+def ssor_apply(N, L, r, omega=SSOR_OMEGA, inner=4, outer=2):
+    """z = SSOR preconditioner applied to r (see or_ssor_apply)."""
+    r = _f64(r).reshape(-1)
+    z = np.empty_like(r)
+    if lib().or_ssor_apply(N, L, omega, inner, outer, r, z) != 0:
+        raise MemoryError("or_ssor_apply")
+    return z
+
+
+def pcg_ssor(N, L, b, x0, rtol, max_iter, omega=SSOR_OMEGA, inner=4, outer=2):
+    """PCG with the SSOR preconditioner; returns (x, info dict) as pcg()."""
+    b = _f64(b).reshape(-1)
+    x = _f64(x0).reshape(-1).copy()
+    info = np.zeros(5)
+    lib().or_pcg_ssor(N, L, b, x, rtol, max_iter, omega, inner, outer, info)
     return x, dict(iters=int(info[0]), rel_res=info[1], true_rel_res=info[2],
                    converged=bool(info[3]), replacements=int(info[4]))
 

@@ -271,6 +271,144 @@ void or_pcg(int N, double L, const double *b, double *x, double rtol, int64_t ma
 }
 
 /* ------------------------------------------------------------------------ */
+/* SSOR preconditioner (Sec. 4.1: the PCG runs used SSOR "with four inner and
+ * two outer iterations, and a damping factor of pi/2"; the paper does not
+ * define inner and outer).  Reading: A = D + L + U with D = (6/h^2) I, L the
+ * backward neighbours (x-1, y-1, z-1, periodic) and U = L^T the forward ones;
+ * one SSOR application is
+ *     z = w (2 - w) (D + w U)^{-1} D (D + w L)^{-1} r,     w = damping,
+ * with each "triangular" solve (cyclic on the periodic grid) approximated by
+ * `inner` Jacobi iterations started from D^{-1} times the right-hand side:
+ *     y_0 = D^{-1} r,   y_{j+1} = D^{-1} r + (w/6) (y_j[i-ex] + y_j[i-ey] + y_j[i-ez]),
+ *     z_0 = y,          z_{j+1} = y + (w/6) (z_j[i+ex] + z_j[i+ey] + z_j[i+ez]),
+ * (D^{-1} w/h^2 = w/6), then z <- w (2 - w) z_inner.  The approximate solves
+ * are polynomials in the backward (forward) shift, each the transpose of the
+ * other, so the preconditioner is symmetric.  `outer` stationary steps:
+ *     z <- z + SSOR(r - A z)   after the first z = SSOR(r).                */
+static void or_ssor_once(int N, double inv_h2, double omega, int inner, const double *r,
+                         double *z, double *y, double *t)
+{
+    int64_t n3 = (int64_t)N * N * N;
+    double dinv = 1.0 / (6.0 * inv_h2);
+    double c = omega / 6.0;
+    for (int64_t i = 0; i < n3; ++i) y[i] = dinv * r[i];
+    for (int j = 0; j < inner; ++j) {
+        for (int iz = 0; iz < N; ++iz) {
+            int zm = (iz + N - 1) % N;
+            for (int iy = 0; iy < N; ++iy) {
+                int ym = (iy + N - 1) % N;
+                for (int ix = 0; ix < N; ++ix) {
+                    int xm = (ix + N - 1) % N;
+                    double s = (y[OR_IDX(N, xm, iy, iz)] + y[OR_IDX(N, ix, ym, iz)]) +
+                               y[OR_IDX(N, ix, iy, zm)];
+                    t[OR_IDX(N, ix, iy, iz)] = dinv * r[OR_IDX(N, ix, iy, iz)] + c * s;
+                }
+            }
+        }
+        for (int64_t i = 0; i < n3; ++i) y[i] = t[i];
+    }
+    for (int64_t i = 0; i < n3; ++i) z[i] = y[i];
+    for (int j = 0; j < inner; ++j) {
+        for (int iz = 0; iz < N; ++iz) {
+            int zp = (iz + 1) % N;
+            for (int iy = 0; iy < N; ++iy) {
+                int yp = (iy + 1) % N;
+                for (int ix = 0; ix < N; ++ix) {
+                    int xp = (ix + 1) % N;
+                    double s = (z[OR_IDX(N, xp, iy, iz)] + z[OR_IDX(N, ix, yp, iz)]) +
+                               z[OR_IDX(N, ix, iy, zp)];
+                    t[OR_IDX(N, ix, iy, iz)] = y[OR_IDX(N, ix, iy, iz)] + c * s;
+                }
+            }
+        }
+        for (int64_t i = 0; i < n3; ++i) z[i] = t[i];
+    }
+    double sc = omega * (2.0 - omega);
+    for (int64_t i = 0; i < n3; ++i) z[i] = sc * z[i];
+}
+
+int or_ssor_apply(int N, double L, double omega, int inner, int outer, const double *r, double *z)
+{
+    int64_t n3 = (int64_t)N * N * N;
+    double inv_h = (double)N / L;
+    double inv_h2 = inv_h * inv_h;
+    double *y = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *t = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *res = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *dz = (double *)malloc(sizeof(double) * (size_t)n3);
+    if (!y || !t || !res || !dz) { free(y); free(t); free(res); free(dz); return -1; }
+    or_ssor_once(N, inv_h2, omega, inner, r, z, y, t);
+    for (int o = 1; o < outer; ++o) {
+        or_apply_A(N, L, z, res);
+        for (int64_t i = 0; i < n3; ++i) res[i] = r[i] - res[i];
+        or_ssor_once(N, inv_h2, omega, inner, res, dz, y, t);
+        for (int64_t i = 0; i < n3; ++i) z[i] = z[i] + dz[i];
+    }
+    free(y); free(t); free(res); free(dz);
+    return 0;
+}
+
+/* PCG with the SSOR preconditioner: or_pcg's iteration and stopping rule with
+ * z = SSOR(r) in place of the Jacobi scaling.  info as in or_pcg.          */
+void or_pcg_ssor(int N, double L, const double *b, double *x, double rtol, int64_t max_iter,
+                 double omega, int inner, int outer, double *info)
+{
+    int64_t n3 = (int64_t)N * N * N;
+    double *r = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *z = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *p = (double *)malloc(sizeof(double) * (size_t)n3);
+    double *q = (double *)malloc(sizeof(double) * (size_t)n3);
+    int64_t it = 0, repl = 0;
+    int converged = 0;
+    double rel = 0.0, trel = 0.0;
+    double nb = sqrt(or_dot(n3, b, b));
+    if (nb == 0.0) {
+        for (int64_t i = 0; i < n3; ++i) x[i] = 0.0;
+        info[0] = 0; info[1] = 0.0; info[2] = 0.0; info[3] = 1; info[4] = 0;
+        free(r); free(z); free(p); free(q);
+        return;
+    }
+    double tol = rtol * nb;
+    double nr = or_true_residual(N, L, b, x, r);
+    rel = trel = nr / nb;
+    if (nr <= tol) converged = 1;
+    or_ssor_apply(N, L, omega, inner, outer, r, z);
+    for (int64_t i = 0; i < n3; ++i) p[i] = z[i];
+    double rz = or_dot(n3, r, z);
+    while (!converged && it < max_iter) {
+        or_apply_A(N, L, p, q);
+        double alpha = rz / or_dot(n3, p, q);
+        for (int64_t i = 0; i < n3; ++i) {
+            x[i] = x[i] + alpha * p[i];
+            r[i] = r[i] - alpha * q[i];
+        }
+        ++it;
+        double rn = sqrt(or_dot(n3, r, r));
+        rel = rn / nb;
+        if (rn <= tol) {
+            double tn = or_true_residual(N, L, b, x, q);
+            trel = tn / nb;
+            if (tn <= tol) { converged = 1; break; }
+            for (int64_t i = 0; i < n3; ++i) r[i] = q[i];
+            or_ssor_apply(N, L, omega, inner, outer, r, z);
+            for (int64_t i = 0; i < n3; ++i) p[i] = z[i];
+            rz = or_dot(n3, r, z);
+            rel = tn / nb;
+            ++repl;
+            continue;
+        }
+        or_ssor_apply(N, L, omega, inner, outer, r, z);
+        double rz_new = or_dot(n3, r, z);
+        double beta = rz_new / rz;
+        rz = rz_new;
+        for (int64_t i = 0; i < n3; ++i) p[i] = z[i] + beta * p[i];
+    }
+    if (!converged) trel = or_residual_norm(N, L, b, x) / nb;
+    info[0] = (double)it; info[1] = rel; info[2] = trel; info[3] = converged; info[4] = (double)repl;
+    free(r); free(z); free(p); free(q);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Field from potential (Sec. 2, Eq. poisson: E = -grad phi) with the
  * second-order central difference that matches the Laplacian:
  *   E_d[i] = -(phi[i+e_d] - phi[i-e_d]) / (2h).

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_NOT_CONVERGED = 0, 1
 PIC_ERR_INVALID, PIC_ERR_HIP, PIC_ERR_NOMEM, PIC_ERR_STATE = -1, -2, -3, -4
-SOLVERS = {"pcg_fp64": 0, "pcg_mixed": 1, "fcg_learned": 2}
+SOLVERS = {"pcg_fp64": 0, "pcg_mixed": 1, "fcg_learned": 2, "pcg_ssor": 3}
 FLAG_NO_WARM_START = 1
 FLAG_WARM_START_ONLY = 2
 FLAG_MIXED_RELIABLE = 4
@@ -38,7 +38,8 @@ class pic_params(ctypes.Structure):
                 ("solver", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("inner_rtol", ctypes.c_double), ("max_inner", ctypes.c_int64),
                 ("max_outer", ctypes.c_int64), ("fcg_window", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("ssor_omega", ctypes.c_double),
+                ("ssor_inner", ctypes.c_int32), ("ssor_outer", ctypes.c_int32)]
 
 
 class pic_solve_info(ctypes.Structure):
@@ -174,7 +175,8 @@ def _stream(stream=None):
 
 def landau_params(N, ppc, k=0.5, dt=0.05, qm=-1.0, rtol=1e-10, max_iter=20000,
                   solver="pcg_fp64", np_max=None, check_every=16, inner_rtol=1e-3,
-                  max_inner=20000, max_outer=50, fcg_window=10):
+                  max_inner=20000, max_outer=50, fcg_window=10, ssor_omega=math.pi / 2,
+                  ssor_inner=4, ssor_outer=2):
     """Parameters of the Landau-damping box (Sec. 2.1): L = 2 pi / k, unit
     mean density, q = -L^3/Np, background +1."""
     L = 2.0 * math.pi / k
@@ -190,6 +192,7 @@ def landau_params(N, ppc, k=0.5, dt=0.05, qm=-1.0, rtol=1e-10, max_iter=20000,
     p.check_every = check_every
     p.inner_rtol, p.max_inner, p.max_outer = inner_rtol, max_inner, max_outer
     p.fcg_window = fcg_window
+    p.ssor_omega, p.ssor_inner, p.ssor_outer = ssor_omega, ssor_inner, ssor_outer
     return p
 
 

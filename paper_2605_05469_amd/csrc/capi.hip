@@ -74,6 +74,7 @@ struct pic_ctx {
     double* fz = nullptr;          // flexible CG: z = M(r)
     double* fq = nullptr;          //              q = A p
     double* fw = nullptr;          //              warm-start trial / true residual
+    double* sv[6] = {};            // SSOR form: z, q, two forward, one backward, r - A z
     std::vector<void*> allocs;
     // kernel timing
     bool timing = false;
@@ -99,8 +100,11 @@ static int validate_params(const pic_params* p) {
         return fail(PIC_ERR_INVALID, "np_max must be in [0, 2^32)");
     if (!(p->rtol > 0.0) || !std::isfinite(p->rtol)) return fail(PIC_ERR_INVALID, "rtol must be > 0");
     if (p->max_iter < 0) return fail(PIC_ERR_INVALID, "max_iter must be >= 0");
-    if (p->solver < PIC_SOLVER_PCG_FP64 || p->solver > PIC_SOLVER_FCG_LEARNED)
+    if (p->solver < PIC_SOLVER_PCG_FP64 || p->solver > PIC_SOLVER_PCG_SSOR)
         return fail(PIC_ERR_INVALID, "unknown solver %d", p->solver);
+    if (!(p->ssor_omega >= 0.0 && p->ssor_omega < 2.0) || p->ssor_inner < 0 || p->ssor_outer < 0)
+        return fail(PIC_ERR_INVALID, "ssor_omega must be in (0, 2) (0: default), "
+                                     "ssor_inner and ssor_outer >= 0 (0: default)");
     if (!std::isfinite(p->charge) || !std::isfinite(p->qm) || !std::isfinite(p->dt) ||
         !std::isfinite(p->rho_bg))
         return fail(PIC_ERR_INVALID, "charge, qm, dt and rho_bg must be finite");
@@ -164,6 +168,20 @@ static int ensure_learned(pic_ctx* c) {
     c->fz = (double*)m;
     c->fq = (double*)((char*)m + vb);
     c->fw = (double*)((char*)m + 2 * vb);
+    return PIC_OK;
+}
+
+static size_t ssor_bytes(const pic_params* p) {
+    const int64_t n3 = (int64_t)p->n * p->n * p->n;
+    return 6 * vec_bytes(n3, 8);
+}
+
+static int ensure_ssor(pic_ctx* c) {
+    if (c->sv[0]) return PIC_OK;
+    void* m = nullptr;
+    RETCHK(dev_alloc(c, &m, ssor_bytes(&c->p)));
+    const size_t vb = vec_bytes(c->n3, 8);
+    for (int i = 0; i < 6; ++i) c->sv[i] = (double*)((char*)m + i * vb);
     return PIC_OK;
 }
 
@@ -528,6 +546,137 @@ static int solve_learned(pic_ctx* c, const double* b, double* x, pic_solve_info*
     return PIC_OK;
 }
 
+// ------------------------------------------------------------- SSOR form --
+// The paper's preconditioner (Sec. 4.1: SSOR, four inner and two outer
+// iterations, damping pi/2), matrix-free: one application is
+//   y_0 = D^-1 r,  y_{j+1} = D^-1 r + (w/6) (y_j[i-ex] + y_j[i-ey] + y_j[i-ez]),
+//   z_0 = y,       z_{j+1} = y + (w/6) (z_j[i+ex] + z_j[i+ey] + z_j[i+ez]),
+//   z = w (2 - w) z_inner,
+// j < inner (Jacobi steps for the cyclic triangular solves), each step one
+// z-marching half-stencil sweep; `outer` stationary steps add SSOR(r - A z).
+// The last sweep of the application reduces r . z for PCG.
+// Buffers: sv[2], sv[3] forward ping-pong, sv[4] backward, sv[5] = r - A z.
+static int ssor_once(pic_ctx* c, const double* rhs, double* out, const double* add,
+                     const double* rdot, hipStream_t s) {
+    const SweepGeo& g = c->geo;
+    const int k = c->p.ssor_inner;
+    const double w = c->p.ssor_omega;
+    const double cc = w / 6.0, dinv = c->minv, sc = w * (2.0 - w);
+    double* ya = c->sv[2];
+    double* yb = c->sv[3];
+    const double* stage = rhs;
+    double sscale = dinv;
+    double* dst = ya;
+    for (int j = 0; j < k; ++j) {
+        dst = (j & 1) ? yb : ya;
+        HIPCHK(launch_ssor_half(g, stage, rhs, nullptr, nullptr, dst, cc, dinv, sscale, 1.0, 0,
+                                c->st, c->partials, s));
+        stage = dst;
+        sscale = 1.0;
+    }
+    double* Y = dst;                       // y_inner
+    double* other = (Y == ya) ? yb : ya;   // free forward buffer
+    double* zb[2] = {c->sv[4], other};
+    stage = Y;
+    for (int j = 0; j < k; ++j) {
+        const bool last = j + 1 == k;
+        double* d = last ? out : zb[j & 1];
+        HIPCHK(launch_ssor_half(g, stage, Y, last ? add : nullptr, last ? rdot : nullptr, d, cc, 1.0,
+                                1.0, last ? sc : 1.0, 1, c->st, c->partials, s));
+        stage = d;
+    }
+    return PIC_OK;
+}
+
+// z = SSOR^outer(r); r . z into st->flex_zr.
+static int ssor_apply(pic_ctx* c, const double* r, double* z, hipStream_t s) {
+    const int o = c->p.ssor_outer;
+    RETCHK(ssor_once(c, r, z, nullptr, o == 1 ? r : nullptr, s));
+    for (int i = 1; i < o; ++i) {
+        HIPCHK(launch_resid_norm(c->geo, r, z, c->sv[5], c->inv_h2, c->st, c->partials, s));
+        RETCHK(ssor_once(c, c->sv[5], z, z, i + 1 == o ? r : nullptr, s));
+    }
+    return PIC_OK;
+}
+
+// PCG with the SSOR preconditioner; iteration and stopping rule of the FP64
+// form (recursive residual, then the true residual, one replacement on a
+// failed check).
+static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* out,
+                      hipStream_t s) {
+    RETCHK(ensure_ssor(c));
+    const SweepGeo& g = c->geo;
+    const int64_t n3 = c->n3;
+    double* z = c->sv[0];
+    double* q = c->sv[1];
+    double* p = c->p2[0];
+    HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 1, c->p.rtol, c->p.max_iter, c->st,
+                             c->partials, s));
+    RETCHK(read_state(c, s));
+    const double nb = c->st_host->cg.nb, tol = c->st_host->cg.tol;
+    out->norm_b = nb;
+    if (c->st_host->cg.state == CG_ZERO_RHS) {
+        HIPCHK(launch_fill(n3, x, 0.0, s));
+        out->converged = 1;
+        return PIC_OK;
+    }
+    double rn = c->st_host->cg.true_rn;
+    out->rel_res = rn / nb;
+    if (rn <= tol) {
+        out->converged = 1;
+        return PIC_OK;
+    }
+    RETCHK(ssor_apply(c, c->r, z, s));
+    HIPCHK(launch_copy(n3, z, p, s));
+    RETCHK(read_state(c, s));
+    double rz = c->st_host->flex_zr;
+    int64_t it = 0;
+    while (it < c->p.max_iter) {
+        HIPCHK(launch_aq(g, p, q, c->inv_h2, c->st, c->partials, s));
+        RETCHK(read_state(c, s));
+        const double pq = c->st_host->flex_pq;
+        const double alpha = rz / pq;
+        if (!std::isfinite(alpha) || !(pq > 0.0)) break;
+        HIPCHK(launch_fcg_update(n3, x, c->r, p, q, alpha, c->st, c->partials, s));
+        RETCHK(read_state(c, s));
+        ++it;
+        rn = std::sqrt(c->st_host->flex_rr);
+        out->rel_res = rn / nb;
+        if (!std::isfinite(rn)) break;
+        if (rn <= tol) {
+            HIPCHK(launch_resid_norm(g, b, x, c->fw ? c->fw : c->sv[5], c->inv_h2, c->st,
+                                     c->partials, s));
+            RETCHK(read_state(c, s));
+            const double tn = c->st_host->out_nr;
+            out->rel_res = tn / nb;
+            if (tn <= tol) {
+                out->converged = 1;
+                break;
+            }
+            HIPCHK(launch_copy(n3, c->fw ? c->fw : c->sv[5], c->r, s));
+            RETCHK(ssor_apply(c, c->r, z, s));
+            HIPCHK(launch_copy(n3, z, p, s));
+            RETCHK(read_state(c, s));
+            rz = c->st_host->flex_zr;
+            out->replacements += 1;
+            continue;
+        }
+        RETCHK(ssor_apply(c, c->r, z, s));
+        RETCHK(read_state(c, s));
+        const double rz_new = c->st_host->flex_zr;
+        const double beta = rz_new / rz;
+        rz = rz_new;
+        HIPCHK(launch_xpby(n3, z, p, beta, s));
+    }
+    out->iterations = it;
+    if (!out->converged) {
+        HIPCHK(launch_resid_norm(g, b, x, c->sv[5], c->inv_h2, c->st, c->partials, s));
+        RETCHK(read_state(c, s));
+        out->rel_res = c->st_host->out_nr / nb;
+    }
+    return PIC_OK;
+}
+
 // ------------------------------------------------------------------ field --
 
 static int field(pic_ctx* c, double* phi, double* ex, double* ey, double* ez, hipStream_t s) {
@@ -550,6 +699,7 @@ size_t pic_workspace_bytes(const pic_params* p) {
     if (p->np_max > 0) b += sort_scratch_bytes(p->np_max);
     if (p->solver == PIC_SOLVER_PCG_MIXED) b += mixed_bytes(p);
     if (p->solver == PIC_SOLVER_FCG_LEARNED) b += learned_bytes(p);
+    if (p->solver == PIC_SOLVER_PCG_SSOR) b += ssor_bytes(p);
     return b;
 }
 
@@ -566,6 +716,9 @@ int pic_create(const pic_params* params, pic_ctx** out) {
     if (c->p.max_inner <= 0) c->p.max_inner = 20000;
     if (!(c->p.inner_rtol > 0.0)) c->p.inner_rtol = 1e-3;
     if (c->p.fcg_window <= 0) c->p.fcg_window = 10;
+    if (c->p.ssor_omega == 0.0) c->p.ssor_omega = 1.5707963267948966;  // pi / 2
+    if (c->p.ssor_inner == 0) c->p.ssor_inner = 4;
+    if (c->p.ssor_outer == 0) c->p.ssor_outer = 2;
     const int n = c->p.n;
     c->n3 = (int64_t)n * n * n;
     c->geo = make_geo(n);
@@ -618,6 +771,7 @@ int pic_create(const pic_params* params, pic_ctx** out) {
         }
         if (c->p.solver == PIC_SOLVER_PCG_MIXED && (rc = ensure_mixed(c)) != PIC_OK) break;
         if (c->p.solver == PIC_SOLVER_FCG_LEARNED && (rc = ensure_learned(c)) != PIC_OK) break;
+        if (c->p.solver == PIC_SOLVER_PCG_SSOR && (rc = ensure_ssor(c)) != PIC_OK) break;
     } while (0);
     if (rc != PIC_OK) {
         std::string keep = g_err;
@@ -642,8 +796,9 @@ int pic_destroy(pic_ctx* c) {
 
 int pic_set_solver(pic_ctx* c, int32_t solver) {
     if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
-    if (solver < PIC_SOLVER_PCG_FP64 || solver > PIC_SOLVER_FCG_LEARNED)
+    if (solver < PIC_SOLVER_PCG_FP64 || solver > PIC_SOLVER_PCG_SSOR)
         return fail(PIC_ERR_INVALID, "unknown solver %d", solver);
+    if (solver == PIC_SOLVER_PCG_SSOR) RETCHK(ensure_ssor(c));
     if (solver == PIC_SOLVER_PCG_MIXED) RETCHK(ensure_mixed(c));
     if (solver == PIC_SOLVER_FCG_LEARNED) RETCHK(ensure_learned(c));
     c->p.solver = solver;
@@ -758,6 +913,7 @@ int pic_poisson_pcg(pic_ctx* c, const double* rho, double* phi, double* ex, doub
     switch (c->p.solver) {
         case PIC_SOLVER_PCG_FP64: RETCHK(solve_fp64(c, rho, phi, &si, s)); break;
         case PIC_SOLVER_PCG_MIXED: RETCHK(solve_mixed(c, rho, phi, &si, s)); break;
+        case PIC_SOLVER_PCG_SSOR: RETCHK(solve_ssor(c, rho, phi, &si, s)); break;
         default: RETCHK(solve_learned(c, rho, phi, &si, s)); break;
     }
     if (want_e) {
@@ -904,6 +1060,7 @@ int pic_step(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, v
     switch (c->p.solver) {
         case PIC_SOLVER_PCG_FP64: rc = solve_fp64(c, F->rho, F->phi, &si, s); break;
         case PIC_SOLVER_PCG_MIXED: rc = solve_mixed(c, F->rho, F->phi, &si, s); break;
+        case PIC_SOLVER_PCG_SSOR: rc = solve_ssor(c, F->rho, F->phi, &si, s); break;
         default: rc = solve_learned(c, F->rho, F->phi, &si, s);
     }
     if (rc < 0) return rc;

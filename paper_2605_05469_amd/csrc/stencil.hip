@@ -462,6 +462,56 @@ struct OpAq {
     __device__ double* partials() const { return part; }
 };
 
+// SSOR preconditioner, one half-sweep (a Jacobi step of an approximate
+// triangular solve, Sec. 4.1's SSOR on the periodic grid):
+//   out = oscale * (bscale * base + c * ((s_x + s_y) + s_z)) (+ add)
+// with s the staged array's backward (dir 0: x-1, y-1, z-1) or forward
+// (dir 1: x+1, y+1, z+1) neighbours, staged values scaled by sscale.
+// Optionally reduces r . out into st->flex_zr (the preconditioned dot of
+// PCG).  Summation order as in the oracle.
+struct OpSsorHalf {
+    using T = double;
+    using In = double;
+    struct Own {
+        double base, add, r;
+    };
+    static constexpr int NACC = 1;
+    const double* src;
+    const double* base;
+    const double* add;   // nullable
+    const double* rdot;  // nullable: reduce rdot . out
+    double* dst;
+    double c, bscale, sscale, oscale;
+    int dir;
+    DevState* st;
+    double* part;
+    __device__ bool active() const { return true; }
+    __device__ void prepare() {}
+    __device__ double fetch(size_t g) const { return src[g]; }
+    __device__ double make(double v, size_t, bool) const { return sscale == 1.0 ? v : sscale * v; }
+    __device__ Own pre(size_t g) const {
+        Own o;
+        o.base = ld_own(base + g);
+        o.add = add ? ld_own(add + g) : 0.0;
+        o.r = rdot ? ld_own(rdot + g) : 0.0;
+        return o;
+    }
+    __device__ void out(const Own& o, size_t g, double, double xm, double xp, double ym, double yp,
+                        double zm, double zp, double (&acc)[1]) const {
+        const double sn = dir == 0 ? (xm + ym) + zm : (xp + yp) + zp;
+        double v = (bscale == 1.0 ? o.base : bscale * o.base) + c * sn;
+        if (oscale != 1.0) v = oscale * v;
+        if (add) v = v + o.add;
+        st_own(v, dst + g);
+        acc[0] += o.r * v;
+    }
+    __device__ void finish(double (&t)[1]) const {
+        if (rdot) st->flex_zr = t[0];
+    }
+    __device__ uint32_t* ticket() const { return &st->tickets[4]; }
+    __device__ double* partials() const { return part; }
+};
+
 // Field: E = -grad (phi - mean) from the gauge-fixed values, W_x =
 // (1/2) h^3 sum Ex^2.  phi itself is shifted by a separate pass afterwards.
 struct OpField {
@@ -810,6 +860,13 @@ __global__ __launch_bounds__(kNT) void copy_kernel(int64_t n3, const double* __r
 hipError_t launch_aq(const SweepGeo& g, const double* p, double* q, double inv_h2, DevState* st,
                      double* partials, hipStream_t s) {
     OpAq op{p, q, inv_h2, st, partials};
+    return launch_sweep(op, g, s);
+}
+hipError_t launch_ssor_half(const SweepGeo& g, const double* src, const double* base,
+                            const double* add, const double* rdot, double* dst, double c,
+                            double bscale, double sscale, double oscale, int dir, DevState* st,
+                            double* partials, hipStream_t s) {
+    OpSsorHalf op{src, base, add, rdot, dst, c, bscale, sscale, oscale, dir, st, partials};
     return launch_sweep(op, g, s);
 }
 hipError_t launch_fcg_update(int64_t n3, double* x, double* r, const double* p, const double* q,

@@ -313,6 +313,24 @@ def test_mixed_reliable_matches_oracle(pic, orc, N, inner_rtol):
     assert info["iterations"] <= 1.3 * pinfo["iters"]
 
 
+@pytest.mark.parametrize("N,inner,outer", [(32, 4, 2), (64, 4, 2), (64, 2, 1)])
+def test_pcg_ssor_matches_oracle(pic, orc, N, inner, outer):
+    """The paper's SSOR preconditioner (Sec. 4.1) inside FP64 PCG: same
+    iteration count as the oracle (dot-product order only), true residual."""
+    ctx, p = _ctx(pic, N, 8, np_max=0, solver="pcg_ssor", ssor_inner=inner, ssor_outer=outer)
+    b = _rhs(orc, N, 8, 6500 + N)
+    dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.poisson(_dev(b), dx)
+    ref, rinfo = orc.pcg_ssor(N, p.length, b, np.zeros(N ** 3), p.rtol, p.max_iter,
+                              math.pi / 2, inner, outer)
+    assert info["converged"] and rinfo["converged"]
+    assert abs(info["iterations"] - rinfo["iters"]) <= 1
+    got = _host(dx)
+    assert orc.residual_norm(N, p.length, b, got) <= p.rtol * np.linalg.norm(b)
+    if info["iterations"] == rinfo["iters"]:
+        assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
 # ------------------------------------------------------------ full step ----
 
 def test_step_parity_config0(pic, orc):
