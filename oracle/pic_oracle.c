@@ -271,9 +271,9 @@ void or_pcg(int N, double L, const double *b, double *x, double rtol, int64_t ma
 }
 
 /* ------------------------------------------------------------------------ */
-/* SSOR preconditioner (Sec. 4.1: the PCG runs used SSOR "with four inner and
- * two outer iterations, and a damping factor of pi/2"; the paper does not
- * define inner and outer).  Reading: A = D + L + U with D = (6/h^2) I, L the
+/* SSOR preconditioner (Sec. 4.1: the PCG runs used SSOR with 4 inner and 2
+ * outer iterations and damping pi/2; the paper defines neither count).
+ * Reading: A = D + L + U with D = (6/h^2) I, L the
  * backward neighbours (x-1, y-1, z-1, periodic) and U = L^T the forward ones;
  * one SSOR application is
  *     z = w (2 - w) (D + w U)^{-1} D (D + w L)^{-1} r,     w = damping,
