@@ -33,7 +33,7 @@ PEAK_HBM_GBS = 8000.0
 # direction sweep reads r, p_old and writes p_new; update sweep reads p, x, r
 # and writes x, r.  (FP32 inner sweeps of the mixed form: half.)
 SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 40),
-               "pcg_ssor": (24, 40)}
+               "pcg_ssor": (24, 40), "fft": (24, 40)}
 # HBM bytes per launch of the FP64 update sweep at 512^3, from rocprofv3
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
@@ -175,12 +175,13 @@ def bench_poisson(args):
     torch.cuda.empty_cache()  # the library allocates the network outside torch
     forms = {}
     all_forms = ("pcg_fp64", "pcg_mixed", "pcg_mixed_reliable", "pcg_ssor", "fcg_learned",
-                 "learned_warm_start_only", "learned_warm_start_mixed")
+                 "learned_warm_start_only", "learned_warm_start_mixed", "fft", "fft_spectral")
     for form in (args.forms.split(",") if args.forms else all_forms):
         if form not in all_forms:
             raise SystemExit("unknown form %r (choose from %s)" % (form, ", ".join(all_forms)))
         solver = ("fcg_learned" if form.startswith("learned") else
-                  "pcg_mixed" if form.startswith("pcg_mixed") else form)
+                  "pcg_mixed" if form.startswith("pcg_mixed") else
+                  "fft" if form.startswith("fft") else form)
         if solver == "fcg_learned":
             try:
                 load_weights(ctx, args.weights)
@@ -191,7 +192,8 @@ def bench_poisson(args):
                       | (P.FLAG_WARM_START_ONLY if form.startswith("learned_") else 0)
                       | (P.FLAG_MIXED_RELIABLE if form in ("pcg_mixed_reliable",
                                                            "learned_warm_start_mixed") else 0)
-                      | (P.FLAG_LEARNED_MIXED if form == "learned_warm_start_mixed" else 0))
+                      | (P.FLAG_LEARNED_MIXED if form == "learned_warm_start_mixed" else 0)
+                      | (P.FLAG_FFT_SPECTRAL if form == "fft_spectral" else 0))
         ctx.set_solver(solver)
         phi = torch.zeros_like(rho)
         torch.cuda.synchronize()
@@ -209,6 +211,8 @@ def bench_poisson(args):
     name = args.solver
     if name == "pcg_mixed" and args.mixed_reliable:
         name = "pcg_mixed_reliable"
+    if name == "fft" and args.fft_spectral:
+        name = "fft_spectral"
     if name == "fcg_learned" and args.warm_start_only:
         name = "learned_warm_start_mixed" if args.learned_mixed else "learned_warm_start_only"
     sel = forms.get(name, {})
@@ -311,6 +315,8 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true")
     ap.add_argument("--forms", default=None,
                     help="poisson workload: comma-separated solver forms to time (default: all)")
+    ap.add_argument("--fft-spectral", action="store_true",
+                    help="fft solver: pseudo-spectral symbol and E = -i k phi")
     ap.add_argument("--learned-mixed", action="store_true",
                     help="learned form: hand over to the mixed form (not FP64 PCG)")
     ap.add_argument("--mixed-reliable", action="store_true",
@@ -350,6 +356,8 @@ def main():
         p.flags |= P.FLAG_MIXED_RELIABLE
     if args.learned_mixed:
         p.flags |= P.FLAG_LEARNED_MIXED
+    if args.fft_spectral:
+        p.flags |= P.FLAG_FFT_SPECTRAL
     ctx = P.Context(p)
     if args.solver == "fcg_learned":
         load_weights(ctx, args.weights)

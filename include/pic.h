@@ -52,8 +52,12 @@ enum {
     PIC_SOLVER_PCG_FP64 = 0,   /* Jacobi-PCG in FP64 (Sec. 3.2)                */
     PIC_SOLVER_PCG_MIXED = 1,  /* FP32 inner PCG inside FP64 refinement        */
     PIC_SOLVER_FCG_LEARNED = 2, /* flexible PCG, U-Net warm start/precond.     */
-    PIC_SOLVER_PCG_SSOR = 3     /* FP64 PCG with the SSOR preconditioner of the
+    PIC_SOLVER_PCG_SSOR = 3,    /* FP64 PCG with the SSOR preconditioner of the
                                    paper's runs (Sec. 4.1), see ssor_* below  */
+    PIC_SOLVER_FFT = 4          /* FFT solve (the paper's comparison solver,
+                                   Sec. 3.1): the 7-point operator's
+                                   eigenvalues, or with PIC_FLAG_FFT_SPECTRAL
+                                   the pseudo-spectral 1/|k|^2 and E = -ik phi */
 };
 
 /* Problem statement (Sec. 2 and 2.1; tolerance as in Sec. 4). */
@@ -67,6 +71,10 @@ enum {
 #define PIC_FLAG_LEARNED_MIXED 8   /* learned form: the solve after the warm start
                                       (PIC_FLAG_WARM_START_ONLY) or after a
                                       fallback is the mixed form, not FP64 PCG */
+#define PIC_FLAG_FFT_SPECTRAL 16   /* FFT form: pseudo-spectral symbol |k|^2 and
+                                      E = -i k phi_hat (three more inverse
+                                      transforms) instead of the 7-point
+                                      eigenvalues and central differences */
 
 typedef struct pic_params {
     int32_t n;            /* grid points per axis N                         */

@@ -17,11 +17,12 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_NOT_CONVERGED = 0, 1
 PIC_ERR_INVALID, PIC_ERR_HIP, PIC_ERR_NOMEM, PIC_ERR_STATE = -1, -2, -3, -4
-SOLVERS = {"pcg_fp64": 0, "pcg_mixed": 1, "fcg_learned": 2, "pcg_ssor": 3}
+SOLVERS = {"pcg_fp64": 0, "pcg_mixed": 1, "fcg_learned": 2, "pcg_ssor": 3, "fft": 4}
 FLAG_NO_WARM_START = 1
 FLAG_WARM_START_ONLY = 2
 FLAG_MIXED_RELIABLE = 4
 FLAG_LEARNED_MIXED = 8
+FLAG_FFT_SPECTRAL = 16
 
 
 class PicError(RuntimeError):

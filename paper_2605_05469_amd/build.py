@@ -12,8 +12,9 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic.so")
 
-SOURCES = ["stencil.hip", "particles.hip", "sort.hip", "net_kernels.hip", "net.hip", "capi.hip",
-           "capi_net.hip"]
+SOURCES = ["stencil.hip", "particles.hip", "sort.hip", "net_kernels.hip", "net.hip", "fft.hip",
+           "capi.hip", "capi_net.hip"]
+ROCM_LIB = "/opt/rocm/lib"
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
@@ -51,7 +52,9 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    # rocFFT for the FFT solver's transforms
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-L" + ROCM_LIB,
+           "-lrocfft"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

@@ -16,6 +16,7 @@
 #include "../../include/pic.h"
 #include "net.hpp"
 #include "particles.hpp"
+#include "fft.hpp"
 #include "solver_state.hpp"
 
 using namespace pic;
@@ -75,6 +76,8 @@ struct pic_ctx {
     double* fq = nullptr;          //              q = A p
     double* fw = nullptr;          //              warm-start trial / true residual
     double* sv[6] = {};            // SSOR form: z, q, two forward, one backward, r - A z
+    FftPlans* fft = nullptr;       // FFT form: rocFFT plans
+    double2* fspec[2] = {};        //           half spectra (phi_hat, a derivative)
     std::vector<void*> allocs;
     // kernel timing
     bool timing = false;
@@ -88,7 +91,8 @@ struct pic_ctx {
 static bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 
 constexpr int32_t kKnownFlags = PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY |
-                                 PIC_FLAG_MIXED_RELIABLE | PIC_FLAG_LEARNED_MIXED;
+                                 PIC_FLAG_MIXED_RELIABLE | PIC_FLAG_LEARNED_MIXED |
+                                 PIC_FLAG_FFT_SPECTRAL;
 
 static int validate_params(const pic_params* p) {
     if (!p) return fail(PIC_ERR_INVALID, "params is NULL");
@@ -100,7 +104,7 @@ static int validate_params(const pic_params* p) {
         return fail(PIC_ERR_INVALID, "np_max must be in [0, 2^32)");
     if (!(p->rtol > 0.0) || !std::isfinite(p->rtol)) return fail(PIC_ERR_INVALID, "rtol must be > 0");
     if (p->max_iter < 0) return fail(PIC_ERR_INVALID, "max_iter must be >= 0");
-    if (p->solver < PIC_SOLVER_PCG_FP64 || p->solver > PIC_SOLVER_PCG_SSOR)
+    if (p->solver < PIC_SOLVER_PCG_FP64 || p->solver > PIC_SOLVER_FFT)
         return fail(PIC_ERR_INVALID, "unknown solver %d", p->solver);
     if (!(p->ssor_omega >= 0.0 && p->ssor_omega < 2.0) || p->ssor_inner < 0 || p->ssor_outer < 0)
         return fail(PIC_ERR_INVALID, "ssor_omega must be in (0, 2) (0: default), "
@@ -182,6 +186,26 @@ static int ensure_ssor(pic_ctx* c) {
     RETCHK(dev_alloc(c, &m, ssor_bytes(&c->p)));
     const size_t vb = vec_bytes(c->n3, 8);
     for (int i = 0; i < 6; ++i) c->sv[i] = (double*)((char*)m + i * vb);
+    return PIC_OK;
+}
+
+// FFT form: two half spectra (the transforms' own work buffer is rocFFT's).
+static size_t fft_bytes(const pic_params* p) {
+    const int64_t nspec = (int64_t)(p->n / 2 + 1) * p->n * p->n;
+    return 2 * vec_bytes(nspec, 16);
+}
+
+static int ensure_fft(pic_ctx* c) {
+    if (c->fft) return PIC_OK;
+    void* m = nullptr;
+    RETCHK(dev_alloc(c, &m, fft_bytes(&c->p)));
+    const int64_t nspec = (int64_t)(c->p.n / 2 + 1) * c->p.n * c->p.n;
+    c->fspec[0] = (double2*)m;
+    c->fspec[1] = (double2*)((char*)m + vec_bytes(nspec, 16));
+    if (fft_create(&c->fft, c->p.n)) {
+        c->fft = nullptr;
+        return fail(PIC_ERR_HIP, "FFT plans: %s", fft_last_error());
+    }
     return PIC_OK;
 }
 
@@ -677,6 +701,57 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
     return PIC_OK;
 }
 
+// -------------------------------------------------------------- FFT form --
+// phi = IFFT(FFT(b) / symbol) with the zero mode removed; with
+// PIC_FLAG_FFT_SPECTRAL and E requested, E_d = IFFT(-i k_d phi_hat) as well
+// (then *e_done is set).  The residual reported is the 7-point operator's
+// (round-off for the discrete symbol; the O(h^2) operator difference for the
+// spectral one).
+static bool fft_spectral(const pic_ctx* c) {
+    return (c->p.flags & PIC_FLAG_FFT_SPECTRAL) != 0;
+}
+
+static int solve_fft(pic_ctx* c, const double* b, double* x, pic_solve_info* out, hipStream_t s,
+                     double* ex, double* ey, double* ez, bool* e_done) {
+    RETCHK(ensure_fft(c));
+    const int n = c->p.n;
+    const int64_t nspec = (int64_t)(n / 2 + 1) * n * n;
+    const bool spec = fft_spectral(c);
+    const double kf = 2.0 * M_PI / c->L;
+    *e_done = false;
+    // rocFFT may overwrite a transform's input: b goes through scratch
+    HIPCHK(launch_copy(c->n3, b, c->r, s));
+    if (fft_forward(c->fft, c->r, c->fspec[0], s)) return fail(PIC_ERR_HIP, "%s", fft_last_error());
+    HIPCHK(launch_fft_divide(nspec, n, c->inv_h2, kf, spec ? 1 : 0, 1.0 / (double)c->n3,
+                             c->fspec[0], s));
+    if (spec && ex && ey && ez) {
+        double* E[3] = {ex, ey, ez};
+        for (int d = 0; d < 3; ++d) {
+            HIPCHK(launch_fft_grad(nspec, n, kf, d, c->fspec[0], c->fspec[1], s));
+            if (fft_inverse(c->fft, c->fspec[1], E[d], s))
+                return fail(PIC_ERR_HIP, "%s", fft_last_error());
+        }
+        *e_done = true;
+    }
+    if (fft_inverse(c->fft, c->fspec[0], x, s)) return fail(PIC_ERR_HIP, "%s", fft_last_error());
+    HIPCHK(launch_resid_norm(c->geo, b, x, c->r, c->inv_h2, c->st, c->partials, s));
+    HIPCHK(launch_sum(c->n3, b, c->st, c->partials, 1, s));
+    RETCHK(read_state(c, s));
+    const double nb = std::sqrt(c->st_host->bb);
+    out->norm_b = nb;
+    out->rel_res = nb > 0 ? c->st_host->out_nr / nb : 0.0;
+    out->converged = 1;
+    return PIC_OK;
+}
+
+// W_x of a spectral field (the field sweep computes it otherwise).
+static int spectral_wx(pic_ctx* c, const double* ex, hipStream_t s, double* wx) {
+    HIPCHK(launch_sum(c->n3, ex, c->st, c->partials, 1, s));
+    RETCHK(read_state(c, s));
+    *wx = 0.5 * c->h3 * c->st_host->bb;
+    return PIC_OK;
+}
+
 // ------------------------------------------------------------------ field --
 
 static int field(pic_ctx* c, double* phi, double* ex, double* ey, double* ez, hipStream_t s) {
@@ -700,6 +775,7 @@ size_t pic_workspace_bytes(const pic_params* p) {
     if (p->solver == PIC_SOLVER_PCG_MIXED) b += mixed_bytes(p);
     if (p->solver == PIC_SOLVER_FCG_LEARNED) b += learned_bytes(p);
     if (p->solver == PIC_SOLVER_PCG_SSOR) b += ssor_bytes(p);
+    if (p->solver == PIC_SOLVER_FFT) b += fft_bytes(p);
     return b;
 }
 
@@ -772,6 +848,7 @@ int pic_create(const pic_params* params, pic_ctx** out) {
         if (c->p.solver == PIC_SOLVER_PCG_MIXED && (rc = ensure_mixed(c)) != PIC_OK) break;
         if (c->p.solver == PIC_SOLVER_FCG_LEARNED && (rc = ensure_learned(c)) != PIC_OK) break;
         if (c->p.solver == PIC_SOLVER_PCG_SSOR && (rc = ensure_ssor(c)) != PIC_OK) break;
+        if (c->p.solver == PIC_SOLVER_FFT && (rc = ensure_fft(c)) != PIC_OK) break;
     } while (0);
     if (rc != PIC_OK) {
         std::string keep = g_err;
@@ -790,15 +867,17 @@ int pic_destroy(pic_ctx* c) {
     if (c->st_host) (void)hipHostFree(c->st_host);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->net) net::destroy(c->net);
+    if (c->fft) fft_destroy(c->fft);
     delete c;
     return PIC_OK;
 }
 
 int pic_set_solver(pic_ctx* c, int32_t solver) {
     if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
-    if (solver < PIC_SOLVER_PCG_FP64 || solver > PIC_SOLVER_PCG_SSOR)
+    if (solver < PIC_SOLVER_PCG_FP64 || solver > PIC_SOLVER_FFT)
         return fail(PIC_ERR_INVALID, "unknown solver %d", solver);
     if (solver == PIC_SOLVER_PCG_SSOR) RETCHK(ensure_ssor(c));
+    if (solver == PIC_SOLVER_FFT) RETCHK(ensure_fft(c));
     if (solver == PIC_SOLVER_PCG_MIXED) RETCHK(ensure_mixed(c));
     if (solver == PIC_SOLVER_FCG_LEARNED) RETCHK(ensure_learned(c));
     c->p.solver = solver;
@@ -910,13 +989,19 @@ int pic_poisson_pcg(pic_ctx* c, const double* rho, double* phi, double* ex, doub
     pic_solve_info si;
     std::memset(&si, 0, sizeof si);
     if (c->timing) timing_reset(c);
+    bool e_done = false;
     switch (c->p.solver) {
         case PIC_SOLVER_PCG_FP64: RETCHK(solve_fp64(c, rho, phi, &si, s)); break;
         case PIC_SOLVER_PCG_MIXED: RETCHK(solve_mixed(c, rho, phi, &si, s)); break;
         case PIC_SOLVER_PCG_SSOR: RETCHK(solve_ssor(c, rho, phi, &si, s)); break;
+        case PIC_SOLVER_FFT:
+            RETCHK(solve_fft(c, rho, phi, &si, s, want_e ? ex : nullptr, ey, ez, &e_done));
+            break;
         default: RETCHK(solve_learned(c, rho, phi, &si, s)); break;
     }
-    if (want_e) {
+    if (want_e && e_done) {
+        RETCHK(spectral_wx(c, ex, s, &si.wx));
+    } else if (want_e) {
         RETCHK(field(c, phi, ex, ey, ez, s));
         RETCHK(read_state(c, s));
         si.wx = c->st_host->wx;
@@ -1057,19 +1142,25 @@ int pic_step(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, v
     pic_solve_info si;
     std::memset(&si, 0, sizeof si);
     int rc;
+    bool e_done = false;
     switch (c->p.solver) {
         case PIC_SOLVER_PCG_FP64: rc = solve_fp64(c, F->rho, F->phi, &si, s); break;
         case PIC_SOLVER_PCG_MIXED: rc = solve_mixed(c, F->rho, F->phi, &si, s); break;
         case PIC_SOLVER_PCG_SSOR: rc = solve_ssor(c, F->rho, F->phi, &si, s); break;
+        case PIC_SOLVER_FFT:
+            rc = solve_fft(c, F->rho, F->phi, &si, s, F->ex, F->ey, F->ez, &e_done);
+            break;
         default: rc = solve_learned(c, F->rho, F->phi, &si, s);
     }
     if (rc < 0) return rc;
     RETCHK(T.mark(4, s));
-    RETCHK(field(c, F->phi, F->ex, F->ey, F->ez, s));
+    double wx_spec = 0.0;
+    if (e_done) RETCHK(spectral_wx(c, F->ex, s, &wx_spec));
+    else RETCHK(field(c, F->phi, F->ex, F->ey, F->ez, s));
     RETCHK(T.mark(5, s));
     if (info) {
         RETCHK(read_state(c, s));
-        si.wx = c->st_host->wx;
+        si.wx = e_done ? wx_spec : c->st_host->wx;
         info->solve = si;
         info->ms_push = T.ms(0, 1);
         info->ms_sort = T.ms(1, 2);

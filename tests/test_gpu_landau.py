@@ -1,7 +1,7 @@
 """End-to-end physics on the GPU: Landau damping (Sec. 2.1; the E_x energy of
 the perturbed mode decays at the rate of the Vlasov-Poisson dispersion
 relation, as in the paper's correctness figure) through pic_init / pic_step,
-for each solver form."""
+for the FP64 and mixed PCG forms and the pseudo-spectral FFT solve."""
 import numpy as np
 import pytest
 
@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("solver,flags", [("pcg_fp64", 0), ("pcg_mixed", 4)])
+@pytest.mark.parametrize("solver,flags", [("pcg_fp64", 0), ("pcg_mixed", 4), ("fft", 16)])
 def test_gpu_landau_damping_rate(solver, flags):
     import paper_2605_05469_amd as P
     N, ppc, steps = 32, 64, 300
