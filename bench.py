@@ -174,13 +174,15 @@ def bench_poisson(args):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()  # the library allocates the network outside torch
     forms = {}
-    all_forms = ("pcg_fp64", "pcg_mixed", "pcg_mixed_reliable", "pcg_ssor", "fcg_learned",
+    all_forms = ("pcg_fp64", "pcg_mixed", "pcg_mixed_reliable", "pcg_ssor", "pcg_ssor_unfused",
+                 "fcg_learned",
                  "learned_warm_start_only", "learned_warm_start_mixed", "fft", "fft_spectral")
     for form in (args.forms.split(",") if args.forms else all_forms):
         if form not in all_forms:
             raise SystemExit("unknown form %r (choose from %s)" % (form, ", ".join(all_forms)))
         solver = ("fcg_learned" if form.startswith("learned") else
                   "pcg_mixed" if form.startswith("pcg_mixed") else
+                  "pcg_ssor" if form.startswith("pcg_ssor") else
                   "fft" if form.startswith("fft") else form)
         if solver == "fcg_learned":
             try:
@@ -193,7 +195,8 @@ def bench_poisson(args):
                       | (P.FLAG_MIXED_RELIABLE if form in ("pcg_mixed_reliable",
                                                            "learned_warm_start_mixed") else 0)
                       | (P.FLAG_LEARNED_MIXED if form == "learned_warm_start_mixed" else 0)
-                      | (P.FLAG_FFT_SPECTRAL if form == "fft_spectral" else 0))
+                      | (P.FLAG_FFT_SPECTRAL if form == "fft_spectral" else 0)
+                      | (P.FLAG_SSOR_UNFUSED if form == "pcg_ssor_unfused" else 0))
         ctx.set_solver(solver)
         phi = torch.zeros_like(rho)
         torch.cuda.synchronize()

@@ -75,6 +75,10 @@ enum {
                                       E = -i k phi_hat (three more inverse
                                       transforms) instead of the 7-point
                                       eigenvalues and central differences */
+#define PIC_FLAG_SSOR_UNFUSED 32   /* SSOR form: run every inner Jacobi step as a
+                                      sweep of its own instead of one fused
+                                      z-march per triangular solve (same
+                                      arithmetic; for comparison) */
 
 typedef struct pic_params {
     int32_t n;            /* grid points per axis N                         */

@@ -23,6 +23,7 @@ FLAG_WARM_START_ONLY = 2
 FLAG_MIXED_RELIABLE = 4
 FLAG_LEARNED_MIXED = 8
 FLAG_FFT_SPECTRAL = 16
+FLAG_SSOR_UNFUSED = 32
 
 
 class PicError(RuntimeError):
@@ -177,7 +178,7 @@ def _stream(stream=None):
 def landau_params(N, ppc, k=0.5, dt=0.05, qm=-1.0, rtol=1e-10, max_iter=20000,
                   solver="pcg_fp64", np_max=None, check_every=16, inner_rtol=1e-3,
                   max_inner=20000, max_outer=50, fcg_window=10, ssor_omega=math.pi / 2,
-                  ssor_inner=4, ssor_outer=2):
+                  ssor_inner=4, ssor_outer=2, flags=0):
     """Parameters of the Landau-damping box (Sec. 2.1): L = 2 pi / k, unit
     mean density, q = -L^3/Np, background +1."""
     L = 2.0 * math.pi / k
@@ -194,6 +195,7 @@ def landau_params(N, ppc, k=0.5, dt=0.05, qm=-1.0, rtol=1e-10, max_iter=20000,
     p.inner_rtol, p.max_inner, p.max_outer = inner_rtol, max_inner, max_outer
     p.fcg_window = fcg_window
     p.ssor_omega, p.ssor_inner, p.ssor_outer = ssor_omega, ssor_inner, ssor_outer
+    p.flags = flags
     return p
 
 
@@ -224,7 +226,8 @@ class Context:
 
     def set_flags(self, flags: int):
         """FLAG_NO_WARM_START | FLAG_WARM_START_ONLY (learned form),
-        FLAG_MIXED_RELIABLE (mixed form), FLAG_LEARNED_MIXED (learned form)."""
+        FLAG_MIXED_RELIABLE (mixed form), FLAG_LEARNED_MIXED (learned form),
+        FLAG_FFT_SPECTRAL (FFT form), FLAG_SSOR_UNFUSED (SSOR form)."""
         _check(lib().pic_set_flags(self._h, int(flags)))
 
     def cell_keys(self, x, y, z, key, stream=None):

@@ -92,7 +92,7 @@ static bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 
 constexpr int32_t kKnownFlags = PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY |
                                  PIC_FLAG_MIXED_RELIABLE | PIC_FLAG_LEARNED_MIXED |
-                                 PIC_FLAG_FFT_SPECTRAL;
+                                 PIC_FLAG_FFT_SPECTRAL | PIC_FLAG_SSOR_UNFUSED;
 
 static int validate_params(const pic_params* p) {
     if (!p) return fail(PIC_ERR_INVALID, "params is NULL");
@@ -578,7 +578,9 @@ static int solve_learned(pic_ctx* c, const double* b, double* x, pic_solve_info*
 //   z = w (2 - w) z_inner,
 // j < inner (Jacobi steps for the cyclic triangular solves), each step one
 // z-marching half-stencil sweep; `outer` stationary steps add SSOR(r - A z).
-// The last sweep of the application reduces r . z for PCG.
+// The last sweep of the application reduces r . z for PCG.  By default each
+// triangular solve (all its inner steps) is one fused z-march; with
+// PIC_FLAG_SSOR_UNFUSED every step is a sweep of its own (same values of z).
 // Buffers: sv[2], sv[3] forward ping-pong, sv[4] backward, sv[5] = r - A z.
 static int ssor_once(pic_ctx* c, const double* rhs, double* out, const double* add,
                      const double* rdot, hipStream_t s) {
@@ -586,6 +588,13 @@ static int ssor_once(pic_ctx* c, const double* rhs, double* out, const double* a
     const int k = c->p.ssor_inner;
     const double w = c->p.ssor_omega;
     const double cc = w / 6.0, dinv = c->minv, sc = w * (2.0 - w);
+    if (!(c->p.flags & PIC_FLAG_SSOR_UNFUSED) && ssor_fused_supported(c->p.n, k)) {
+        HIPCHK(launch_ssor_fused(c->p.n, k, 0, rhs, nullptr, nullptr, c->sv[2], dinv, cc, 1.0,
+                                 c->st, c->partials, s));
+        HIPCHK(launch_ssor_fused(c->p.n, k, 1, c->sv[2], add, rdot, out, 1.0, cc, sc, c->st,
+                                 c->partials, s));
+        return PIC_OK;
+    }
     double* ya = c->sv[2];
     double* yb = c->sv[3];
     const double* stage = rhs;

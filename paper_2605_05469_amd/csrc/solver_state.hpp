@@ -96,6 +96,10 @@ hipError_t launch_resid_norm(const SweepGeo& g, const double* b, const double* x
 // Flexible CG pieces (learned preconditioner): q = A p with p.q -> flex_pq;
 // x += a p, r -= a q with r.r -> flex_rr; z.r, z.q -> flex_zr, flex_zq;
 // p = z + b p; w = x + z; dst = src.
+bool ssor_fused_supported(int n, int inner);
+hipError_t launch_ssor_fused(int n, int inner, int dir, const double* src, const double* add,
+                             const double* rdot, double* dst, double s0, double c, double oscale,
+                             DevState* st, double* partials, hipStream_t s);
 hipError_t launch_ssor_half(const SweepGeo& g, const double* src, const double* base,
                             const double* add, const double* rdot, double* dst, double c,
                             double bscale, double sscale, double oscale, int dir, DevState* st,

@@ -512,6 +512,124 @@ struct OpSsorHalf {
     __device__ double* partials() const { return part; }
 };
 
+// SSOR, one whole approximate triangular solve in one z-march (temporal
+// blocking of its K Jacobi steps).  Forward (DIR 0, backward neighbours):
+//   y_0 = s0 * src,  y_l = y_0 + c ((y_{l-1}[x-1] + y_{l-1}[y-1]) + y_{l-1}[z-1]),
+// backward (DIR 1) the same with forward neighbours and s0 = 1; the output is
+// oscale * y_K (+ add), optionally reducing rdot . out into st->flex_zr.
+// Level l at plane z needs level l-1 at planes z and z-1 at the neighbours on
+// one side, so each level is computed on the TX x TY tile widened by K - l
+// points on that side, and each level keeps its previous plane in LDS: the
+// block marches its z range (upward for DIR 0, downward for DIR 1) starting K
+// planes early, after which every level is valid.  The arithmetic and its
+// order are those of K separate half-sweeps (identical results); the bytes
+// moved are one read of src (with a K-point halo) and one write per point.
+// LDS doubles before level l (two planes per level, level j covering
+// (TX + K - j) x (TY + K - j) points).
+constexpr int ssor_level_off(int K, int TX, int TY, int l) {
+    int o = 0;
+    for (int j = 0; j < l; ++j) o += 2 * (TX + K - j) * (TY + K - j);
+    return o;
+}
+
+template <int K, int DIR, int TX, int TY>
+__global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int nbx, int nby, int zlen,
+                                                         const double* __restrict__ src,
+                                                         const double* add,  // may be dst
+                                                         const double* __restrict__ rdot,
+                                                         double* dst, double s0,
+                                                         double c, double oscale, DevState* st,
+                                                         double* part) {
+    constexpr int W0 = TX + K, H0 = TY + K;
+    constexpr int NLDS = ssor_level_off(K, TX, TY, K);
+    __shared__ double lds[NLDS];
+    __shared__ double red[kNT / kWave];
+    __shared__ int lflag;
+    const int tid = threadIdx.x;
+    const uint32_t lb = remap_xcd(blockIdx.x, gridDim.x);
+    const int bx = (int)(lb % nbx), by = (int)((lb / nbx) % nby), bz = (int)(lb / (nbx * nby));
+    const int x0 = bx * TX, y0 = by * TY;
+    const int z0 = bz * zlen, z1 = z0 + zlen;
+    const size_t nn = (size_t)n * n;
+    // level 0 region origin: widened towards -x, -y (DIR 0) or +x, +y (DIR 1)
+    const int ax = DIR == 0 ? x0 - K : x0, ay = DIR == 0 ? y0 - K : y0;
+    for (int i = tid; i < NLDS; i += kNT) lds[i] = 0.0;
+    double acc[1] = {0.0};
+    constexpr int NP0 = (W0 * H0 + kNT - 1) / kNT;
+    double stg[NP0];
+    const int nsteps = zlen + K;
+    int cur = 0;
+    __syncthreads();
+    for (int t = 0; t <= nsteps; ++t) {
+        // prefetch level 0 of step t (plane sequence: DIR 0 upward from
+        // z0 - K, DIR 1 downward from z1 - 1 + K), then finish step t - 1
+        if (t < nsteps) {
+            int zf = DIR == 0 ? z0 - K + t : z1 - 1 + K - t;
+            zf = zf < 0 ? zf + n : (zf >= n ? zf - n : zf);
+            const size_t zo = (size_t)zf * nn;
+#pragma unroll
+            for (int k = 0; k < NP0; ++k) {
+                const int e = tid + k * kNT;
+                if (e < W0 * H0) {
+                    int gx = ax + e % W0, gy = ay + e / W0;
+                    gx = gx < 0 ? gx + n : (gx >= n ? gx - n : gx);
+                    gy = gy < 0 ? gy + n : (gy >= n ? gy - n : gy);
+                    stg[k] = src[zo + (size_t)gy * n + gx];
+                }
+            }
+        }
+        if (t > 0) {
+            const int tp = t - 1;
+            const int z = DIR == 0 ? z0 - K + tp : z1 - 1 + K - tp;
+            const bool out_plane = DIR == 0 ? (z >= z0) : (z < z1);
+            const double* B = lds + cur * W0 * H0;  // level 0, this plane
+            for (int l = 1; l <= K; ++l) {
+                const int Wp = TX + K - l + 1, Hp = TY + K - l + 1;
+                const int Wl = Wp - 1, Hl = Hp - 1;
+                const double* P = lds + ssor_level_off(K, TX, TY, l - 1) + cur * Wp * Hp;
+                const double* Pz = lds + ssor_level_off(K, TX, TY, l - 1) + (cur ^ 1) * Wp * Hp;
+                double* Q = lds + ssor_level_off(K, TX, TY, l) + cur * Wl * Hl;
+                // this level's region inside level l-1's (offset o1) and level 0's (ol)
+                const int o1 = DIR == 0 ? 1 : 0, ol = DIR == 0 ? l : 0;
+                for (int e = tid; e < Wl * Hl; e += kNT) {
+                    const int lx = e % Wl, ly = e / Wl;
+                    const int pi = (ly + o1) * Wp + (lx + o1);
+                    const double sn = DIR == 0 ? (P[pi - 1] + P[pi - Wp]) + Pz[pi]
+                                               : (P[pi + 1] + P[pi + Wp]) + Pz[pi];
+                    const double v = B[(ly + ol) * W0 + (lx + ol)] + c * sn;
+                    if (l < K) {
+                        Q[e] = v;
+                    } else if (out_plane) {
+                        const size_t g = (size_t)z * nn + (size_t)(y0 + ly) * n + (x0 + lx);
+                        double o = oscale == 1.0 ? v : oscale * v;
+                        if (add) o = o + add[g];
+                        dst[g] = o;
+                        if (rdot) acc[0] += rdot[g] * o;
+                    }
+                }
+                __syncthreads();
+            }
+            cur ^= 1;
+        }
+        if (t < nsteps) {
+            double* L0 = lds + cur * W0 * H0;
+#pragma unroll
+            for (int k = 0; k < NP0; ++k) {
+                const int e = tid + k * kNT;
+                if (e < W0 * H0) L0[e] = s0 == 1.0 ? stg[k] : s0 * stg[k];
+            }
+            __syncthreads();
+        }
+    }
+    block_sum<kNT, 1>(acc, red);
+    if (tid == 0) part[lb] = acc[0];
+    if (last_block(&st->tickets[4], gridDim.x, &lflag)) {
+        double tot[1];
+        sum_partials<kNT, 1>(part, (int)gridDim.x, tot, red);
+        if (tid == 0 && rdot) st->flex_zr = tot[0];
+    }
+}
+
 // Field: E = -grad (phi - mean) from the gauge-fixed values, W_x =
 // (1/2) h^3 sum Ex^2.  phi itself is shifted by a separate pass afterwards.
 struct OpField {
@@ -862,6 +980,50 @@ hipError_t launch_aq(const SweepGeo& g, const double* p, double* q, double inv_h
     OpAq op{p, q, inv_h2, st, partials};
     return launch_sweep(op, g, s);
 }
+// Fused SSOR solve launcher: K = inner steps (2..8 instantiated), 64 x 8
+// tiles (32 x 8 when n is not a multiple of 64), z split to about 4096 blocks.
+template <int K, int DIR, int TX>
+static hipError_t ssor_fused_t(int n, const double* src, const double* add, const double* rdot,
+                               double* dst, double s0, double c, double oscale, DevState* st,
+                               double* partials, hipStream_t s) {
+    constexpr int TY = 8;
+    const int nbx = n / TX, nby = n / TY;
+    int nbz = 1;
+    for (int z = 1; z <= n / 16; ++z)
+        if (n % z == 0 && (int64_t)nbx * nby * z <= 4096) nbz = z;
+    const int nb = nbx * nby * nbz;
+    if (nb > kMaxSweepBlocks) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((ssor_fused_kernel<K, DIR, TX, TY>), dim3(nb), dim3(kNT), 0, s, n, nbx, nby,
+                       n / nbz, src, add, rdot, dst, s0, c, oscale, st, partials);
+    return hipGetLastError();
+}
+
+template <int K, int DIR>
+static hipError_t ssor_fused_k(int n, const double* src, const double* add, const double* rdot,
+                               double* dst, double s0, double c, double oscale, DevState* st,
+                               double* partials, hipStream_t s) {
+    if (n % 64 == 0)
+        return ssor_fused_t<K, DIR, 64>(n, src, add, rdot, dst, s0, c, oscale, st, partials, s);
+    return ssor_fused_t<K, DIR, 32>(n, src, add, rdot, dst, s0, c, oscale, st, partials, s);
+}
+
+bool ssor_fused_supported(int n, int inner) { return n % 32 == 0 && inner >= 1 && inner <= 4; }
+
+hipError_t launch_ssor_fused(int n, int inner, int dir, const double* src, const double* add,
+                             const double* rdot, double* dst, double s0, double c, double oscale,
+                             DevState* st, double* partials, hipStream_t s) {
+#define SF(KK)                                                                                   \
+    if (inner == KK)                                                                             \
+        return dir == 0 ? ssor_fused_k<KK, 0>(n, src, add, rdot, dst, s0, c, oscale, st, partials, s) \
+                        : ssor_fused_k<KK, 1>(n, src, add, rdot, dst, s0, c, oscale, st, partials, s)
+    SF(1);
+    SF(2);
+    SF(3);
+    SF(4);
+#undef SF
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_ssor_half(const SweepGeo& g, const double* src, const double* base,
                             const double* add, const double* rdot, double* dst, double c,
                             double bscale, double sscale, double oscale, int dir, DevState* st,

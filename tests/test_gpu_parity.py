@@ -313,11 +313,15 @@ def test_mixed_reliable_matches_oracle(pic, orc, N, inner_rtol):
     assert info["iterations"] <= 1.3 * pinfo["iters"]
 
 
-@pytest.mark.parametrize("N,inner,outer", [(32, 4, 2), (64, 4, 2), (64, 2, 1)])
-def test_pcg_ssor_matches_oracle(pic, orc, N, inner, outer):
+@pytest.mark.parametrize("unfused", [False, True])
+@pytest.mark.parametrize("N,inner,outer", [(32, 4, 2), (64, 4, 2), (64, 2, 1), (96, 3, 2),
+                                           (64, 1, 3)])
+def test_pcg_ssor_matches_oracle(pic, orc, N, inner, outer, unfused):
     """The paper's SSOR preconditioner (Sec. 4.1) inside FP64 PCG: same
-    iteration count as the oracle (dot-product order only), true residual."""
-    ctx, p = _ctx(pic, N, 8, np_max=0, solver="pcg_ssor", ssor_inner=inner, ssor_outer=outer)
+    iteration count as the oracle (dot-product order only), true residual;
+    triangular solves fused into one z-march each, or one sweep per step."""
+    ctx, p = _ctx(pic, N, 8, np_max=0, solver="pcg_ssor", ssor_inner=inner, ssor_outer=outer,
+                  flags=pic.FLAG_SSOR_UNFUSED if unfused else 0)
     b = _rhs(orc, N, 8, 6500 + N)
     dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
     info = ctx.poisson(_dev(b), dx)
@@ -329,6 +333,24 @@ def test_pcg_ssor_matches_oracle(pic, orc, N, inner, outer):
     assert orc.residual_norm(N, p.length, b, got) <= p.rtol * np.linalg.norm(b)
     if info["iterations"] == rinfo["iters"]:
         assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("N", [64, 128])
+def test_ssor_fused_equals_unfused(pic, orc, N):
+    """The fused triangular solves compute the same z as the per-step sweeps
+    (same operations in the same order); only r . z is reduced in another
+    block order, so the two solves agree to rounding of the dot products."""
+    b = _dev(_rhs(orc, N, 8, 6600 + N))
+    res = []
+    for flags in (0, pic.FLAG_SSOR_UNFUSED):
+        ctx, p = _ctx(pic, N, 8, np_max=0, solver="pcg_ssor", flags=flags)
+        dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+        info = ctx.poisson(b, dx)
+        assert info["converged"]
+        res.append((info["iterations"], _host(dx)))
+    assert abs(res[0][0] - res[1][0]) <= 1
+    if res[0][0] == res[1][0]:
+        assert np.linalg.norm(res[0][1] - res[1][1]) <= 1e-11 * np.linalg.norm(res[1][1])
 
 
 # ------------------------------------------------------------ full step ----
