@@ -61,11 +61,17 @@ def lib():
                                  ctypes.c_void_p, _dp]
         L.or_deposit.restype = c_dbl
         L.or_apply_A.argtypes = [c_int, c_dbl, _dp, _dp]
+        L.or_apply_A_bc.argtypes = [c_int, c_dbl, c_int, _dp, _dp]
         L.or_residual_norm.argtypes = [c_int, c_dbl, _dp, _dp]
         L.or_residual_norm.restype = c_dbl
+        L.or_residual_norm_bc.argtypes = [c_int, c_dbl, c_int, _dp, _dp]
+        L.or_residual_norm_bc.restype = c_dbl
         L.or_pcg.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, _dp]
+        L.or_pcg_bc.argtypes = [c_int, c_dbl, c_int, _dp, _dp, c_dbl, c_i64, _dp]
         L.or_efield.argtypes = [c_int, c_dbl, _dp, _dp, _dp, _dp]
         L.or_efield.restype = c_dbl
+        L.or_efield_bc.argtypes = [c_int, c_dbl, c_int, _dp, _dp, _dp, _dp]
+        L.or_efield_bc.restype = c_dbl
         L.or_gather_push.argtypes = [c_i64, c_int, c_dbl, c_dbl, c_dbl, _dp, _dp, _dp,
                                      _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_void_p]
         L.or_half_kick.argtypes = [c_i64, c_int, c_dbl, c_dbl, c_dbl, _dp, _dp, _dp,
@@ -75,6 +81,10 @@ def lib():
         L.or_ssor_apply.argtypes = [c_int, c_dbl, c_dbl, c_int, c_int, _dp, _dp]
         L.or_ssor_apply.restype = c_int
         L.or_pcg_ssor.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_dbl, c_int, c_int, _dp]
+        L.or_ssor_apply_bc.argtypes = [c_int, c_dbl, c_int, c_dbl, c_int, c_int, _dp, _dp]
+        L.or_ssor_apply_bc.restype = c_int
+        L.or_pcg_ssor_bc.argtypes = [c_int, c_dbl, c_int, _dp, _dp, c_dbl, c_i64, c_dbl, c_int,
+                                     c_int, _dp]
         L.or_mixed_pcg_ex.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_dbl, c_i64,
                                       ctypes.c_int, _dp]
         L.or_deposit_vertices.argtypes = [c_i64, c_int, c_dbl, c_dbl, _dp, _dp, _dp, c_i64, _i64p, _dp]
@@ -136,23 +146,33 @@ def deposit_vertices(N: int, L: float, q: float, x, y, z, vid) -> np.ndarray:
     return out
 
 
-def apply_A(N: int, L: float, u) -> np.ndarray:
+# Boundary kinds of the PCG solve (Sec. 3.2): the periodic box of the PIC
+# loop, and the bounded boxes (homogeneous, all six faces) of or_apply_A_bc.
+BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
+
+
+def grid_h(N: int, L: float, bc: int = 0) -> float:
+    """Grid spacing: L/(N+1) for Dirichlet (interior vertices), else L/N."""
+    return L / (N + 1) if bc == BC_DIRICHLET else L / N
+
+
+def apply_A(N: int, L: float, u, bc: int = 0) -> np.ndarray:
     u = _f64(u).reshape(-1)
     out = np.empty_like(u)
-    lib().or_apply_A(N, L, u, out)
+    lib().or_apply_A_bc(N, L, bc, u, out)
     return out
 
 
-def residual_norm(N: int, L: float, b, x) -> float:
-    return lib().or_residual_norm(N, L, _f64(b).reshape(-1), _f64(x).reshape(-1))
+def residual_norm(N: int, L: float, b, x, bc: int = 0) -> float:
+    return lib().or_residual_norm_bc(N, L, bc, _f64(b).reshape(-1), _f64(x).reshape(-1))
 
 
-def pcg(N: int, L: float, b, x0, rtol: float, max_iter: int):
+def pcg(N: int, L: float, b, x0, rtol: float, max_iter: int, bc: int = 0):
     """Jacobi-PCG; returns (x, info dict)."""
     b = _f64(b).reshape(-1)
     x = _f64(x0).reshape(-1).copy()
     info = np.zeros(5)
-    lib().or_pcg(N, L, b, x, rtol, max_iter, info)
+    lib().or_pcg_bc(N, L, bc, b, x, rtol, max_iter, info)
     return x, dict(iters=int(info[0]), rel_res=info[1], true_rel_res=info[2],
                    converged=bool(info[3]), replacements=int(info[4]))
 
@@ -160,30 +180,31 @@ def pcg(N: int, L: float, b, x0, rtol: float, max_iter: int):
 SSOR_OMEGA = math.pi / 2  # the damping factor of the paper's PCG runs (Sec. 4.1)
 
 
-def ssor_apply(N, L, r, omega=SSOR_OMEGA, inner=4, outer=2):
+def ssor_apply(N, L, r, omega=SSOR_OMEGA, inner=4, outer=2, bc=0):
     """z = SSOR preconditioner applied to r (see or_ssor_apply)."""
     r = _f64(r).reshape(-1)
     z = np.empty_like(r)
-    if lib().or_ssor_apply(N, L, omega, inner, outer, r, z) != 0:
+    if lib().or_ssor_apply_bc(N, L, bc, omega, inner, outer, r, z) != 0:
         raise MemoryError("or_ssor_apply")
     return z
 
 
-def pcg_ssor(N, L, b, x0, rtol, max_iter, omega=SSOR_OMEGA, inner=4, outer=2):
+def pcg_ssor(N, L, b, x0, rtol, max_iter, omega=SSOR_OMEGA, inner=4, outer=2, bc=0):
     """PCG with the SSOR preconditioner; returns (x, info dict) as pcg()."""
     b = _f64(b).reshape(-1)
     x = _f64(x0).reshape(-1).copy()
     info = np.zeros(5)
-    lib().or_pcg_ssor(N, L, b, x, rtol, max_iter, omega, inner, outer, info)
+    lib().or_pcg_ssor_bc(N, L, bc, b, x, rtol, max_iter, omega, inner, outer, info)
     return x, dict(iters=int(info[0]), rel_res=info[1], true_rel_res=info[2],
                    converged=bool(info[3]), replacements=int(info[4]))
 
 
-def efield(N: int, L: float, phi):
-    """Gauge-fix phi (returned copy) and E = -grad phi; returns (phi, ex, ey, ez, Wx)."""
+def efield(N: int, L: float, phi, bc: int = 0):
+    """Gauge-fix phi (returned copy; not for Dirichlet) and E = -grad phi;
+    returns (phi, ex, ey, ez, Wx)."""
     phi = _f64(phi).reshape(-1).copy()
     ex, ey, ez = (np.empty_like(phi) for _ in range(3))
-    wx = lib().or_efield(N, L, phi, ex, ey, ez)
+    wx = lib().or_efield_bc(N, L, bc, phi, ex, ey, ez)
     return phi, ex, ey, ez, wx
 
 

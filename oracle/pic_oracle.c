@@ -24,6 +24,15 @@
  * Conventions shared with the product (restated, not shared code):
  *   grid: vertex-centred, value i sits at x = i*h, h = L/N, periodic, layout
  *         [iz][iy][ix] with ix fastest;   inv_h = (double)N / L.
+ *   Bounded boxes (the PCG solver's Dirichlet and Neumann boundaries, Sec. 3.2
+ *   and Table solver_comparison_table; the discretisation is this file's
+ *   reading, the paper gives none), bc = 1 or 2, same on all six faces:
+ *     Dirichlet (bc 1): phi = 0 on the boundary of [0, L]^3; the unknowns are
+ *       the N^3 interior vertices x_i = (i+1) h, h = L/(N+1); a neighbour on
+ *       the boundary contributes 0;  inv_h = (double)(N + 1) / L.
+ *     Neumann (bc 2): zero normal derivative; the unknowns sit at the cell
+ *       centres x_i = (i + 1/2) h, h = L/N; the value across a face mirrors the
+ *       value inside (zero flux);  inv_h = (double)N / L.
  *   Floating point: IEEE binary64, round to nearest; this file must be compiled
  *   with -ffp-contract=off and without -ffast-math.
  *
@@ -38,7 +47,7 @@
 
 #define OR_IDX(N, ix, iy, iz) ((((int64_t)(iz)) * (N) + (iy)) * (int64_t)(N) + (ix))
 
-int or_abi_version(void) { return 3; }
+int or_abi_version(void) { return 4; }
 
 /* ------------------------------------------------------------------------ */
 /* Cell index and CIC fraction of one coordinate.
@@ -149,27 +158,52 @@ double or_deposit(int64_t np, int N, double L, double q, double rho_bg,
 }
 
 /* ------------------------------------------------------------------------ */
-/* A = -Lap_h, the 7-point second-order central-difference operator on the
- * periodic grid (Sec. 3.2):  (A u)_i = (6 u_i - sum of 6 neighbours) / h^2.
- * Neighbour sum taken as ((xm + xp) + (ym + yp)) + (zm + zp).               */
-void or_apply_A(int N, double L, const double *u, double *Au)
+/* 1/h of the grid of boundary kind bc (conventions above). */
+static double or_inv_h(int N, double L, int bc)
 {
-    double inv_h = (double)N / L;
+    return bc == 1 ? (double)(N + 1) / L : (double)N / L;
+}
+
+/* Value of u at integer point (ix, iy, iz), each coordinate in [-1, N]: the
+ * point itself inside the grid; outside it, the periodic image (bc 0), zero
+ * (bc 1, Dirichlet) or the mirrored inside value (bc 2, Neumann). */
+static double or_ghost(const double *u, int N, int bc, int ix, int iy, int iz)
+{
+    int c[3] = {ix, iy, iz};
+    for (int d = 0; d < 3; ++d) {
+        if (c[d] >= 0 && c[d] < N) continue;
+        if (bc == 1) return 0.0;
+        if (bc == 2) c[d] = c[d] < 0 ? 0 : N - 1;
+        else c[d] = c[d] < 0 ? c[d] + N : c[d] - N;
+    }
+    return u[OR_IDX(N, c[0], c[1], c[2])];
+}
+
+/* A = -Lap_h, the 7-point second-order central-difference operator
+ * (Sec. 3.2):  (A u)_i = (6 u_i - sum of 6 neighbours) / h^2, the neighbours
+ * taken through the boundary rule of bc (periodic for the PIC loop).
+ * Neighbour sum taken as ((xm + xp) + (ym + yp)) + (zm + zp).               */
+void or_apply_A_bc(int N, double L, int bc, const double *u, double *Au)
+{
+    double inv_h = or_inv_h(N, L, bc);
     double inv_h2 = inv_h * inv_h;
 #pragma omp parallel for schedule(static)
     for (int iz = 0; iz < N; ++iz) {
-        int zm = (iz + N - 1) % N, zp = (iz + 1) % N;
         for (int iy = 0; iy < N; ++iy) {
-            int ym = (iy + N - 1) % N, yp = (iy + 1) % N;
             for (int ix = 0; ix < N; ++ix) {
-                int xm = (ix + N - 1) % N, xp = (ix + 1) % N;
-                double t = ((u[OR_IDX(N, xm, iy, iz)] + u[OR_IDX(N, xp, iy, iz)]) +
-                            (u[OR_IDX(N, ix, ym, iz)] + u[OR_IDX(N, ix, yp, iz)])) +
-                           (u[OR_IDX(N, ix, iy, zm)] + u[OR_IDX(N, ix, iy, zp)]);
+                double t = ((or_ghost(u, N, bc, ix - 1, iy, iz) + or_ghost(u, N, bc, ix + 1, iy, iz)) +
+                            (or_ghost(u, N, bc, ix, iy - 1, iz) + or_ghost(u, N, bc, ix, iy + 1, iz))) +
+                           (or_ghost(u, N, bc, ix, iy, iz - 1) + or_ghost(u, N, bc, ix, iy, iz + 1));
                 Au[OR_IDX(N, ix, iy, iz)] = (6.0 * u[OR_IDX(N, ix, iy, iz)] - t) * inv_h2;
             }
         }
     }
+}
+
+/* The periodic operator of the PIC loop. */
+void or_apply_A(int N, double L, const double *u, double *Au)
+{
+    or_apply_A_bc(N, L, 0, u, Au);
 }
 
 static double or_dot(int64_t n, const double *a, const double *b)
@@ -180,23 +214,28 @@ static double or_dot(int64_t n, const double *a, const double *b)
 }
 
 /* r = b - A x;  returns ||r||_2.  */
-static double or_true_residual(int N, double L, const double *b, const double *x,
+static double or_true_residual(int N, double L, int bc, const double *b, const double *x,
                                double *r)
 {
     int64_t n3 = (int64_t)N * N * N;
-    or_apply_A(N, L, x, r);
+    or_apply_A_bc(N, L, bc, x, r);
     for (int64_t i = 0; i < n3; ++i) r[i] = b[i] - r[i];
     return sqrt(or_dot(n3, r, r));
 }
 
-double or_residual_norm(int N, double L, const double *b, const double *x)
+double or_residual_norm_bc(int N, double L, int bc, const double *b, const double *x)
 {
     int64_t n3 = (int64_t)N * N * N;
     double *r = (double *)malloc(sizeof(double) * (size_t)n3);
     if (!r) return -1.0;
-    double nr = or_true_residual(N, L, b, x, r);
+    double nr = or_true_residual(N, L, bc, b, x, r);
     free(r);
     return nr;
+}
+
+double or_residual_norm(int N, double L, const double *b, const double *x)
+{
+    return or_residual_norm_bc(N, L, 0, b, x);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -210,13 +249,18 @@ double or_residual_norm(int N, double L, const double *b, const double *x)
  * b - A x is then computed, and if it fails the same test it replaces r,
  * p restarts from M^{-1} r, and iteration continues (residual replacement).
  * ||b|| = 0 gives x = 0.
+ * Bounded boxes (bc 1, 2): the same iteration with the operator of bc and
+ * M^{-1} = (h^2/6) I with that grid's h, which is diag(A)^{-1} for Dirichlet;
+ * for Neumann it is the inverse of the interior rows' diagonal (the boundary
+ * rows' diagonal is (6 - m)/h^2 for a point touching m faces) -- a reading,
+ * kept so that the preconditioner stays a scalar.
  * info[0]=iterations, [1]=last recursive ||r||/||b||, [2]=true ||b-Ax||/||b||,
  * [3]=converged (1/0), [4]=residual replacements.                         */
-void or_pcg(int N, double L, const double *b, double *x, double rtol, int64_t max_iter,
-            double *info)
+void or_pcg_bc(int N, double L, int bc, const double *b, double *x, double rtol,
+               int64_t max_iter, double *info)
 {
     int64_t n3 = (int64_t)N * N * N;
-    double inv_h = (double)N / L;
+    double inv_h = or_inv_h(N, L, bc);
     double minv = 1.0 / (6.0 * (inv_h * inv_h));
     double *r = (double *)malloc(sizeof(double) * (size_t)n3);
     double *z = (double *)malloc(sizeof(double) * (size_t)n3);
@@ -233,13 +277,13 @@ void or_pcg(int N, double L, const double *b, double *x, double rtol, int64_t ma
         return;
     }
     double tol = rtol * nb;
-    double nr = or_true_residual(N, L, b, x, r);
+    double nr = or_true_residual(N, L, bc, b, x, r);
     rel = trel = nr / nb;
     if (nr <= tol) converged = 1;
     for (int64_t i = 0; i < n3; ++i) { z[i] = minv * r[i]; p[i] = z[i]; }
     double rz = or_dot(n3, r, z);
     while (!converged && it < max_iter) {
-        or_apply_A(N, L, p, q);
+        or_apply_A_bc(N, L, bc, p, q);
         double alpha = rz / or_dot(n3, p, q);
         for (int64_t i = 0; i < n3; ++i) {
             x[i] = x[i] + alpha * p[i];
@@ -249,7 +293,7 @@ void or_pcg(int N, double L, const double *b, double *x, double rtol, int64_t ma
         double rn = sqrt(or_dot(n3, r, r));
         rel = rn / nb;
         if (rn <= tol) {
-            double tn = or_true_residual(N, L, b, x, q);
+            double tn = or_true_residual(N, L, bc, b, x, q);
             trel = tn / nb;
             if (tn <= tol) { converged = 1; break; }
             /* residual replacement: r <- b - A x, restart the direction */
@@ -265,9 +309,15 @@ void or_pcg(int N, double L, const double *b, double *x, double rtol, int64_t ma
         rz = rz_new;
         for (int64_t i = 0; i < n3; ++i) p[i] = z[i] + beta * p[i];
     }
-    if (!converged) trel = or_residual_norm(N, L, b, x) / nb;
+    if (!converged) trel = or_residual_norm_bc(N, L, bc, b, x) / nb;
     info[0] = (double)it; info[1] = rel; info[2] = trel; info[3] = converged; info[4] = (double)repl;
     free(r); free(z); free(p); free(q);
+}
+
+void or_pcg(int N, double L, const double *b, double *x, double rtol, int64_t max_iter,
+            double *info)
+{
+    or_pcg_bc(N, L, 0, b, x, rtol, max_iter, info);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -284,23 +334,26 @@ void or_pcg(int N, double L, const double *b, double *x, double rtol, int64_t ma
  * (D^{-1} w/h^2 = w/6), then z <- w (2 - w) z_inner.  The approximate solves
  * are polynomials in the backward (forward) shift, each the transpose of the
  * other, so the preconditioner is symmetric.  `outer` stationary steps:
- *     z <- z + SSOR(r - A z)   after the first z = SSOR(r).                */
-static void or_ssor_once(int N, double inv_h2, double omega, int inner, const double *r,
+ *     z <- z + SSOR(r - A z)   after the first z = SSOR(r).
+ * Bounded boxes: D = (6/h^2) I with the box's h and L, U the couplings
+ * between unknowns only (no neighbour across a face), which makes the
+ * triangular solves true (non-cyclic) ones; A is the operator of bc.       */
+static void or_ssor_once(int N, int bc, double inv_h2, double omega, int inner, const double *r,
                          double *z, double *y, double *t)
 {
     int64_t n3 = (int64_t)N * N * N;
     double dinv = 1.0 / (6.0 * inv_h2);
     double c = omega / 6.0;
+    /* the triangular factors hold the off-diagonal couplings between
+     * unknowns: cyclic on the periodic grid, none across a bounded face */
+    int tb = bc == 0 ? 0 : 1;
     for (int64_t i = 0; i < n3; ++i) y[i] = dinv * r[i];
     for (int j = 0; j < inner; ++j) {
         for (int iz = 0; iz < N; ++iz) {
-            int zm = (iz + N - 1) % N;
             for (int iy = 0; iy < N; ++iy) {
-                int ym = (iy + N - 1) % N;
                 for (int ix = 0; ix < N; ++ix) {
-                    int xm = (ix + N - 1) % N;
-                    double s = (y[OR_IDX(N, xm, iy, iz)] + y[OR_IDX(N, ix, ym, iz)]) +
-                               y[OR_IDX(N, ix, iy, zm)];
+                    double s = (or_ghost(y, N, tb, ix - 1, iy, iz) + or_ghost(y, N, tb, ix, iy - 1, iz)) +
+                               or_ghost(y, N, tb, ix, iy, iz - 1);
                     t[OR_IDX(N, ix, iy, iz)] = dinv * r[OR_IDX(N, ix, iy, iz)] + c * s;
                 }
             }
@@ -310,13 +363,10 @@ static void or_ssor_once(int N, double inv_h2, double omega, int inner, const do
     for (int64_t i = 0; i < n3; ++i) z[i] = y[i];
     for (int j = 0; j < inner; ++j) {
         for (int iz = 0; iz < N; ++iz) {
-            int zp = (iz + 1) % N;
             for (int iy = 0; iy < N; ++iy) {
-                int yp = (iy + 1) % N;
                 for (int ix = 0; ix < N; ++ix) {
-                    int xp = (ix + 1) % N;
-                    double s = (z[OR_IDX(N, xp, iy, iz)] + z[OR_IDX(N, ix, yp, iz)]) +
-                               z[OR_IDX(N, ix, iy, zp)];
+                    double s = (or_ghost(z, N, tb, ix + 1, iy, iz) + or_ghost(z, N, tb, ix, iy + 1, iz)) +
+                               or_ghost(z, N, tb, ix, iy, iz + 1);
                     t[OR_IDX(N, ix, iy, iz)] = y[OR_IDX(N, ix, iy, iz)] + c * s;
                 }
             }
@@ -327,31 +377,37 @@ static void or_ssor_once(int N, double inv_h2, double omega, int inner, const do
     for (int64_t i = 0; i < n3; ++i) z[i] = sc * z[i];
 }
 
-int or_ssor_apply(int N, double L, double omega, int inner, int outer, const double *r, double *z)
+int or_ssor_apply_bc(int N, double L, int bc, double omega, int inner, int outer,
+                     const double *r, double *z)
 {
     int64_t n3 = (int64_t)N * N * N;
-    double inv_h = (double)N / L;
+    double inv_h = or_inv_h(N, L, bc);
     double inv_h2 = inv_h * inv_h;
     double *y = (double *)malloc(sizeof(double) * (size_t)n3);
     double *t = (double *)malloc(sizeof(double) * (size_t)n3);
     double *res = (double *)malloc(sizeof(double) * (size_t)n3);
     double *dz = (double *)malloc(sizeof(double) * (size_t)n3);
     if (!y || !t || !res || !dz) { free(y); free(t); free(res); free(dz); return -1; }
-    or_ssor_once(N, inv_h2, omega, inner, r, z, y, t);
+    or_ssor_once(N, bc, inv_h2, omega, inner, r, z, y, t);
     for (int o = 1; o < outer; ++o) {
-        or_apply_A(N, L, z, res);
+        or_apply_A_bc(N, L, bc, z, res);
         for (int64_t i = 0; i < n3; ++i) res[i] = r[i] - res[i];
-        or_ssor_once(N, inv_h2, omega, inner, res, dz, y, t);
+        or_ssor_once(N, bc, inv_h2, omega, inner, res, dz, y, t);
         for (int64_t i = 0; i < n3; ++i) z[i] = z[i] + dz[i];
     }
     free(y); free(t); free(res); free(dz);
     return 0;
 }
 
+int or_ssor_apply(int N, double L, double omega, int inner, int outer, const double *r, double *z)
+{
+    return or_ssor_apply_bc(N, L, 0, omega, inner, outer, r, z);
+}
+
 /* PCG with the SSOR preconditioner: or_pcg's iteration and stopping rule with
  * z = SSOR(r) in place of the Jacobi scaling.  info as in or_pcg.          */
-void or_pcg_ssor(int N, double L, const double *b, double *x, double rtol, int64_t max_iter,
-                 double omega, int inner, int outer, double *info)
+void or_pcg_ssor_bc(int N, double L, int bc, const double *b, double *x, double rtol,
+                    int64_t max_iter, double omega, int inner, int outer, double *info)
 {
     int64_t n3 = (int64_t)N * N * N;
     double *r = (double *)malloc(sizeof(double) * (size_t)n3);
@@ -369,14 +425,14 @@ void or_pcg_ssor(int N, double L, const double *b, double *x, double rtol, int64
         return;
     }
     double tol = rtol * nb;
-    double nr = or_true_residual(N, L, b, x, r);
+    double nr = or_true_residual(N, L, bc, b, x, r);
     rel = trel = nr / nb;
     if (nr <= tol) converged = 1;
-    or_ssor_apply(N, L, omega, inner, outer, r, z);
+    or_ssor_apply_bc(N, L, bc, omega, inner, outer, r, z);
     for (int64_t i = 0; i < n3; ++i) p[i] = z[i];
     double rz = or_dot(n3, r, z);
     while (!converged && it < max_iter) {
-        or_apply_A(N, L, p, q);
+        or_apply_A_bc(N, L, bc, p, q);
         double alpha = rz / or_dot(n3, p, q);
         for (int64_t i = 0; i < n3; ++i) {
             x[i] = x[i] + alpha * p[i];
@@ -386,62 +442,75 @@ void or_pcg_ssor(int N, double L, const double *b, double *x, double rtol, int64
         double rn = sqrt(or_dot(n3, r, r));
         rel = rn / nb;
         if (rn <= tol) {
-            double tn = or_true_residual(N, L, b, x, q);
+            double tn = or_true_residual(N, L, bc, b, x, q);
             trel = tn / nb;
             if (tn <= tol) { converged = 1; break; }
             for (int64_t i = 0; i < n3; ++i) r[i] = q[i];
-            or_ssor_apply(N, L, omega, inner, outer, r, z);
+            or_ssor_apply_bc(N, L, bc, omega, inner, outer, r, z);
             for (int64_t i = 0; i < n3; ++i) p[i] = z[i];
             rz = or_dot(n3, r, z);
             rel = tn / nb;
             ++repl;
             continue;
         }
-        or_ssor_apply(N, L, omega, inner, outer, r, z);
+        or_ssor_apply_bc(N, L, bc, omega, inner, outer, r, z);
         double rz_new = or_dot(n3, r, z);
         double beta = rz_new / rz;
         rz = rz_new;
         for (int64_t i = 0; i < n3; ++i) p[i] = z[i] + beta * p[i];
     }
-    if (!converged) trel = or_residual_norm(N, L, b, x) / nb;
+    if (!converged) trel = or_residual_norm_bc(N, L, bc, b, x) / nb;
     info[0] = (double)it; info[1] = rel; info[2] = trel; info[3] = converged; info[4] = (double)repl;
     free(r); free(z); free(p); free(q);
+}
+
+void or_pcg_ssor(int N, double L, const double *b, double *x, double rtol, int64_t max_iter,
+                 double omega, int inner, int outer, double *info)
+{
+    or_pcg_ssor_bc(N, L, 0, b, x, rtol, max_iter, omega, inner, outer, info);
 }
 
 /* ------------------------------------------------------------------------ */
 /* Field from potential (Sec. 2, Eq. poisson: E = -grad phi) with the
  * second-order central difference that matches the Laplacian:
- *   E_d[i] = -(phi[i+e_d] - phi[i-e_d]) / (2h).
- * The gauge is fixed first: phi <- phi - mean(phi) (written back).
+ *   E_d[i] = -(phi[i+e_d] - phi[i-e_d]) / (2h),
+ * a neighbour outside the grid taken through the boundary rule of bc.
+ * The gauge is fixed first where the operator has constants in its kernel
+ * (periodic, Neumann): phi <- phi - mean(phi) (written back); a Dirichlet
+ * potential is unique and left as it is.
  * Returns W_x = (1/2) h^3 sum E_x^2, the energy of the x component
  * (the quantity of Fig. correctness_landau, with eps0 = 1).               */
-double or_efield(int N, double L, double *phi, double *ex, double *ey, double *ez)
+double or_efield_bc(int N, double L, int bc, double *phi, double *ex, double *ey, double *ez)
 {
     int64_t n3 = (int64_t)N * N * N;
-    double inv_h = (double)N / L;
+    double inv_h = or_inv_h(N, L, bc);
     double ehalf = 0.5 * inv_h;
-    double h = L / (double)N;
-    double s = 0.0;
-    for (int64_t i = 0; i < n3; ++i) s += phi[i];
-    double mean = s / (double)n3;
-    for (int64_t i = 0; i < n3; ++i) phi[i] = phi[i] - mean;
+    double h = L / (double)(bc == 1 ? N + 1 : N);
+    if (bc != 1) {
+        double s = 0.0;
+        for (int64_t i = 0; i < n3; ++i) s += phi[i];
+        double mean = s / (double)n3;
+        for (int64_t i = 0; i < n3; ++i) phi[i] = phi[i] - mean;
+    }
 #pragma omp parallel for schedule(static)
     for (int iz = 0; iz < N; ++iz) {
-        int zm = (iz + N - 1) % N, zp = (iz + 1) % N;
         for (int iy = 0; iy < N; ++iy) {
-            int ym = (iy + N - 1) % N, yp = (iy + 1) % N;
             for (int ix = 0; ix < N; ++ix) {
-                int xm = (ix + N - 1) % N, xp = (ix + 1) % N;
                 int64_t c = OR_IDX(N, ix, iy, iz);
-                ex[c] = -(phi[OR_IDX(N, xp, iy, iz)] - phi[OR_IDX(N, xm, iy, iz)]) * ehalf;
-                ey[c] = -(phi[OR_IDX(N, ix, yp, iz)] - phi[OR_IDX(N, ix, ym, iz)]) * ehalf;
-                ez[c] = -(phi[OR_IDX(N, ix, iy, zp)] - phi[OR_IDX(N, ix, iy, zm)]) * ehalf;
+                ex[c] = -(or_ghost(phi, N, bc, ix + 1, iy, iz) - or_ghost(phi, N, bc, ix - 1, iy, iz)) * ehalf;
+                ey[c] = -(or_ghost(phi, N, bc, ix, iy + 1, iz) - or_ghost(phi, N, bc, ix, iy - 1, iz)) * ehalf;
+                ez[c] = -(or_ghost(phi, N, bc, ix, iy, iz + 1) - or_ghost(phi, N, bc, ix, iy, iz - 1)) * ehalf;
             }
         }
     }
     double w = 0.0;
     for (int64_t i = 0; i < n3; ++i) w += ex[i] * ex[i];
     return 0.5 * w * (h * h * h);
+}
+
+double or_efield(int N, double L, double *phi, double *ex, double *ey, double *ez)
+{
+    return or_efield_bc(N, L, 0, phi, ex, ey, ez);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -629,7 +698,7 @@ void or_mixed_pcg_ex(int N, double L, const double *b, double *x, double rtol,
     int have_dir = 0;        /* reliable form: p holds the last direction */
     double rz_last = 0.0, nr_prev = 0.0;
     for (;;) {
-        double nr = or_true_residual(N, L, b, x, r);
+        double nr = or_true_residual(N, L, 0, b, x, r);
         trel = nr / nb;
         if (nr <= rtol * nb) { converged = 1; break; }
         if (outer >= max_outer) break;
@@ -719,7 +788,7 @@ void or_fcg(int N, double L, const double *b, double *x, double rtol, int64_t ma
         return;
     }
     double tol = rtol * nb;
-    double nr = or_true_residual(N, L, b, x, r);
+    double nr = or_true_residual(N, L, 0, b, x, r);
     double best = nr;
     int since_best = 0;
     if (nr <= tol) converged = 1;
@@ -735,7 +804,7 @@ void or_fcg(int N, double L, const double *b, double *x, double rtol, int64_t ma
         if (!flexible) {
             if (!fell_back) {
                 fell_back = 1;
-                nr = or_true_residual(N, L, b, x, r);
+                nr = or_true_residual(N, L, 0, b, x, r);
                 if (nr <= tol) { converged = 1; break; }
                 for (int64_t i = 0; i < n3; ++i) { z[i] = minv * r[i]; p[i] = z[i]; }
                 rz = or_dot(n3, r, z);
@@ -746,7 +815,7 @@ void or_fcg(int N, double L, const double *b, double *x, double rtol, int64_t ma
             ++it;
             double rn = sqrt(or_dot(n3, r, r));
             if (rn <= tol) {
-                double tn = or_true_residual(N, L, b, x, q);
+                double tn = or_true_residual(N, L, 0, b, x, q);
                 if (tn <= tol) { converged = 1; break; }
                 for (int64_t i = 0; i < n3; ++i) { r[i] = q[i]; z[i] = minv * r[i]; p[i] = z[i]; }
                 rz = or_dot(n3, r, z);
@@ -768,7 +837,7 @@ void or_fcg(int N, double L, const double *b, double *x, double rtol, int64_t ma
         double rn = sqrt(or_dot(n3, r, r));
         if (!isfinite(rn)) { flexible = 0; continue; }
         if (rn <= tol) {
-            double tn = or_true_residual(N, L, b, x, z);
+            double tn = or_true_residual(N, L, 0, b, x, z);
             if (tn <= tol) { converged = 1; break; }
             for (int64_t i = 0; i < n3; ++i) r[i] = z[i];
             rn = tn;

@@ -27,6 +27,12 @@ def box_length(k: float = 0.5) -> float:
     return 2.0 * math.pi / k
 
 
+def normal_field(n: int, seed: int) -> np.ndarray:
+    """n independent N(0, 1) values (FP64) from PCG64(seed): a generic
+    right-hand side for solves on boxes without particles."""
+    return np.random.Generator(np.random.PCG64(seed)).standard_normal(n)
+
+
 @dataclass
 class LandauParams:
     N: int = 32
