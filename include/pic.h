@@ -60,6 +60,29 @@ enum {
                                    the pseudo-spectral 1/|k|^2 and E = -ik phi */
 };
 
+/* pic_params.bc: boundary kind of the box (Sec. 3.2: the PCG solver takes
+ * periodic, Dirichlet and Neumann boundaries; the same kind on all six faces,
+ * homogeneous).  The discretisation of the bounded boxes is a reading (the
+ * paper gives none):
+ *   PIC_BC_PERIODIC   the PIC loop's periodic cube [0, L)^3, h = L/N.
+ *   PIC_BC_DIRICHLET  phi = 0 on the boundary of [0, L]^3; the N^3 unknowns
+ *                     are the interior vertices x_i = (i+1) h, h = L/(N+1); a
+ *                     neighbour on the boundary contributes 0.  A is
+ *                     nonsingular: rho needs no mean projection and phi is
+ *                     not gauge-shifted.
+ *   PIC_BC_NEUMANN    zero normal derivative; the unknowns sit at the cell
+ *                     centres x_i = (i+1/2) h, h = L/N; the value across a
+ *                     face mirrors the value inside.  Constants are in A's
+ *                     kernel: rho must have zero mean, phi is gauge-fixed.
+ * Bounded boxes take the solver forms PCG_FP64, PCG_MIXED and PCG_SSOR; the
+ * Jacobi scaling stays (h^2/6) I (diag(A)^-1 for Dirichlet; the interior
+ * rows' diagonal for Neumann), and SSOR's D is the same scalar with L, U the
+ * couplings between unknowns.  Only pic_poisson_pcg and pic_efield accept a
+ * bounded context; the particle phases need the periodic box. */
+#define PIC_BC_PERIODIC 0
+#define PIC_BC_DIRICHLET 1
+#define PIC_BC_NEUMANN 2
+
 /* Problem statement (Sec. 2 and 2.1; tolerance as in Sec. 4). */
 /* pic_params.flags */
 #define PIC_FLAG_NO_WARM_START 1   /* learned form: no network warm start */
@@ -106,6 +129,7 @@ typedef struct pic_params {
     double ssor_omega;    /* damping w in (0, 2)                            */
     int32_t ssor_inner;   /* Jacobi steps per triangular solve (>= 1)        */
     int32_t ssor_outer;   /* stationary SSOR steps per application (>= 1)    */
+    int32_t bc;           /* PIC_BC_* (above); 0 = the periodic box          */
 } pic_params;
 
 /* Host-side result of one Poisson solve. */
@@ -194,12 +218,13 @@ int pic_deposit_cic(pic_ctx *ctx, int64_t np, const double *x, const double *y,
                     const double *z, const uint32_t *cell_start, double *rho,
                     double *norm_b, void *stream);
 
-/* Solve (Sec. 3.2): A phi = rho with A = -Lap_h, the periodic 7-point
- * second-order operator, by the solver form selected in the context, starting
- * from the phi passed in (the previous step's solution, Sec. 4.1), to
- * ||rho - A phi|| <= rtol ||rho||.  rho must have zero mean.  If ex, ey, ez are
- * all non-NULL, phi is gauge-fixed to zero mean and E = -grad_h phi is
- * computed by central differences (Sec. 2, Eq. poisson).  info: host out. */
+/* Solve (Sec. 3.2): A phi = rho with A = -Lap_h, the 7-point second-order
+ * operator on the context's box (periodic unless pic_params.bc says
+ * otherwise), by the solver form selected in the context, starting from the
+ * phi passed in (the previous step's solution, Sec. 4.1), to
+ * ||rho - A phi|| <= rtol ||rho||.  rho must have zero mean (not so on a
+ * Dirichlet box).  If ex, ey, ez are all non-NULL, the field is computed as
+ * pic_efield does (Sec. 2, Eq. poisson).  info: host out. */
 int pic_poisson_pcg(pic_ctx *ctx, const double *rho, double *phi, double *ex,
                     double *ey, double *ez, pic_solve_info *info, void *stream);
 
@@ -217,8 +242,10 @@ int pic_half_kick(pic_ctx *ctx, int64_t np, const double *x, const double *y,
                   const double *z, double *vx, double *vy, double *vz,
                   const double *ex, const double *ey, const double *ez, void *stream);
 
-/* E = -grad_h phi after gauge-fixing phi to zero mean; wx (host out,
- * nullable) = (1/2) h^3 sum Ex^2, the x-field energy of Fig. correctness_landau. */
+/* E = -grad_h phi by central differences after gauge-fixing phi to zero
+ * mean (a Dirichlet potential is left as it is; a neighbour outside a
+ * bounded box follows the box's boundary rule); wx (host out, nullable) =
+ * (1/2) h^3 sum Ex^2, the x-field energy of Fig. correctness_landau. */
 int pic_efield(pic_ctx *ctx, double *phi, double *ex, double *ey, double *ez,
                double *wx, void *stream);
 

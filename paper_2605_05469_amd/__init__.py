@@ -25,6 +25,9 @@ FLAG_LEARNED_MIXED = 8
 FLAG_FFT_SPECTRAL = 16
 FLAG_SSOR_UNFUSED = 32
 
+# pic_params.bc: the box's boundary kind (the particle phases need PERIODIC)
+BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
+
 
 class PicError(RuntimeError):
     def __init__(self, code, msg):
@@ -41,7 +44,8 @@ class pic_params(ctypes.Structure):
                 ("inner_rtol", ctypes.c_double), ("max_inner", ctypes.c_int64),
                 ("max_outer", ctypes.c_int64), ("fcg_window", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("ssor_omega", ctypes.c_double),
-                ("ssor_inner", ctypes.c_int32), ("ssor_outer", ctypes.c_int32)]
+                ("ssor_inner", ctypes.c_int32), ("ssor_outer", ctypes.c_int32),
+                ("bc", ctypes.c_int32)]
 
 
 class pic_solve_info(ctypes.Structure):
@@ -178,7 +182,7 @@ def _stream(stream=None):
 def landau_params(N, ppc, k=0.5, dt=0.05, qm=-1.0, rtol=1e-10, max_iter=20000,
                   solver="pcg_fp64", np_max=None, check_every=16, inner_rtol=1e-3,
                   max_inner=20000, max_outer=50, fcg_window=10, ssor_omega=math.pi / 2,
-                  ssor_inner=4, ssor_outer=2, flags=0):
+                  ssor_inner=4, ssor_outer=2, flags=0, bc=BC_PERIODIC):
     """Parameters of the Landau-damping box (Sec. 2.1): L = 2 pi / k, unit
     mean density, q = -L^3/Np, background +1."""
     L = 2.0 * math.pi / k
@@ -196,6 +200,7 @@ def landau_params(N, ppc, k=0.5, dt=0.05, qm=-1.0, rtol=1e-10, max_iter=20000,
     p.fcg_window = fcg_window
     p.ssor_omega, p.ssor_inner, p.ssor_outer = ssor_omega, ssor_inner, ssor_outer
     p.flags = flags
+    p.bc = bc
     return p
 
 

@@ -53,7 +53,8 @@ extern "C" int pic_set_error_(int code, const char* msg) { return fail(code, "%s
 struct pic_ctx {
     pic_params p;
     int device = 0;
-    SweepGeo geo;
+    SweepGeo geo;      // the operator A (boundary kind of the box)
+    SweepGeo geo_tri;  // SSOR's triangular factors
     int64_t n3 = 0;
     double L = 0, inv_h = 0, inv_h2 = 0, minv = 0, h = 0, h3 = 0, ehalf = 0, qh3 = 0;
     double coef_push = 0, coef_kick = 0;
@@ -94,6 +95,13 @@ constexpr int32_t kKnownFlags = PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONL
                                  PIC_FLAG_MIXED_RELIABLE | PIC_FLAG_LEARNED_MIXED |
                                  PIC_FLAG_FFT_SPECTRAL | PIC_FLAG_SSOR_UNFUSED;
 
+// The solver forms that take a bounded box: the matrix-free stencil ones.
+// The FFT form and the network (periodic convolutions) need the periodic box.
+static bool bounded_solver(int32_t solver) {
+    return solver == PIC_SOLVER_PCG_FP64 || solver == PIC_SOLVER_PCG_MIXED ||
+           solver == PIC_SOLVER_PCG_SSOR;
+}
+
 static int validate_params(const pic_params* p) {
     if (!p) return fail(PIC_ERR_INVALID, "params is NULL");
     if (p->n < 32 || p->n > 1024 || (p->n % 32) != 0)
@@ -113,6 +121,11 @@ static int validate_params(const pic_params* p) {
         !std::isfinite(p->rho_bg))
         return fail(PIC_ERR_INVALID, "charge, qm, dt and rho_bg must be finite");
     if (p->flags & ~kKnownFlags) return fail(PIC_ERR_INVALID, "unknown flags 0x%x", p->flags);
+    if (p->bc < PIC_BC_PERIODIC || p->bc > PIC_BC_NEUMANN)
+        return fail(PIC_ERR_INVALID, "unknown boundary kind %d", p->bc);
+    if (p->bc != PIC_BC_PERIODIC && !bounded_solver(p->solver))
+        return fail(PIC_ERR_INVALID, "solver %d needs the periodic box (bounded boxes: "
+                                     "PCG_FP64, PCG_MIXED, PCG_SSOR)", p->solver);
     return PIC_OK;
 }
 
@@ -584,15 +597,16 @@ static int solve_learned(pic_ctx* c, const double* b, double* x, pic_solve_info*
 // Buffers: sv[2], sv[3] forward ping-pong, sv[4] backward, sv[5] = r - A z.
 static int ssor_once(pic_ctx* c, const double* rhs, double* out, const double* add,
                      const double* rdot, hipStream_t s) {
-    const SweepGeo& g = c->geo;
+    const SweepGeo& g = c->geo_tri;
+    const int bounded = c->p.bc != PIC_BC_PERIODIC;
     const int k = c->p.ssor_inner;
     const double w = c->p.ssor_omega;
     const double cc = w / 6.0, dinv = c->minv, sc = w * (2.0 - w);
     if (!(c->p.flags & PIC_FLAG_SSOR_UNFUSED) && ssor_fused_supported(c->p.n, k)) {
-        HIPCHK(launch_ssor_fused(c->p.n, k, 0, rhs, nullptr, nullptr, c->sv[2], dinv, cc, 1.0,
+        HIPCHK(launch_ssor_fused(c->p.n, bounded, k, 0, rhs, nullptr, nullptr, c->sv[2], dinv, cc,
+                                 1.0, c->st, c->partials, s));
+        HIPCHK(launch_ssor_fused(c->p.n, bounded, k, 1, c->sv[2], add, rdot, out, 1.0, cc, sc,
                                  c->st, c->partials, s));
-        HIPCHK(launch_ssor_fused(c->p.n, k, 1, c->sv[2], add, rdot, out, 1.0, cc, sc, c->st,
-                                 c->partials, s));
         return PIC_OK;
     }
     double* ya = c->sv[2];
@@ -764,7 +778,9 @@ static int spectral_wx(pic_ctx* c, const double* ex, hipStream_t s, double* wx) 
 // ------------------------------------------------------------------ field --
 
 static int field(pic_ctx* c, double* phi, double* ex, double* ey, double* ez, hipStream_t s) {
-    HIPCHK(launch_sum(c->n3, phi, c->st, c->partials, 0, s));
+    // the gauge (mean of phi) where constants are in A's kernel; a Dirichlet
+    // potential is unique and kept as it is
+    if (c->p.bc != PIC_BC_DIRICHLET) HIPCHK(launch_sum(c->n3, phi, c->st, c->partials, 0, s));
     HIPCHK(launch_field(c->geo, phi, ex, ey, ez, c->ehalf, c->h3, c->st, c->partials, s));
     return PIC_OK;
 }
@@ -806,13 +822,19 @@ int pic_create(const pic_params* params, pic_ctx** out) {
     if (c->p.ssor_outer == 0) c->p.ssor_outer = 2;
     const int n = c->p.n;
     c->n3 = (int64_t)n * n * n;
-    c->geo = make_geo(n);
+    const int bc = c->p.bc;
+    c->geo = make_geo(n, bc);
+    // SSOR's triangular factors couple unknowns only: no neighbour across a
+    // bounded face (zero ghosts), cyclic on the periodic box
+    c->geo_tri = make_geo(n, bc == PIC_BC_PERIODIC ? 0 : 1);
     c->L = c->p.length;
-    // the same formulas, in the same order, as the CPU definition
-    c->inv_h = (double)n / c->L;
+    // the same formulas, in the same order, as the CPU definition; a
+    // Dirichlet box has N interior vertices, so h = L / (N + 1)
+    const int cells = bc == PIC_BC_DIRICHLET ? n + 1 : n;
+    c->inv_h = (double)cells / c->L;
     c->inv_h2 = c->inv_h * c->inv_h;
     c->minv = 1.0 / (6.0 * (c->inv_h * c->inv_h));
-    c->h = c->L / (double)n;
+    c->h = c->L / (double)cells;
     c->h3 = c->h * c->h * c->h;
     c->ehalf = 0.5 * c->inv_h;
     c->qh3 = c->p.charge * (c->inv_h * c->inv_h * c->inv_h);
@@ -885,6 +907,8 @@ int pic_set_solver(pic_ctx* c, int32_t solver) {
     if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
     if (solver < PIC_SOLVER_PCG_FP64 || solver > PIC_SOLVER_FFT)
         return fail(PIC_ERR_INVALID, "unknown solver %d", solver);
+    if (c->p.bc != PIC_BC_PERIODIC && !bounded_solver(solver))
+        return fail(PIC_ERR_INVALID, "solver %d needs the periodic box", solver);
     if (solver == PIC_SOLVER_PCG_SSOR) RETCHK(ensure_ssor(c));
     if (solver == PIC_SOLVER_FFT) RETCHK(ensure_fft(c));
     if (solver == PIC_SOLVER_PCG_MIXED) RETCHK(ensure_mixed(c));
@@ -929,9 +953,18 @@ static int check_np(pic_ctx* c, int64_t np) {
     return PIC_OK;
 }
 
+// Particles live in the periodic cube: the particle phases refuse a context
+// made for a bounded box (only its solve and field are built).
+static int check_periodic(pic_ctx* c) {
+    if (c->p.bc != PIC_BC_PERIODIC)
+        return fail(PIC_ERR_INVALID, "particle phases need the periodic box (bc = %d)", c->p.bc);
+    return PIC_OK;
+}
+
 int pic_cell_keys(pic_ctx* c, int64_t np, const double* x, const double* y, const double* z,
                   uint32_t* key, void* stream) {
     RETCHK(check_np(c, np));
+    RETCHK(check_periodic(c));
     if (np == 0) return PIC_OK;
     NEED(x, "x"); NEED(y, "y"); NEED(z, "z");
     if (!key) return fail(PIC_ERR_INVALID, "key is NULL");
@@ -962,6 +995,7 @@ int pic_sort_cells(pic_ctx* c, int64_t np, const uint32_t* key, const double* co
 int pic_deposit_cic(pic_ctx* c, int64_t np, const double* x, const double* y, const double* z,
                     const uint32_t* cell_start, double* rho, double* norm_b, void* stream) {
     RETCHK(check_np(c, np));
+    RETCHK(check_periodic(c));
     NEED(rho, "rho");
     if (np > 0) { NEED(x, "x"); NEED(y, "y"); NEED(z, "z"); }
     hipStream_t s = (hipStream_t)stream;
@@ -1036,6 +1070,8 @@ int pic_set_unet(pic_ctx* c, const float* params, void* stream) {
 
 int pic_unet_precondition(pic_ctx* c, const double* r, double* z, void* stream) {
     if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
+    if (c->p.bc != PIC_BC_PERIODIC)
+        return fail(PIC_ERR_INVALID, "the network's convolutions need the periodic box");
     NEED(r, "r");
     NEED(z, "z");
     return fcg_precond(c, r, z, (hipStream_t)stream);
@@ -1045,6 +1081,7 @@ int pic_gather_push(pic_ctx* c, int64_t np, double* x, double* y, double* z, dou
                     double* vy, double* vz, const double* ex, const double* ey, const double* ez,
                     uint32_t* key_out, void* stream) {
     RETCHK(check_np(c, np));
+    RETCHK(check_periodic(c));
     if (np == 0) return PIC_OK;
     NEED(x, "x"); NEED(y, "y"); NEED(z, "z"); NEED(vx, "vx"); NEED(vy, "vy"); NEED(vz, "vz");
     NEED(ex, "ex"); NEED(ey, "ey"); NEED(ez, "ez");
@@ -1057,6 +1094,7 @@ int pic_half_kick(pic_ctx* c, int64_t np, const double* x, const double* y, cons
                   double* vx, double* vy, double* vz, const double* ex, const double* ey,
                   const double* ez, void* stream) {
     RETCHK(check_np(c, np));
+    RETCHK(check_periodic(c));
     if (np == 0) return PIC_OK;
     NEED(x, "x"); NEED(y, "y"); NEED(z, "z"); NEED(vx, "vx"); NEED(vy, "vy"); NEED(vz, "vz");
     NEED(ex, "ex"); NEED(ey, "ey"); NEED(ez, "ez");
@@ -1068,6 +1106,7 @@ int pic_half_kick(pic_ctx* c, int64_t np, const double* x, const double* y, cons
 static int check_parts(pic_ctx* c, pic_particles* P, pic_fields* F) {
     if (!P || !F) return fail(PIC_ERR_INVALID, "particles/fields is NULL");
     RETCHK(check_np(c, P->np));
+    RETCHK(check_periodic(c));
     NEED(F->rho, "rho"); NEED(F->phi, "phi"); NEED(F->ex, "ex"); NEED(F->ey, "ey"); NEED(F->ez, "ez");
     if (!P->cell_start) return fail(PIC_ERR_INVALID, "cell_start is NULL");
     if (P->np > 0) {

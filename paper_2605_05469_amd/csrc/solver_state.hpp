@@ -57,11 +57,11 @@ struct DevState {
 // fills in the tiling (tiles in x and y, blocks per column in z).
 struct SweepGeo {
     int32_t n;   // grid points per axis
-    int32_t zc;  // unused (kept for layout)
+    int32_t bc;  // neighbours outside the grid: 0 periodic, 1 zero, 2 mirrored
     uint32_t nbx, nby, nbz, nb;
 };
 
-SweepGeo make_geo(int n);
+SweepGeo make_geo(int n, int bc);
 
 // Host launchers (stream-ordered, asynchronous).  All return hipError_t.
 // FP64 Jacobi-PCG pieces.
@@ -97,9 +97,10 @@ hipError_t launch_resid_norm(const SweepGeo& g, const double* b, const double* x
 // x += a p, r -= a q with r.r -> flex_rr; z.r, z.q -> flex_zr, flex_zq;
 // p = z + b p; w = x + z; dst = src.
 bool ssor_fused_supported(int n, int inner);
-hipError_t launch_ssor_fused(int n, int inner, int dir, const double* src, const double* add,
-                             const double* rdot, double* dst, double s0, double c, double oscale,
-                             DevState* st, double* partials, hipStream_t s);
+hipError_t launch_ssor_fused(int n, int bounded, int inner, int dir, const double* src,
+                             const double* add, const double* rdot, double* dst, double s0,
+                             double c, double oscale, DevState* st, double* partials,
+                             hipStream_t s);
 hipError_t launch_ssor_half(const SweepGeo& g, const double* src, const double* base,
                             const double* add, const double* rdot, double* dst, double c,
                             double bscale, double sscale, double oscale, int dir, DevState* st,

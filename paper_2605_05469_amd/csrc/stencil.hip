@@ -55,6 +55,11 @@ constexpr int kMaxSweepBlocks = 8192;
 // Generic sweep.  A sweep never writes the array it stages into LDS:
 // neighbouring workgroups read that array as their halo at any time.
 //
+// Neighbours outside the grid follow g.bc: the periodic image (0), zero (1:
+// Dirichlet, and the triangular factors of a bounded box), or the mirrored
+// value inside the face (2: Neumann).  Ghost entries are loaded from the
+// clamped index (always in bounds) and replaced by zero for bc 1.
+//
 // LDS holds two planes (z and z+1, each with its halo); the z-1 neighbour of
 // each thread's own points is kept in registers from the previous plane.  The
 // loads for plane z+2 (halo plane) and for the own-point operands of plane z+1
@@ -106,21 +111,27 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
     const int lx = tid % TX, ly0 = tid / TX;
 
     // in-plane offsets of this thread's staged entries (fixed for the block)
+    const int bc = g.bc;
+    auto gmap = [n, bc](int v) {
+        if (v >= 0 && v < n) return v;
+        if (bc == 0) return v < 0 ? v + n : v - n;
+        return v < 0 ? 0 : n - 1;
+    };
     uint32_t eoff[NE];
-    uint32_t eown = 0;
+    uint32_t eown = 0, ezero = 0;
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
         const int e = tid + j * kNT;
         const int ly = e / PX;
         const int lxx = e - ly * PX;
-        int gx = x0 + lxx - 1;
-        gx = gx < 0 ? gx + n : (gx >= n ? gx - n : gx);
-        int gy = y0 + ly - 1;
-        gy = gy < 0 ? gy + n : (gy >= n ? gy - n : gy);
+        const int rx = x0 + lxx - 1, ry = y0 + ly - 1;
+        const int gx = gmap(rx), gy = gmap(ry);
         eoff[j] = (uint32_t)gy * (uint32_t)n + (uint32_t)gx;
         if (e < PLANE && lxx >= 1 && lxx <= TX && ly >= 1 && ly <= kTY) eown |= 1u << j;
+        if (bc == 1 && (rx != gx || ry != gy)) ezero |= 1u << j;
     }
-    auto zwrap = [n](int z) { return z >= n ? z - n : (z < 0 ? z + n : z); };
+    auto zwrap = [&gmap](int z) { return gmap(z); };
+    auto zzero = [n, bc](int z) { return bc == 1 && (z < 0 || z >= n); };
     auto own_index = [&](int z, int k) {
         return (size_t)z * nn + (size_t)(y0 + ly0 + k * RPT) * n + (size_t)(x0 + lx);
     };
@@ -138,28 +149,33 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
         for (int j = 0; j < NE; ++j)
             if (tid + j * kNT < PLANE) fin[j] = op.fetch(zo + eoff[j]);
     };
-    auto commit_plane = [&](T* dst, int gz, bool ownz) {
-        const size_t zo = (size_t)gz * nn;
+    // zr: the plane's coordinate before the boundary rule
+    auto commit_plane = [&](T* dst, int zr, bool ownz) {
+        const size_t zo = (size_t)zwrap(zr) * nn;
+        const uint32_t zmask = zzero(zr) ? ~0u : ezero;
 #pragma unroll
         for (int j = 0; j < NE; ++j) {
             const int e = tid + j * kNT;
-            if (e < PLANE) dst[e] = op.make(fin[j], zo + eoff[j], ownz && ((eown >> j) & 1u));
+            if (e < PLANE)
+                dst[e] = ((zmask >> j) & 1u) ? T(0)
+                                             : op.make(fin[j], zo + eoff[j], ownz && ((eown >> j) & 1u));
         }
     };
 
     // prologue: z-1 values of the own points, planes z0 and z0+1, prefetches
     {
         const int zb = zwrap(z0 - 1);
+        const bool zero = zzero(z0 - 1);
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
             const size_t gi = own_index(zb, k);
-            zm[k] = op.make(op.fetch(gi), gi, false);
+            zm[k] = zero ? T(0) : op.make(op.fetch(gi), gi, false);
         }
     }
     fetch_plane(z0);
     commit_plane(buf[0], z0, true);
     fetch_plane(zwrap(z0 + 1));
-    commit_plane(buf[1], zwrap(z0 + 1), zc > 1);
+    commit_plane(buf[1], z0 + 1, zc > 1);
     if (zc >= 2) fetch_plane(zwrap(z0 + 2));
 #pragma unroll
     for (int k = 0; k < PPT; ++k) fown[k] = op.pre(own_index(z0, k));
@@ -183,7 +199,7 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
             for (int k = 0; k < PPT; ++k) fown[k] = op.pre(own_index(z + 1, k));
         }
         __syncthreads();
-        if (i + 2 <= zc) commit_plane(buf[cur], zwrap(z + 2), i + 2 < zc);
+        if (i + 2 <= zc) commit_plane(buf[cur], z + 2, i + 2 < zc);
         if (i + 3 <= zc) fetch_plane(zwrap(z + 3));
         __syncthreads();
         cur ^= 1;
@@ -533,7 +549,8 @@ constexpr int ssor_level_off(int K, int TX, int TY, int l) {
 }
 
 template <int K, int DIR, int TX, int TY>
-__global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int nbx, int nby, int zlen,
+__global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int bounded, int nbx, int nby,
+                                                         int zlen,
                                                          const double* __restrict__ src,
                                                          const double* add,  // may be dst
                                                          const double* __restrict__ rdot,
@@ -560,21 +577,28 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int nbx, int nby
     const int nsteps = zlen + K;
     int cur = 0;
     __syncthreads();
+    // a bounded box has no neighbour across a face: every level is zero
+    // outside the grid (the load uses the clamped index, always in bounds)
+    auto outside = [n](int v) { return v < 0 || v >= n; };
+    auto gmap = [n, bounded](int v) {
+        if (v >= 0 && v < n) return v;
+        if (!bounded) return v < 0 ? v + n : v - n;
+        return v < 0 ? 0 : n - 1;
+    };
     for (int t = 0; t <= nsteps; ++t) {
         // prefetch level 0 of step t (plane sequence: DIR 0 upward from
         // z0 - K, DIR 1 downward from z1 - 1 + K), then finish step t - 1
         if (t < nsteps) {
-            int zf = DIR == 0 ? z0 - K + t : z1 - 1 + K - t;
-            zf = zf < 0 ? zf + n : (zf >= n ? zf - n : zf);
-            const size_t zo = (size_t)zf * nn;
+            const int zr = DIR == 0 ? z0 - K + t : z1 - 1 + K - t;
+            const bool zout = bounded && outside(zr);
+            const size_t zo = (size_t)gmap(zr) * nn;
 #pragma unroll
             for (int k = 0; k < NP0; ++k) {
                 const int e = tid + k * kNT;
                 if (e < W0 * H0) {
-                    int gx = ax + e % W0, gy = ay + e / W0;
-                    gx = gx < 0 ? gx + n : (gx >= n ? gx - n : gx);
-                    gy = gy < 0 ? gy + n : (gy >= n ? gy - n : gy);
-                    stg[k] = src[zo + (size_t)gy * n + gx];
+                    const int rx = ax + e % W0, ry = ay + e / W0;
+                    const double v = src[zo + (size_t)gmap(ry) * n + gmap(rx)];
+                    stg[k] = (zout || (bounded && (outside(rx) || outside(ry)))) ? 0.0 : v;
                 }
             }
         }
@@ -582,6 +606,7 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int nbx, int nby
             const int tp = t - 1;
             const int z = DIR == 0 ? z0 - K + tp : z1 - 1 + K - tp;
             const bool out_plane = DIR == 0 ? (z >= z0) : (z < z1);
+            const bool zout = bounded && outside(z);
             const double* B = lds + cur * W0 * H0;  // level 0, this plane
             for (int l = 1; l <= K; ++l) {
                 const int Wp = TX + K - l + 1, Hp = TY + K - l + 1;
@@ -596,8 +621,12 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int nbx, int nby
                     const int pi = (ly + o1) * Wp + (lx + o1);
                     const double sn = DIR == 0 ? (P[pi - 1] + P[pi - Wp]) + Pz[pi]
                                                : (P[pi + 1] + P[pi + Wp]) + Pz[pi];
-                    const double v = B[(ly + ol) * W0 + (lx + ol)] + c * sn;
+                    double v = B[(ly + ol) * W0 + (lx + ol)] + c * sn;
                     if (l < K) {
+                        // level l's region starts K - l points upwind of the tile
+                        const int rx = DIR == 0 ? x0 - (K - l) + lx : x0 + lx;
+                        const int ry = DIR == 0 ? y0 - (K - l) + ly : y0 + ly;
+                        if (bounded && (zout || outside(rx) || outside(ry))) v = 0.0;
                         Q[e] = v;
                     } else if (out_plane) {
                         const size_t g = (size_t)z * nn + (size_t)(y0 + ly) * n + (x0 + lx);
@@ -642,10 +671,11 @@ struct OpField {
     double* ey;
     double* ez;
     double ehalf, h3, mean;
+    int gauge;  // 0: phi as it is (Dirichlet box)
     DevState* st;
     double* part;
     __device__ bool active() const { return true; }
-    __device__ void prepare() { mean = st->mean; }
+    __device__ void prepare() { mean = gauge ? st->mean : 0.0; }
     __device__ double fetch(size_t g) const { return phi[g]; }
     __device__ double make(double v, size_t, bool) const { return v - mean; }
     __device__ Nothing pre(size_t) const { return Nothing{}; }
@@ -759,10 +789,10 @@ __global__ __launch_bounds__(kNT) void fill_kernel(int64_t n, double* __restrict
 
 // --------------------------------------------------------------------------
 // Host side.
-SweepGeo make_geo(int n) {
+SweepGeo make_geo(int n, int bc) {
     SweepGeo g;
     g.n = n;
-    g.zc = 0;
+    g.bc = bc;
     g.nbx = g.nby = g.nbz = g.nb = 0;
     return g;
 }
@@ -799,7 +829,6 @@ static hipError_t launch_sweep_tx(const Op& op, const SweepGeo& gin, hipStream_t
     if (nbz < 1) nbz = 1;
     g.nbz = nbz;
     g.nb = tiles * nbz;
-    g.zc = 0;
     hipLaunchKernelGGL((sweep_kernel<Op, TX>), dim3(g.nb), dim3(kNT), 0, s, op, g);
     return hipGetLastError();
 }
@@ -866,9 +895,10 @@ static int stream_blocks(int64_t n);
 
 hipError_t launch_field(const SweepGeo& g, double* phi, double* ex, double* ey, double* ez,
                         double ehalf, double h3, DevState* st, double* partials, hipStream_t s) {
-    OpField op{phi, ex, ey, ez, ehalf, h3, 0.0, st, partials};
+    const int gauge = g.bc != 1;
+    OpField op{phi, ex, ey, ez, ehalf, h3, 0.0, gauge, st, partials};
     hipError_t e = launch_sweep(op, g, s);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !gauge) return e;
     const int64_t n3 = (int64_t)g.n * g.n * g.n;
     hipLaunchKernelGGL(shift_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, phi,
                        (const DevState*)st);
@@ -983,7 +1013,7 @@ hipError_t launch_aq(const SweepGeo& g, const double* p, double* q, double inv_h
 // Fused SSOR solve launcher: K = inner steps (2..8 instantiated), 64 x 8
 // tiles (32 x 8 when n is not a multiple of 64), z split to about 4096 blocks.
 template <int K, int DIR, int TX>
-static hipError_t ssor_fused_t(int n, const double* src, const double* add, const double* rdot,
+static hipError_t ssor_fused_t(int n, int bounded, const double* src, const double* add, const double* rdot,
                                double* dst, double s0, double c, double oscale, DevState* st,
                                double* partials, hipStream_t s) {
     constexpr int TY = 8;
@@ -993,29 +1023,34 @@ static hipError_t ssor_fused_t(int n, const double* src, const double* add, cons
         if (n % z == 0 && (int64_t)nbx * nby * z <= 4096) nbz = z;
     const int nb = nbx * nby * nbz;
     if (nb > kMaxSweepBlocks) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((ssor_fused_kernel<K, DIR, TX, TY>), dim3(nb), dim3(kNT), 0, s, n, nbx, nby,
-                       n / nbz, src, add, rdot, dst, s0, c, oscale, st, partials);
+    hipLaunchKernelGGL((ssor_fused_kernel<K, DIR, TX, TY>), dim3(nb), dim3(kNT), 0, s, n, bounded,
+                       nbx, nby, n / nbz, src, add, rdot, dst, s0, c, oscale, st, partials);
     return hipGetLastError();
 }
 
 template <int K, int DIR>
-static hipError_t ssor_fused_k(int n, const double* src, const double* add, const double* rdot,
-                               double* dst, double s0, double c, double oscale, DevState* st,
-                               double* partials, hipStream_t s) {
+static hipError_t ssor_fused_k(int n, int bounded, const double* src, const double* add,
+                               const double* rdot, double* dst, double s0, double c, double oscale,
+                               DevState* st, double* partials, hipStream_t s) {
     if (n % 64 == 0)
-        return ssor_fused_t<K, DIR, 64>(n, src, add, rdot, dst, s0, c, oscale, st, partials, s);
-    return ssor_fused_t<K, DIR, 32>(n, src, add, rdot, dst, s0, c, oscale, st, partials, s);
+        return ssor_fused_t<K, DIR, 64>(n, bounded, src, add, rdot, dst, s0, c, oscale, st,
+                                        partials, s);
+    return ssor_fused_t<K, DIR, 32>(n, bounded, src, add, rdot, dst, s0, c, oscale, st, partials,
+                                    s);
 }
 
 bool ssor_fused_supported(int n, int inner) { return n % 32 == 0 && inner >= 1 && inner <= 4; }
 
-hipError_t launch_ssor_fused(int n, int inner, int dir, const double* src, const double* add,
-                             const double* rdot, double* dst, double s0, double c, double oscale,
-                             DevState* st, double* partials, hipStream_t s) {
-#define SF(KK)                                                                                   \
-    if (inner == KK)                                                                             \
-        return dir == 0 ? ssor_fused_k<KK, 0>(n, src, add, rdot, dst, s0, c, oscale, st, partials, s) \
-                        : ssor_fused_k<KK, 1>(n, src, add, rdot, dst, s0, c, oscale, st, partials, s)
+hipError_t launch_ssor_fused(int n, int bounded, int inner, int dir, const double* src,
+                             const double* add, const double* rdot, double* dst, double s0,
+                             double c, double oscale, DevState* st, double* partials,
+                             hipStream_t s) {
+#define SF(KK)                                                                                  \
+    if (inner == KK)                                                                            \
+        return dir == 0 ? ssor_fused_k<KK, 0>(n, bounded, src, add, rdot, dst, s0, c, oscale, st, \
+                                              partials, s)                                      \
+                        : ssor_fused_k<KK, 1>(n, bounded, src, add, rdot, dst, s0, c, oscale, st, \
+                                              partials, s)
     SF(1);
     SF(2);
     SF(3);

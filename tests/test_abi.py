@@ -50,12 +50,16 @@ def test_abi_version_and_errors_without_gpu(lib):
     h = ctypes.c_void_p()
     for field, bad in (("n", 33), ("n", 16), ("n", 2048), ("rtol", 0.0), ("length", -1.0),
                        ("solver", 7), ("np_max", -5), ("flags", 64),
-                       ("ssor_omega", 2.5), ("ssor_inner", -1)):
+                       ("ssor_omega", 2.5), ("ssor_inner", -1), ("bc", 3), ("bc", -1)):
         q = P.landau_params(32, 8)
         setattr(q, field, bad)
         assert lib.pic_workspace_bytes(ctypes.byref(q)) == 0
         assert lib.pic_create(ctypes.byref(q), ctypes.byref(h)) == P.PIC_ERR_INVALID
         assert lib.pic_last_error()
+    # bounded boxes take only the stencil solver forms
+    for bc, solver in ((P.BC_DIRICHLET, "fft"), (P.BC_NEUMANN, "fcg_learned")):
+        q = P.landau_params(32, 8, solver=solver, bc=bc)
+        assert lib.pic_create(ctypes.byref(q), ctypes.byref(h)) == P.PIC_ERR_INVALID
     assert lib.pic_create(None, ctypes.byref(h)) == P.PIC_ERR_INVALID
     assert lib.pic_destroy(None) == 0
     # the entry points reject a NULL context instead of crashing
