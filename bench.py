@@ -33,7 +33,8 @@ PEAK_HBM_GBS = 8000.0
 # direction sweep reads r, p_old and writes p_new; update sweep reads p, x, r
 # and writes x, r.  (FP32 inner sweeps of the mixed form: half.)
 SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 40),
-               "pcg_ssor": (24, 40), "fft": (24, 40)}
+               "pcg_ssor": (24, 40), "fft": (24, 40),
+               "pif": (24, 40)}
 # HBM bytes per launch of the FP64 update sweep at 512^3, from rocprofv3
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.

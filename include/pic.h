@@ -54,10 +54,14 @@ enum {
     PIC_SOLVER_FCG_LEARNED = 2, /* flexible PCG, U-Net warm start/precond.     */
     PIC_SOLVER_PCG_SSOR = 3,    /* FP64 PCG with the SSOR preconditioner of the
                                    paper's runs (Sec. 4.1), see ssor_* below  */
-    PIC_SOLVER_FFT = 4          /* FFT solve (the paper's comparison solver,
+    PIC_SOLVER_FFT = 4,         /* FFT solve (the paper's comparison solver,
                                    Sec. 3.1): the 7-point operator's
                                    eigenvalues, or with PIC_FLAG_FFT_SPECTRAL
                                    the pseudo-spectral 1/|k|^2 and E = -ik phi */
+    PIC_SOLVER_PIF = 5          /* Particle-in-Fourier (Sec. 3.4): no grid
+                                   solve; pic_init/pic_step and pic_pif_field
+                                   (below) couple the particles to N^3 Fourier
+                                   modes by NUFFTs */
 };
 
 /* pic_params.bc: boundary kind of the box (Sec. 3.2: the PCG solver takes
@@ -130,6 +134,8 @@ typedef struct pic_params {
     int32_t ssor_inner;   /* Jacobi steps per triangular solve (>= 1)        */
     int32_t ssor_outer;   /* stationary SSOR steps per application (>= 1)    */
     int32_t bc;           /* PIC_BC_* (above); 0 = the periodic box          */
+    double pif_tol;       /* PIF form: NUFFT tolerance in [1e-7, 1e-2]
+                             (0: 1e-4, the paper's, Sec. 4)                 */
 } pic_params;
 
 /* Host-side result of one Poisson solve. */
@@ -256,9 +262,28 @@ int pic_init(pic_ctx *ctx, pic_particles *parts, pic_fields *fields,
 
 /* One PIC step (Fig. pic-loop): gather+push -> stable cell sort (cur -> alt,
  * swapped) -> deposit -> solve (warm start from fields->phi) -> field.
- * info: host out (nullable; when set, per-phase event times are recorded). */
+ * info: host out (nullable; when set, per-phase event times are recorded).
+ * With PIC_SOLVER_PIF the step is push (field of the previous step's modes,
+ * evaluated by the type-2 NUFFT) -> sort -> spread -> transforms and the
+ * mode-wise solve; the grid fields in `fields` are not used and W_x comes
+ * from the modes (Parseval). */
 int pic_step(pic_ctx *ctx, pic_particles *parts, pic_fields *fields,
              pic_step_info *info, void *stream);
+
+/* Particle-in-Fourier field at the particles (Sec. 3.4; NUFFT appendix):
+ *   rho_hat(k) = sum_j q exp(-i k.x_j)        (type-1 NUFFT, q = charge)
+ *   E_hat(k)   = -i k rho_hat(k) / |k|^2      (k = 0 dropped)
+ *   E(x_j)     = Re (1/L^3) sum_k E_hat(k) exp(i k.x_j)   (type-2 NUFFT)
+ * over k in (2 pi / L) {-N/2 .. N/2-1}^3, to the tolerance pic_params.pif_tol
+ * (window: exponential of semicircle, width ceil(log10(1/tol)) + 1, on a
+ * 2N-per-axis oversampled grid).  The particles must be cell-sorted with
+ * cell_start from pic_sort_cells; ex, ey, ez (np each) receive E at them;
+ * wx (host out, nullable) = (1/2) int Ex^2.  The context's solver must be
+ * PIC_SOLVER_PIF (N <= 512).  The spread sums with FP64 atomics (summation
+ * order not deterministic). */
+int pic_pif_field(pic_ctx *ctx, int64_t np, const double *x, const double *y,
+                  const double *z, const uint32_t *cell_start, double *ex, double *ey,
+                  double *ez, double *wx, void *stream);
 
 /* Average duration (ms) of the most recent solve's dominant kernel launches,
  * measured with HIP events on the solve's stream when timing is enabled by

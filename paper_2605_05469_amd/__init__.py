@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_NOT_CONVERGED = 0, 1
 PIC_ERR_INVALID, PIC_ERR_HIP, PIC_ERR_NOMEM, PIC_ERR_STATE = -1, -2, -3, -4
-SOLVERS = {"pcg_fp64": 0, "pcg_mixed": 1, "fcg_learned": 2, "pcg_ssor": 3, "fft": 4}
+SOLVERS = {"pcg_fp64": 0, "pcg_mixed": 1, "fcg_learned": 2, "pcg_ssor": 3, "fft": 4, "pif": 5}
 FLAG_NO_WARM_START = 1
 FLAG_WARM_START_ONLY = 2
 FLAG_MIXED_RELIABLE = 4
@@ -45,7 +45,7 @@ class pic_params(ctypes.Structure):
                 ("max_outer", ctypes.c_int64), ("fcg_window", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("ssor_omega", ctypes.c_double),
                 ("ssor_inner", ctypes.c_int32), ("ssor_outer", ctypes.c_int32),
-                ("bc", ctypes.c_int32)]
+                ("bc", ctypes.c_int32), ("pif_tol", ctypes.c_double)]
 
 
 class pic_solve_info(ctypes.Structure):
@@ -96,7 +96,8 @@ EXPORTS = ["pic_create", "pic_destroy", "pic_workspace_bytes", "pic_last_error",
            "pic_net_destroy", "pic_net_set_params", "pic_net_get_params", "pic_net_forward",
            "pic_net_backward", "pic_net_train_step", "pic_net_precondition",
            "pic_conv3d_frag_elems", "pic_conv3d_pack", "pic_conv3d_fwd", "pic_conv3d_bwd_data",
-           "pic_conv3d_wgrad_scratch_elems", "pic_conv3d_bwd_weight", "pic_adam_step"]
+           "pic_conv3d_wgrad_scratch_elems", "pic_conv3d_bwd_weight", "pic_adam_step",
+           "pic_pif_field"]
 
 
 def lib():
@@ -125,6 +126,7 @@ def lib():
     L.pic_gather_push.argtypes = [vp, i64] + [vp] * 10 + [vp]
     L.pic_half_kick.argtypes = [vp, i64] + [vp] * 9 + [vp]
     L.pic_efield.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]
+    L.pic_pif_field.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]
     L.pic_init.argtypes = [vp, ctypes.POINTER(pic_particles), ctypes.POINTER(pic_fields),
                            ctypes.POINTER(pic_step_info), vp]
     L.pic_step.argtypes = L.pic_init.argtypes
@@ -182,7 +184,7 @@ def _stream(stream=None):
 def landau_params(N, ppc, k=0.5, dt=0.05, qm=-1.0, rtol=1e-10, max_iter=20000,
                   solver="pcg_fp64", np_max=None, check_every=16, inner_rtol=1e-3,
                   max_inner=20000, max_outer=50, fcg_window=10, ssor_omega=math.pi / 2,
-                  ssor_inner=4, ssor_outer=2, flags=0, bc=BC_PERIODIC):
+                  ssor_inner=4, ssor_outer=2, flags=0, bc=BC_PERIODIC, pif_tol=0.0):
     """Parameters of the Landau-damping box (Sec. 2.1): L = 2 pi / k, unit
     mean density, q = -L^3/Np, background +1."""
     L = 2.0 * math.pi / k
@@ -201,6 +203,7 @@ def landau_params(N, ppc, k=0.5, dt=0.05, qm=-1.0, rtol=1e-10, max_iter=20000,
     p.ssor_omega, p.ssor_inner, p.ssor_outer = ssor_omega, ssor_inner, ssor_outer
     p.flags = flags
     p.bc = bc
+    p.pif_tol = pif_tol
     return p
 
 
@@ -266,6 +269,14 @@ class Context:
         wx = ctypes.c_double(0.0)
         _check(lib().pic_efield(self._h, _ptr(phi), _ptr(ex), _ptr(ey), _ptr(ez),
                                 ctypes.byref(wx), _stream(stream)))
+        return wx.value
+
+    def pif_field(self, x, y, z, cell_start, ex, ey, ez, stream=None):
+        """PIF field at cell-sorted particles (solver "pif"); returns W_x."""
+        wx = ctypes.c_double(0.0)
+        _check(lib().pic_pif_field(self._h, 0 if x is None else x.numel(), _ptr(x), _ptr(y),
+                                   _ptr(z), _ptr(cell_start), _ptr(ex), _ptr(ey), _ptr(ez),
+                                   ctypes.byref(wx), _stream(stream)))
         return wx.value
 
     def gather_push(self, x, y, z, vx, vy, vz, ex, ey, ez, key=None, stream=None):

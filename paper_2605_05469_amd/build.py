@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic.so")
 
-SOURCES = ["stencil.hip", "particles.hip", "sort.hip", "net_kernels.hip", "net.hip", "fft.hip",
+SOURCES = ["stencil.hip", "particles.hip", "sort.hip", "net_kernels.hip", "net.hip", "fft.hip", "pif.hip",
            "capi.hip", "capi_net.hip"]
 ROCM_LIB = "/opt/rocm/lib"
 

@@ -17,6 +17,7 @@
 #include "net.hpp"
 #include "particles.hpp"
 #include "fft.hpp"
+#include "pif.hpp"
 #include "solver_state.hpp"
 
 using namespace pic;
@@ -78,6 +79,7 @@ struct pic_ctx {
     double* fw = nullptr;          //              warm-start trial / true residual
     double* sv[6] = {};            // SSOR form: z, q, two forward, one backward, r - A z
     FftPlans* fft = nullptr;       // FFT form: rocFFT plans
+    PifState* pif = nullptr;       // PIF form: oversampled grids, spectra, plans
     double2* fspec[2] = {};        //           half spectra (phi_hat, a derivative)
     std::vector<void*> allocs;
     // kernel timing
@@ -102,6 +104,9 @@ static bool bounded_solver(int32_t solver) {
            solver == PIC_SOLVER_PCG_SSOR;
 }
 
+// PIF: the oversampled grid has 2n points per axis; n = 512 takes ~41 GB.
+constexpr int kPifMaxModes = 512;
+
 static int validate_params(const pic_params* p) {
     if (!p) return fail(PIC_ERR_INVALID, "params is NULL");
     if (p->n < 32 || p->n > 1024 || (p->n % 32) != 0)
@@ -112,8 +117,12 @@ static int validate_params(const pic_params* p) {
         return fail(PIC_ERR_INVALID, "np_max must be in [0, 2^32)");
     if (!(p->rtol > 0.0) || !std::isfinite(p->rtol)) return fail(PIC_ERR_INVALID, "rtol must be > 0");
     if (p->max_iter < 0) return fail(PIC_ERR_INVALID, "max_iter must be >= 0");
-    if (p->solver < PIC_SOLVER_PCG_FP64 || p->solver > PIC_SOLVER_FFT)
+    if (p->solver < PIC_SOLVER_PCG_FP64 || p->solver > PIC_SOLVER_PIF)
         return fail(PIC_ERR_INVALID, "unknown solver %d", p->solver);
+    if (p->pif_tol != 0.0 && pif_width(p->pif_tol) == 0)
+        return fail(PIC_ERR_INVALID, "pif_tol must be in [1e-7, 1e-2] (0: default 1e-4)");
+    if (p->solver == PIC_SOLVER_PIF && p->n > kPifMaxModes)
+        return fail(PIC_ERR_INVALID, "PIF: at most %d modes per axis", kPifMaxModes);
     if (!(p->ssor_omega >= 0.0 && p->ssor_omega < 2.0) || p->ssor_inner < 0 || p->ssor_outer < 0)
         return fail(PIC_ERR_INVALID, "ssor_omega must be in (0, 2) (0: default), "
                                      "ssor_inner and ssor_outer >= 0 (0: default)");
@@ -206,6 +215,17 @@ static int ensure_ssor(pic_ctx* c) {
 static size_t fft_bytes(const pic_params* p) {
     const int64_t nspec = (int64_t)(p->n / 2 + 1) * p->n * p->n;
     return 2 * vec_bytes(nspec, 16);
+}
+
+// PIF form: oversampled grids, spectra and plans of its own (pif.hip).
+static int ensure_pif(pic_ctx* c) {
+    if (c->pif) return PIC_OK;
+    const int rc = pif_create(&c->pif, c->p.n, c->L, c->p.pif_tol);
+    if (rc) {
+        c->pif = nullptr;
+        return fail(rc == -3 ? PIC_ERR_NOMEM : PIC_ERR_HIP, "PIF buffers: %s", pif_last_error());
+    }
+    return PIC_OK;
 }
 
 static int ensure_fft(pic_ctx* c) {
@@ -801,6 +821,7 @@ size_t pic_workspace_bytes(const pic_params* p) {
     if (p->solver == PIC_SOLVER_FCG_LEARNED) b += learned_bytes(p);
     if (p->solver == PIC_SOLVER_PCG_SSOR) b += ssor_bytes(p);
     if (p->solver == PIC_SOLVER_FFT) b += fft_bytes(p);
+    if (p->solver == PIC_SOLVER_PIF) b += pif_bytes(p->n);
     return b;
 }
 
@@ -820,6 +841,7 @@ int pic_create(const pic_params* params, pic_ctx** out) {
     if (c->p.ssor_omega == 0.0) c->p.ssor_omega = 1.5707963267948966;  // pi / 2
     if (c->p.ssor_inner == 0) c->p.ssor_inner = 4;
     if (c->p.ssor_outer == 0) c->p.ssor_outer = 2;
+    if (c->p.pif_tol == 0.0) c->p.pif_tol = 1e-4;  // the paper's NUFFT tolerance (Sec. 4)
     const int n = c->p.n;
     c->n3 = (int64_t)n * n * n;
     const int bc = c->p.bc;
@@ -880,6 +902,7 @@ int pic_create(const pic_params* params, pic_ctx** out) {
         if (c->p.solver == PIC_SOLVER_FCG_LEARNED && (rc = ensure_learned(c)) != PIC_OK) break;
         if (c->p.solver == PIC_SOLVER_PCG_SSOR && (rc = ensure_ssor(c)) != PIC_OK) break;
         if (c->p.solver == PIC_SOLVER_FFT && (rc = ensure_fft(c)) != PIC_OK) break;
+        if (c->p.solver == PIC_SOLVER_PIF && (rc = ensure_pif(c)) != PIC_OK) break;
     } while (0);
     if (rc != PIC_OK) {
         std::string keep = g_err;
@@ -899,18 +922,22 @@ int pic_destroy(pic_ctx* c) {
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->net) net::destroy(c->net);
     if (c->fft) fft_destroy(c->fft);
+    if (c->pif) pif_destroy(c->pif);
     delete c;
     return PIC_OK;
 }
 
 int pic_set_solver(pic_ctx* c, int32_t solver) {
     if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
-    if (solver < PIC_SOLVER_PCG_FP64 || solver > PIC_SOLVER_FFT)
+    if (solver < PIC_SOLVER_PCG_FP64 || solver > PIC_SOLVER_PIF)
         return fail(PIC_ERR_INVALID, "unknown solver %d", solver);
+    if (solver == PIC_SOLVER_PIF && c->p.n > kPifMaxModes)
+        return fail(PIC_ERR_INVALID, "PIF: at most %d modes per axis", kPifMaxModes);
     if (c->p.bc != PIC_BC_PERIODIC && !bounded_solver(solver))
         return fail(PIC_ERR_INVALID, "solver %d needs the periodic box", solver);
     if (solver == PIC_SOLVER_PCG_SSOR) RETCHK(ensure_ssor(c));
     if (solver == PIC_SOLVER_FFT) RETCHK(ensure_fft(c));
+    if (solver == PIC_SOLVER_PIF) RETCHK(ensure_pif(c));
     if (solver == PIC_SOLVER_PCG_MIXED) RETCHK(ensure_mixed(c));
     if (solver == PIC_SOLVER_FCG_LEARNED) RETCHK(ensure_learned(c));
     c->p.solver = solver;
@@ -1033,6 +1060,8 @@ int pic_poisson_pcg(pic_ctx* c, const double* rho, double* phi, double* ex, doub
     std::memset(&si, 0, sizeof si);
     if (c->timing) timing_reset(c);
     bool e_done = false;
+    if (c->p.solver == PIC_SOLVER_PIF)
+        return fail(PIC_ERR_INVALID, "the PIF form has no grid solve (pic_pif_field, pic_step)");
     switch (c->p.solver) {
         case PIC_SOLVER_PCG_FP64: RETCHK(solve_fp64(c, rho, phi, &si, s)); break;
         case PIC_SOLVER_PCG_MIXED: RETCHK(solve_mixed(c, rho, phi, &si, s)); break;
@@ -1051,6 +1080,32 @@ int pic_poisson_pcg(pic_ctx* c, const double* rho, double* phi, double* ex, doub
     }
     if (info) *info = si;
     return si.converged ? PIC_OK : PIC_NOT_CONVERGED;
+}
+
+int pic_pif_field(pic_ctx* c, int64_t np, const double* x, const double* y, const double* z,
+                  const uint32_t* cell_start, double* ex, double* ey, double* ez, double* wx,
+                  void* stream) {
+    RETCHK(check_np(c, np));
+    RETCHK(check_periodic(c));
+    if (c->p.solver != PIC_SOLVER_PIF) return fail(PIC_ERR_INVALID, "solver is not PIF");
+    NEED(cell_start, "cell_start");
+    if (np > 0) {
+        NEED(x, "x"); NEED(y, "y"); NEED(z, "z"); NEED(ex, "ex"); NEED(ey, "ey"); NEED(ez, "ez");
+    }
+    RETCHK(ensure_pif(c));
+    hipStream_t s = (hipStream_t)stream;
+    if (pif_spread(c->pif, np, x, y, z, cell_start, c->p.charge, s) ||
+        pif_fields(c->pif, c->st, c->partials, s))
+        return fail(PIC_ERR_HIP, "PIF field: %s", pif_last_error());
+    if (pif_interp(c->pif, 0, np, const_cast<double*>(x), const_cast<double*>(y),
+                   const_cast<double*>(z), nullptr, nullptr, nullptr, ex, ey, ez, nullptr,
+                   cell_start, 0.0, 0.0, s))
+        return fail(PIC_ERR_HIP, "PIF field: %s", pif_last_error());
+    if (wx) {
+        RETCHK(read_state(c, s));
+        *wx = c->st_host->wx;
+    }
+    return PIC_OK;
 }
 
 int pic_set_unet(pic_ctx* c, const float* params, void* stream) {
@@ -1152,11 +1207,44 @@ struct PhaseTimer {
     }
 };
 
+// The PIF form's field: spread of the sorted particles, transforms and the
+// mode-wise solve (the field grids stay in the PIF state for the next push).
+static int pif_field_phase(pic_ctx* c, pic_particles* P, hipStream_t s, bool spread) {
+    if (spread && pif_spread(c->pif, P->np, P->cur.x, P->cur.y, P->cur.z, P->cell_start,
+                             c->p.charge, s))
+        return fail(PIC_ERR_HIP, "PIF spread: %s", pif_last_error());
+    if (!spread && pif_fields(c->pif, c->st, c->partials, s))
+        return fail(PIC_ERR_HIP, "PIF field: %s", pif_last_error());
+    return PIC_OK;
+}
+
+static int pif_info(pic_ctx* c, hipStream_t s, pic_solve_info* si) {
+    std::memset(si, 0, sizeof *si);
+    RETCHK(read_state(c, s));
+    si->wx = c->st_host->wx;
+    si->converged = 1;
+    return PIC_OK;
+}
+
 int pic_init(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, void* stream) {
     RETCHK(check_parts(c, P, F));
     hipStream_t s = (hipStream_t)stream;
     if (P->np > 0) HIPCHK(launch_keys(P->np, P->cur.x, P->cur.y, P->cur.z, P->key, c->p.n, c->inv_h, s));
     RETCHK(sort_swap(c, P, s));
+    if (c->p.solver == PIC_SOLVER_PIF) {
+        RETCHK(ensure_pif(c));
+        RETCHK(pif_field_phase(c, P, s, true));
+        RETCHK(pif_field_phase(c, P, s, false));
+        if (pif_interp(c->pif, 2, P->np, P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy,
+                       P->cur.vz, nullptr, nullptr, nullptr, nullptr, P->cell_start, c->coef_kick,
+                       0.0, s))
+            return fail(PIC_ERR_HIP, "PIF half kick: %s", pif_last_error());
+        if (info) {
+            std::memset(info, 0, sizeof *info);
+            RETCHK(pif_info(c, s, &info->solve));
+        }
+        return PIC_OK;
+    }
     HIPCHK(launch_deposit(P->np, P->cur.x, P->cur.y, P->cur.z, P->np > 0 ? P->cell_start : nullptr,
                           F->rho, c->p.n, c->inv_h, c->qh3, c->p.rho_bg, c->st, c->partials, dep_scratch(c), s));
     pic_solve_info si;
@@ -1178,6 +1266,31 @@ int pic_step(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, v
     PhaseTimer T;
     RETCHK(T.init(info != nullptr));
     RETCHK(T.mark(0, s));
+    if (c->p.solver == PIC_SOLVER_PIF) {
+        // push with the field of the previous solve, sort, spread, solve
+        RETCHK(ensure_pif(c));
+        if (pif_interp(c->pif, 1, P->np, P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy,
+                       P->cur.vz, nullptr, nullptr, nullptr, P->key, P->cell_start, c->coef_push,
+                       c->p.dt, s))
+            return fail(PIC_ERR_HIP, "PIF push: %s", pif_last_error());
+        RETCHK(T.mark(1, s));
+        RETCHK(sort_swap(c, P, s));
+        RETCHK(T.mark(2, s));
+        RETCHK(pif_field_phase(c, P, s, true));
+        RETCHK(T.mark(3, s));
+        RETCHK(pif_field_phase(c, P, s, false));
+        RETCHK(T.mark(4, s));
+        RETCHK(T.mark(5, s));
+        if (info) {
+            RETCHK(pif_info(c, s, &info->solve));
+            info->ms_push = T.ms(0, 1);
+            info->ms_sort = T.ms(1, 2);
+            info->ms_deposit = T.ms(2, 3);
+            info->ms_solve = T.ms(3, 4);
+            info->ms_field = T.ms(4, 5);
+        }
+        return PIC_OK;
+    }
     HIPCHK(launch_gather_push(P->np, P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy, P->cur.vz,
                               F->ex, F->ey, F->ez, P->key, c->p.n, c->inv_h, c->L, c->p.dt,
                               c->coef_push, s));

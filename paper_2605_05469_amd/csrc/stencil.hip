@@ -76,7 +76,7 @@ constexpr int kMaxSweepBlocks = 8192;
 //            double (&acc)[NACC]) const;
 //   void finish(double (&tot)[NACC]) const;           // thread 0 of last block
 //   uint32_t* ticket() const;  double* partials() const;
-template <class Op, int TX>
+template <class Op, int TX, int BC>
 __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
     using T = typename Op::T;
     using In = typename Op::In;
@@ -111,8 +111,8 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
     const int lx = tid % TX, ly0 = tid / TX;
 
     // in-plane offsets of this thread's staged entries (fixed for the block)
-    const int bc = g.bc;
-    auto gmap = [n, bc](int v) {
+    constexpr int bc = BC;  // g.bc, fixed at compile time
+    auto gmap = [n](int v) {
         if (v >= 0 && v < n) return v;
         if (bc == 0) return v < 0 ? v + n : v - n;
         return v < 0 ? 0 : n - 1;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
         if (bc == 1 && (rx != gx || ry != gy)) ezero |= 1u << j;
     }
     auto zwrap = [&gmap](int z) { return gmap(z); };
-    auto zzero = [n, bc](int z) { return bc == 1 && (z < 0 || z >= n); };
+    auto zzero = [n](int z) { return bc == 1 && (z < 0 || z >= n); };
     auto own_index = [&](int z, int k) {
         return (size_t)z * nn + (size_t)(y0 + ly0 + k * RPT) * n + (size_t)(x0 + lx);
     };
@@ -802,12 +802,12 @@ int max_sweep_blocks() { return kMaxSweepBlocks; }
 // Launch one wave of resident workgroups: every (x, y) tile column gets the
 // same number of blocks (nbz), each marching an equal share of the z planes,
 // so all blocks finish together and the z-halo overhead is 2 planes per share.
-template <class Op, int TX>
+template <class Op, int TX, int BC>
 static hipError_t launch_sweep_tx(const Op& op, const SweepGeo& gin, hipStream_t s) {
     static int occ = 0, cus = 0;
     if (occ == 0) {
         int o = 0, c = 0, dev = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sweep_kernel<Op, TX>, kNT, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sweep_kernel<Op, TX, BC>, kNT, 0) !=
                 hipSuccess || o < 1)
             o = 1;
         (void)hipGetDevice(&dev);
@@ -829,14 +829,21 @@ static hipError_t launch_sweep_tx(const Op& op, const SweepGeo& gin, hipStream_t
     if (nbz < 1) nbz = 1;
     g.nbz = nbz;
     g.nb = tiles * nbz;
-    hipLaunchKernelGGL((sweep_kernel<Op, TX>), dim3(g.nb), dim3(kNT), 0, s, op, g);
+    hipLaunchKernelGGL((sweep_kernel<Op, TX, BC>), dim3(g.nb), dim3(kNT), 0, s, op, g);
     return hipGetLastError();
+}
+
+template <class Op, int BC>
+static hipError_t launch_sweep_bc(const Op& op, const SweepGeo& g, hipStream_t s) {
+    if (g.n % 64 == 0) return launch_sweep_tx<Op, 64, BC>(op, g, s);
+    return launch_sweep_tx<Op, 32, BC>(op, g, s);
 }
 
 template <class Op>
 static hipError_t launch_sweep(const Op& op, const SweepGeo& g, hipStream_t s) {
-    if (g.n % 64 == 0) return launch_sweep_tx<Op, 64>(op, g, s);
-    return launch_sweep_tx<Op, 32>(op, g, s);
+    if (g.bc == 1) return launch_sweep_bc<Op, 1>(op, g, s);
+    if (g.bc == 2) return launch_sweep_bc<Op, 2>(op, g, s);
+    return launch_sweep_bc<Op, 0>(op, g, s);
 }
 
 hipError_t launch_residual64(const SweepGeo& g, const double* b, const double* x, double* r,
