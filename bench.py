@@ -38,7 +38,7 @@ SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 
 # HBM bytes per launch of the FP64 update sweep at 512^3, from rocprofv3
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
-UPDATE_SWEEP_TRAFFIC = {(512, "pcg_fp64"): 5.612e9}
+UPDATE_SWEEP_TRAFFIC = {(512, "pcg_fp64"): 5.571e9}
 
 
 def log(*a):
