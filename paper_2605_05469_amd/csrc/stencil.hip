@@ -540,8 +540,6 @@ struct OpSsorHalf {
 // planes early, after which every level is valid.  The arithmetic and its
 // order are those of K separate half-sweeps (identical results); the bytes
 // moved are one read of src (with a K-point halo) and one write per point.
-// LDS doubles before level l (two planes per level, level j covering
-// (TX + K - j) x (TY + K - j) points).
 constexpr int ssor_level_off(int K, int TX, int TY, int l) {
     int o = 0;
     for (int j = 0; j < l; ++j) o += 2 * (TX + K - j) * (TY + K - j);
@@ -558,11 +556,14 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int bounded, int
                                                          double c, double oscale, DevState* st,
                                                          double* part) {
     constexpr int W0 = TX + K, H0 = TY + K;
+    constexpr int RT = kNT / TX;  // thread rows
+    static_assert(K < TX, "a level's region spans at most two column passes");
     constexpr int NLDS = ssor_level_off(K, TX, TY, K);
     __shared__ double lds[NLDS];
     __shared__ double red[kNT / kWave];
     __shared__ int lflag;
     const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
     const uint32_t lb = remap_xcd(blockIdx.x, gridDim.x);
     const int bx = (int)(lb % nbx), by = (int)((lb / nbx) % nby), bz = (int)(lb / (nbx * nby));
     const int x0 = bx * TX, y0 = by * TY;
@@ -608,6 +609,7 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int bounded, int
             const bool out_plane = DIR == 0 ? (z >= z0) : (z < z1);
             const bool zout = bounded && outside(z);
             const double* B = lds + cur * W0 * H0;  // level 0, this plane
+#pragma unroll
             for (int l = 1; l <= K; ++l) {
                 const int Wp = TX + K - l + 1, Hp = TY + K - l + 1;
                 const int Wl = Wp - 1, Hl = Hp - 1;
@@ -616,24 +618,33 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int bounded, int
                 double* Q = lds + ssor_level_off(K, TX, TY, l) + cur * Wl * Hl;
                 // this level's region inside level l-1's (offset o1) and level 0's (ol)
                 const int o1 = DIR == 0 ? 1 : 0, ol = DIR == 0 ? l : 0;
-                for (int e = tid; e < Wl * Hl; e += kNT) {
-                    const int lx = e % Wl, ly = e / Wl;
-                    const int pi = (ly + o1) * Wp + (lx + o1);
-                    const double sn = DIR == 0 ? (P[pi - 1] + P[pi - Wp]) + Pz[pi]
-                                               : (P[pi + 1] + P[pi + Wp]) + Pz[pi];
-                    double v = B[(ly + ol) * W0 + (lx + ol)] + c * sn;
-                    if (l < K) {
-                        // level l's region starts K - l points upwind of the tile
-                        const int rx = DIR == 0 ? x0 - (K - l) + lx : x0 + lx;
-                        const int ry = DIR == 0 ? y0 - (K - l) + ly : y0 + ly;
-                        if (bounded && (zout || outside(rx) || outside(ry))) v = 0.0;
-                        Q[e] = v;
-                    } else if (out_plane) {
-                        const size_t g = (size_t)z * nn + (size_t)(y0 + ly) * n + (x0 + lx);
-                        double o = oscale == 1.0 ? v : oscale * v;
-                        if (add) o = o + add[g];
-                        dst[g] = o;
-                        if (rdot) acc[0] += rdot[g] * o;
+                // thread (tx, ty) takes columns tx, tx + TX and rows ty, ty + RT, ...
+#pragma unroll
+                for (int cp = 0; cp < 2; ++cp) {
+                    const int lx = tx + cp * TX;
+                    if (lx >= Wl) continue;
+#pragma unroll
+                    for (int rp = 0; rp < (TY + K + RT - 1) / RT; ++rp) {
+                        const int ly = ty + rp * RT;
+                        if (ly >= Hl) continue;
+                        const int e = ly * Wl + lx;
+                        const int pi = (ly + o1) * Wp + (lx + o1);
+                        const double sn = DIR == 0 ? (P[pi - 1] + P[pi - Wp]) + Pz[pi]
+                                                   : (P[pi + 1] + P[pi + Wp]) + Pz[pi];
+                        double v = B[(ly + ol) * W0 + (lx + ol)] + c * sn;
+                        if (l < K) {
+                            // level l's region starts K - l points upwind of the tile
+                            const int rx = DIR == 0 ? x0 - (K - l) + lx : x0 + lx;
+                            const int ry = DIR == 0 ? y0 - (K - l) + ly : y0 + ly;
+                            if (bounded && (zout || outside(rx) || outside(ry))) v = 0.0;
+                            Q[e] = v;
+                        } else if (out_plane) {
+                            const size_t g = (size_t)z * nn + (size_t)(y0 + ly) * n + (x0 + lx);
+                            double o = oscale == 1.0 ? v : oscale * v;
+                            if (add) o = o + add[g];
+                            dst[g] = o;
+                            if (rdot) acc[0] += rdot[g] * o;
+                        }
                     }
                 }
                 __syncthreads();
@@ -943,6 +954,10 @@ hipError_t launch_fill(int64_t n, double* v, double val, hipStream_t s) {
 }
 
 // ------------------------------------------------- flexible CG streams ----
+// Streaming kernels take two consecutive points per thread (16-byte loads and
+// stores) when every pointer is 16-byte aligned and n3 is even; VEC = 1 is
+// the one-point form.  Reductions sum each thread's points in index order.
+template <int VEC>
 __global__ __launch_bounds__(kNT) void fcg_update_kernel(int64_t n3, double* __restrict__ x,
                                                          double* __restrict__ r,
                                                          const double* __restrict__ p,
@@ -951,11 +966,29 @@ __global__ __launch_bounds__(kNT) void fcg_update_kernel(int64_t n3, double* __r
     __shared__ double red[kNT / kWave];
     __shared__ int lflag;
     double acc[1] = {0.0};
-    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT) {
-        x[i] = x[i] + a * p[i];
-        const double rv = r[i] - a * q[i];
-        r[i] = rv;
-        acc[0] += rv * rv;
+    if (VEC == 2) {
+        const int64_t n2 = n3 / 2;
+        for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n2;
+             i += (int64_t)gridDim.x * kNT) {
+            const double2 xv = reinterpret_cast<const double2*>(x)[i];
+            const double2 pv = reinterpret_cast<const double2*>(p)[i];
+            const double2 rv = reinterpret_cast<const double2*>(r)[i];
+            const double2 qv = reinterpret_cast<const double2*>(q)[i];
+            const double2 xn = make_double2(xv.x + a * pv.x, xv.y + a * pv.y);
+            const double2 rn = make_double2(rv.x - a * qv.x, rv.y - a * qv.y);
+            reinterpret_cast<double2*>(x)[i] = xn;
+            reinterpret_cast<double2*>(r)[i] = rn;
+            acc[0] += rn.x * rn.x;
+            acc[0] += rn.y * rn.y;
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3;
+             i += (int64_t)gridDim.x * kNT) {
+            x[i] = x[i] + a * p[i];
+            const double rv = r[i] - a * q[i];
+            r[i] = rv;
+            acc[0] += rv * rv;
+        }
     }
     block_sum<kNT, 1>(acc, red);
     if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
@@ -993,8 +1026,19 @@ __global__ __launch_bounds__(kNT) void fcg_dots_kernel(int64_t n3, const double*
     }
 }
 
+template <int VEC>
 __global__ __launch_bounds__(kNT) void xpby_kernel(int64_t n3, const double* __restrict__ z,
                                                    double* __restrict__ p, double b) {
+    if (VEC == 2) {
+        const int64_t n2 = n3 / 2;
+        for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n2;
+             i += (int64_t)gridDim.x * kNT) {
+            const double2 zv = reinterpret_cast<const double2*>(z)[i];
+            const double2 pv = reinterpret_cast<const double2*>(p)[i];
+            reinterpret_cast<double2*>(p)[i] = make_double2(zv.x + b * pv.x, zv.y + b * pv.y);
+        }
+        return;
+    }
     for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
         p[i] = z[i] + b * p[i];
 }
@@ -1006,8 +1050,16 @@ __global__ __launch_bounds__(kNT) void axpy_copy_kernel(int64_t n3, const double
         w[i] = x[i] + z[i];
 }
 
+template <int VEC>
 __global__ __launch_bounds__(kNT) void copy_kernel(int64_t n3, const double* __restrict__ a,
                                                    double* __restrict__ b) {
+    if (VEC == 2) {
+        const int64_t n2 = n3 / 2;
+        for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n2;
+             i += (int64_t)gridDim.x * kNT)
+            reinterpret_cast<double2*>(b)[i] = reinterpret_cast<const double2*>(a)[i];
+        return;
+    }
     for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
         b[i] = a[i];
 }
@@ -1017,13 +1069,12 @@ hipError_t launch_aq(const SweepGeo& g, const double* p, double* q, double inv_h
     OpAq op{p, q, inv_h2, st, partials};
     return launch_sweep(op, g, s);
 }
-// Fused SSOR solve launcher: K = inner steps (2..8 instantiated), 64 x 8
-// tiles (32 x 8 when n is not a multiple of 64), z split to about 4096 blocks.
-template <int K, int DIR, int TX>
+// Fused SSOR solve launcher: K = inner steps (1..4 instantiated); z split to
+// about 4096 blocks.
+template <int K, int DIR, int TX, int TY>
 static hipError_t ssor_fused_t(int n, int bounded, const double* src, const double* add, const double* rdot,
                                double* dst, double s0, double c, double oscale, DevState* st,
                                double* partials, hipStream_t s) {
-    constexpr int TY = 8;
     const int nbx = n / TX, nby = n / TY;
     int nbz = 1;
     for (int z = 1; z <= n / 16; ++z)
@@ -1039,11 +1090,12 @@ template <int K, int DIR>
 static hipError_t ssor_fused_k(int n, int bounded, const double* src, const double* add,
                                const double* rdot, double* dst, double s0, double c, double oscale,
                                DevState* st, double* partials, hipStream_t s) {
-    if (n % 64 == 0)
-        return ssor_fused_t<K, DIR, 64>(n, bounded, src, add, rdot, dst, s0, c, oscale, st,
-                                        partials, s);
-    return ssor_fused_t<K, DIR, 32>(n, bounded, src, add, rdot, dst, s0, c, oscale, st, partials,
-                                    s);
+    // 64-wide tiles only while their LDS keeps 5+ waves per SIMD resident
+    if (n % 64 == 0 && K < 3)
+        return ssor_fused_t<K, DIR, 64, 8>(n, bounded, src, add, rdot, dst, s0, c, oscale, st,
+                                           partials, s);
+    return ssor_fused_t<K, DIR, 32, 8>(n, bounded, src, add, rdot, dst, s0, c, oscale, st,
+                                       partials, s);
 }
 
 bool ssor_fused_supported(int n, int inner) { return n % 32 == 0 && inner >= 1 && inner <= 4; }
@@ -1073,10 +1125,20 @@ hipError_t launch_ssor_half(const SweepGeo& g, const double* src, const double* 
     OpSsorHalf op{src, base, add, rdot, dst, c, bscale, sscale, oscale, dir, st, partials};
     return launch_sweep(op, g, s);
 }
+static bool vec2_ok(int64_t n3, const void* a, const void* b, const void* c = nullptr,
+                    const void* d = nullptr) {
+    const uintptr_t m = (uintptr_t)a | (uintptr_t)b | (uintptr_t)c | (uintptr_t)d;
+    return (n3 % 2) == 0 && (m & 15u) == 0;
+}
+
 hipError_t launch_fcg_update(int64_t n3, double* x, double* r, const double* p, const double* q,
                              double a, DevState* st, double* partials, hipStream_t s) {
-    hipLaunchKernelGGL(fcg_update_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, x, r, p, q, a,
-                       st, partials);
+    if (vec2_ok(n3, x, r, p, q))
+        hipLaunchKernelGGL(fcg_update_kernel<2>, dim3(stream_blocks(n3 / 2)), dim3(kNT), 0, s, n3, x,
+                           r, p, q, a, st, partials);
+    else
+        hipLaunchKernelGGL(fcg_update_kernel<1>, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, x, r,
+                           p, q, a, st, partials);
     return hipGetLastError();
 }
 hipError_t launch_fcg_dots(int64_t n3, const double* z, const double* r, const double* q,
@@ -1086,7 +1148,10 @@ hipError_t launch_fcg_dots(int64_t n3, const double* z, const double* r, const d
     return hipGetLastError();
 }
 hipError_t launch_xpby(int64_t n3, const double* z, double* p, double b, hipStream_t s) {
-    hipLaunchKernelGGL(xpby_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, z, p, b);
+    if (vec2_ok(n3, z, p))
+        hipLaunchKernelGGL(xpby_kernel<2>, dim3(stream_blocks(n3 / 2)), dim3(kNT), 0, s, n3, z, p, b);
+    else
+        hipLaunchKernelGGL(xpby_kernel<1>, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, z, p, b);
     return hipGetLastError();
 }
 hipError_t launch_axpy_copy(int64_t n3, const double* x, const double* z, double* w, hipStream_t s) {
@@ -1094,7 +1159,10 @@ hipError_t launch_axpy_copy(int64_t n3, const double* x, const double* z, double
     return hipGetLastError();
 }
 hipError_t launch_copy(int64_t n3, const double* src, double* dst, hipStream_t s) {
-    hipLaunchKernelGGL(copy_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, src, dst);
+    if (vec2_ok(n3, src, dst))
+        hipLaunchKernelGGL(copy_kernel<2>, dim3(stream_blocks(n3 / 2)), dim3(kNT), 0, s, n3, src, dst);
+    else
+        hipLaunchKernelGGL(copy_kernel<1>, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, src, dst);
     return hipGetLastError();
 }
 
