@@ -179,6 +179,18 @@ static double or_ghost(const double *u, int N, int bc, int ix, int iy, int iz)
     return u[OR_IDX(N, c[0], c[1], c[2])];
 }
 
+/* Index of the neighbour of coordinate i (step d = -1 or +1) under the
+ * boundary rule of bc, or -1 where the neighbour is a Dirichlet zero: the
+ * same rule as or_ghost, one axis at a time. */
+static int or_nbr(int i, int d, int N, int bc)
+{
+    int j = i + d;
+    if (j >= 0 && j < N) return j;
+    if (bc == 1) return -1;
+    if (bc == 2) return i;
+    return j < 0 ? j + N : j - N;
+}
+
 /* A = -Lap_h, the 7-point second-order central-difference operator
  * (Sec. 3.2):  (A u)_i = (6 u_i - sum of 6 neighbours) / h^2, the neighbours
  * taken through the boundary rule of bc (periodic for the PIC loop).
@@ -189,11 +201,18 @@ void or_apply_A_bc(int N, double L, int bc, const double *u, double *Au)
     double inv_h2 = inv_h * inv_h;
 #pragma omp parallel for schedule(static)
     for (int iz = 0; iz < N; ++iz) {
+        int zm = or_nbr(iz, -1, N, bc), zp = or_nbr(iz, 1, N, bc);
         for (int iy = 0; iy < N; ++iy) {
+            int ym = or_nbr(iy, -1, N, bc), yp = or_nbr(iy, 1, N, bc);
             for (int ix = 0; ix < N; ++ix) {
-                double t = ((or_ghost(u, N, bc, ix - 1, iy, iz) + or_ghost(u, N, bc, ix + 1, iy, iz)) +
-                            (or_ghost(u, N, bc, ix, iy - 1, iz) + or_ghost(u, N, bc, ix, iy + 1, iz))) +
-                           (or_ghost(u, N, bc, ix, iy, iz - 1) + or_ghost(u, N, bc, ix, iy, iz + 1));
+                int xm = or_nbr(ix, -1, N, bc), xp = or_nbr(ix, 1, N, bc);
+                double vxm = xm < 0 ? 0.0 : u[OR_IDX(N, xm, iy, iz)];
+                double vxp = xp < 0 ? 0.0 : u[OR_IDX(N, xp, iy, iz)];
+                double vym = ym < 0 ? 0.0 : u[OR_IDX(N, ix, ym, iz)];
+                double vyp = yp < 0 ? 0.0 : u[OR_IDX(N, ix, yp, iz)];
+                double vzm = zm < 0 ? 0.0 : u[OR_IDX(N, ix, iy, zm)];
+                double vzp = zp < 0 ? 0.0 : u[OR_IDX(N, ix, iy, zp)];
+                double t = ((vxm + vxp) + (vym + vyp)) + (vzm + vzp);
                 Au[OR_IDX(N, ix, iy, iz)] = (6.0 * u[OR_IDX(N, ix, iy, iz)] - t) * inv_h2;
             }
         }
@@ -494,12 +513,21 @@ double or_efield_bc(int N, double L, int bc, double *phi, double *ex, double *ey
     }
 #pragma omp parallel for schedule(static)
     for (int iz = 0; iz < N; ++iz) {
+        int zm = or_nbr(iz, -1, N, bc), zp = or_nbr(iz, 1, N, bc);
         for (int iy = 0; iy < N; ++iy) {
+            int ym = or_nbr(iy, -1, N, bc), yp = or_nbr(iy, 1, N, bc);
             for (int ix = 0; ix < N; ++ix) {
+                int xm = or_nbr(ix, -1, N, bc), xp = or_nbr(ix, 1, N, bc);
                 int64_t c = OR_IDX(N, ix, iy, iz);
-                ex[c] = -(or_ghost(phi, N, bc, ix + 1, iy, iz) - or_ghost(phi, N, bc, ix - 1, iy, iz)) * ehalf;
-                ey[c] = -(or_ghost(phi, N, bc, ix, iy + 1, iz) - or_ghost(phi, N, bc, ix, iy - 1, iz)) * ehalf;
-                ez[c] = -(or_ghost(phi, N, bc, ix, iy, iz + 1) - or_ghost(phi, N, bc, ix, iy, iz - 1)) * ehalf;
+                double vxm = xm < 0 ? 0.0 : phi[OR_IDX(N, xm, iy, iz)];
+                double vxp = xp < 0 ? 0.0 : phi[OR_IDX(N, xp, iy, iz)];
+                double vym = ym < 0 ? 0.0 : phi[OR_IDX(N, ix, ym, iz)];
+                double vyp = yp < 0 ? 0.0 : phi[OR_IDX(N, ix, yp, iz)];
+                double vzm = zm < 0 ? 0.0 : phi[OR_IDX(N, ix, iy, zm)];
+                double vzp = zp < 0 ? 0.0 : phi[OR_IDX(N, ix, iy, zp)];
+                ex[c] = -(vxp - vxm) * ehalf;
+                ey[c] = -(vyp - vym) * ehalf;
+                ez[c] = -(vzp - vzm) * ehalf;
             }
         }
     }

@@ -676,7 +676,6 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
     const int64_t n3 = c->n3;
     double* z = c->sv[0];
     double* q = c->sv[1];
-    double* p = c->p2[0];
     HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 1, c->p.rtol, c->p.max_iter, c->st,
                              c->partials, s));
     RETCHK(read_state(c, s));
@@ -694,12 +693,17 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
         return PIC_OK;
     }
     RETCHK(ssor_apply(c, c->r, z, s));
-    HIPCHK(launch_copy(n3, z, p, s));
     RETCHK(read_state(c, s));
-    double rz = c->st_host->flex_zr;
+    double rz = c->st_host->flex_zr, beta = 0.0;
+    int restart = 1;  // p = z (no previous direction)
+    int cur = 0;      // p2[cur] holds the current direction
     int64_t it = 0;
     while (it < c->p.max_iter) {
-        HIPCHK(launch_aq(g, p, q, c->inv_h2, c->st, c->partials, s));
+        // p_new = z + beta p, q = A p_new, p_new . q
+        HIPCHK(launch_aqz(g, z, c->p2[cur], c->p2[cur ^ 1], q, beta, restart, c->inv_h2, c->st,
+                          c->partials, s));
+        cur ^= 1;
+        double* p = c->p2[cur];
         RETCHK(read_state(c, s));
         const double pq = c->st_host->flex_pq;
         const double alpha = rz / pq;
@@ -711,8 +715,8 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
         out->rel_res = rn / nb;
         if (!std::isfinite(rn)) break;
         if (rn <= tol) {
-            HIPCHK(launch_resid_norm(g, b, x, c->fw ? c->fw : c->sv[5], c->inv_h2, c->st,
-                                     c->partials, s));
+            double* res = c->fw ? c->fw : c->sv[5];
+            HIPCHK(launch_resid_norm(g, b, x, res, c->inv_h2, c->st, c->partials, s));
             RETCHK(read_state(c, s));
             const double tn = c->st_host->out_nr;
             out->rel_res = tn / nb;
@@ -720,20 +724,21 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
                 out->converged = 1;
                 break;
             }
-            HIPCHK(launch_copy(n3, c->fw ? c->fw : c->sv[5], c->r, s));
+            // residual replacement: r = b - A x, the direction restarts
+            HIPCHK(launch_copy(n3, res, c->r, s));
             RETCHK(ssor_apply(c, c->r, z, s));
-            HIPCHK(launch_copy(n3, z, p, s));
             RETCHK(read_state(c, s));
             rz = c->st_host->flex_zr;
+            restart = 1;
             out->replacements += 1;
             continue;
         }
         RETCHK(ssor_apply(c, c->r, z, s));
         RETCHK(read_state(c, s));
         const double rz_new = c->st_host->flex_zr;
-        const double beta = rz_new / rz;
+        beta = rz_new / rz;
         rz = rz_new;
-        HIPCHK(launch_xpby(n3, z, p, beta, s));
+        restart = 0;
     }
     out->iterations = it;
     if (!out->converged) {

@@ -105,6 +105,9 @@ hipError_t launch_ssor_half(const SweepGeo& g, const double* src, const double* 
                             const double* add, const double* rdot, double* dst, double c,
                             double bscale, double sscale, double oscale, int dir, DevState* st,
                             double* partials, hipStream_t s);
+hipError_t launch_aqz(const SweepGeo& g, const double* z, const double* p_old, double* p_new,
+                      double* q, double beta, int restart, double inv_h2, DevState* st,
+                      double* partials, hipStream_t s);
 hipError_t launch_aq(const SweepGeo& g, const double* p, double* q, double inv_h2, DevState* st,
                      double* partials, hipStream_t s);
 hipError_t launch_fcg_update(int64_t n3, double* x, double* r, const double* p, const double* q,

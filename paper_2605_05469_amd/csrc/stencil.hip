@@ -452,6 +452,50 @@ struct OpOuterResid {
 };
 
 // Flexible CG: q = A p (stored), reduce p . q.
+// p_new = z + beta p_old (p_new = z on a restart), q = A p_new (stored);
+// reduce p_new . q into st->flex_pq.  The direction update of a PCG with a
+// general preconditioner, fused into its product sweep.
+struct OpAqZ {
+    using T = double;
+    struct In {
+        double z, p;
+    };
+    using Own = Nothing;
+    static constexpr int NACC = 1;
+    const double* z;
+    const double* p_old;
+    double* p_new;
+    double* q;
+    double beta;
+    int restart;
+    double inv_h2;
+    DevState* st;
+    double* part;
+    __device__ bool active() const { return true; }
+    __device__ void prepare() {}
+    __device__ In fetch(size_t g) const {
+        In v;
+        v.z = z[g];
+        v.p = restart ? 0.0 : p_old[g];
+        return v;
+    }
+    __device__ double make(const In& v, size_t g, bool own) const {
+        const double pn = restart ? v.z : v.z + beta * v.p;
+        if (own) st_own(pn, p_new + g);
+        return pn;
+    }
+    __device__ Nothing pre(size_t) const { return Nothing{}; }
+    __device__ void out(const Nothing&, size_t g, double c, double xm, double xp, double ym,
+                        double yp, double zm, double zp, double (&acc)[1]) const {
+        const double qv = apply_A<double>(c, xm, xp, ym, yp, zm, zp, inv_h2);
+        st_own(qv, q + g);
+        acc[0] += c * qv;
+    }
+    __device__ void finish(double (&t)[1]) const { st->flex_pq = t[0]; }
+    __device__ uint32_t* ticket() const { return &st->tickets[1]; }
+    __device__ double* partials() const { return part; }
+};
+
 struct OpAq {
     using T = double;
     using In = double;
@@ -1062,6 +1106,13 @@ __global__ __launch_bounds__(kNT) void copy_kernel(int64_t n3, const double* __r
     }
     for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
         b[i] = a[i];
+}
+
+hipError_t launch_aqz(const SweepGeo& g, const double* z, const double* p_old, double* p_new,
+                      double* q, double beta, int restart, double inv_h2, DevState* st,
+                      double* partials, hipStream_t s) {
+    OpAqZ op{z, p_old, p_new, q, beta, restart, inv_h2, st, partials};
+    return launch_sweep(op, g, s);
 }
 
 hipError_t launch_aq(const SweepGeo& g, const double* p, double* q, double inv_h2, DevState* st,
