@@ -584,12 +584,13 @@ struct OpSsorHalf {
 // planes early, after which every level is valid.  The arithmetic and its
 // order are those of K separate half-sweeps (identical results); the bytes
 // moved are one read of src (with a K-point halo) and one write per point.
-constexpr int ssor_level_off(int K, int TX, int TY, int l) {
-    int o = 0;
-    for (int j = 0; j < l; ++j) o += 2 * (TX + K - j) * (TY + K - j);
-    return o;
-}
-
+// Every level is computed on the whole (TX + K) x (TY + K) region of level 0
+// (values outside a level's own region are not needed by any output and are
+// simply not used), so each thread owns the same NP0 region points at every
+// level and plane: its level-0 value (the B term) and each level's value of
+// the previous plane (the z neighbour) stay in its registers, and only the
+// in-plane upwind neighbours go through LDS -- one padded plane per level
+// (a zero row and column on the upwind side keep the edge reads in bounds).
 template <int K, int DIR, int TX, int TY>
 __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int bounded, int nbx, int nby,
                                                          int zlen,
@@ -600,110 +601,126 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int bounded, int
                                                          double c, double oscale, DevState* st,
                                                          double* part) {
     constexpr int W0 = TX + K, H0 = TY + K;
-    constexpr int RT = kNT / TX;  // thread rows
-    static_assert(K < TX, "a level's region spans at most two column passes");
-    constexpr int NLDS = ssor_level_off(K, TX, TY, K);
-    __shared__ double lds[NLDS];
+    constexpr int WP = W0 + 1, HP = H0 + 1;  // padded plane
+    constexpr int PLANE = WP * HP;
+    constexpr int NP0 = (W0 * H0 + kNT - 1) / kNT;
+    __shared__ double lds[K][PLANE];
     __shared__ double red[kNT / kWave];
     __shared__ int lflag;
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
     const uint32_t lb = remap_xcd(blockIdx.x, gridDim.x);
     const int bx = (int)(lb % nbx), by = (int)((lb / nbx) % nby), bz = (int)(lb / (nbx * nby));
     const int x0 = bx * TX, y0 = by * TY;
     const int z0 = bz * zlen, z1 = z0 + zlen;
     const size_t nn = (size_t)n * n;
-    // level 0 region origin: widened towards -x, -y (DIR 0) or +x, +y (DIR 1)
+    // region origin: widened towards -x, -y (DIR 0) or +x, +y (DIR 1)
     const int ax = DIR == 0 ? x0 - K : x0, ay = DIR == 0 ? y0 - K : y0;
-    for (int i = tid; i < NLDS; i += kNT) lds[i] = 0.0;
-    double acc[1] = {0.0};
-    constexpr int NP0 = (W0 * H0 + kNT - 1) / kNT;
-    double stg[NP0];
-    const int nsteps = zlen + K;
-    int cur = 0;
-    __syncthreads();
-    // a bounded box has no neighbour across a face: every level is zero
-    // outside the grid (the load uses the clamped index, always in bounds)
+    // padded offset of region point (lx, ly): the pad is the row/column before
+    // the region (DIR 0) or after it (DIR 1)
+    constexpr int PO = DIR == 0 ? WP + 1 : 0;
     auto outside = [n](int v) { return v < 0 || v >= n; };
     auto gmap = [n, bounded](int v) {
         if (v >= 0 && v < n) return v;
         if (!bounded) return v < 0 ? v + n : v - n;
         return v < 0 ? 0 : n - 1;
     };
-    for (int t = 0; t <= nsteps; ++t) {
-        // prefetch level 0 of step t (plane sequence: DIR 0 upward from
-        // z0 - K, DIR 1 downward from z1 - 1 + K), then finish step t - 1
-        if (t < nsteps) {
-            const int zr = DIR == 0 ? z0 - K + t : z1 - 1 + K - t;
-            const bool zout = bounded && outside(zr);
-            const size_t zo = (size_t)gmap(zr) * nn;
+    // this thread's region points (fixed for all levels and planes)
+    int pofs[NP0];            // padded LDS offset, -1: no point
+    uint32_t goff[NP0];       // in-plane global offset of the (mapped) point
+    uint32_t outm = 0;        // bit k: point k is an output point
+    uint32_t zerom = 0;       // bit k: point k lies outside a bounded grid
+#pragma unroll
+    for (int k = 0; k < NP0; ++k) {
+        const int e = tid + k * kNT;
+        pofs[k] = -1;
+        goff[k] = 0;
+        if (e < W0 * H0) {
+            const int lx = e % W0, ly = e / W0;
+            const int rx = ax + lx, ry = ay + ly;
+            pofs[k] = PO + ly * WP + lx;
+            goff[k] = (uint32_t)gmap(ry) * (uint32_t)n + (uint32_t)gmap(rx);
+            const bool in_tile = rx >= x0 && rx < x0 + TX && ry >= y0 && ry < y0 + TY;
+            if (in_tile) outm |= 1u << k;
+            if (bounded && (outside(rx) || outside(ry))) zerom |= 1u << k;
+        }
+    }
+    for (int i = tid; i < K * PLANE; i += kNT) (&lds[0][0])[i] = 0.0;
+    double acc[1] = {0.0};
+    double stg[NP0];          // level 0 of the next plane (prefetched)
+    double prev[K][NP0];      // levels 0..K-1 at the previous plane
+#pragma unroll
+    for (int l = 0; l < K; ++l)
+#pragma unroll
+        for (int k = 0; k < NP0; ++k) prev[l][k] = 0.0;
+    const int nsteps = zlen + K;  // planes in march order: z0 - K .. z1 - 1 (DIR 0)
+    auto zof = [&](int p) { return DIR == 0 ? z0 - K + p : z1 - 1 + K - p; };
+    auto fetch0 = [&](int p) {
+        const int zr = zof(p);
+        const bool zout = bounded && outside(zr);
+        const size_t zo = (size_t)gmap(zr) * nn;
+#pragma unroll
+        for (int k = 0; k < NP0; ++k) {
+            const double v = pofs[k] >= 0 ? src[zo + goff[k]] : 0.0;
+            stg[k] = (zout || ((zerom >> k) & 1u)) ? 0.0 : v;
+        }
+    };
+    __syncthreads();
+    fetch0(0);
+    for (int t = 0; t < nsteps; ++t) {
+        const int z = zof(t);
+        const bool zout = bounded && outside(z);
+        const bool out_plane = DIR == 0 ? (z >= z0) : (z < z1);
+        double cur[NP0];
+#pragma unroll
+        for (int k = 0; k < NP0; ++k) {
+            cur[k] = s0 == 1.0 ? stg[k] : s0 * stg[k];
+            if (pofs[k] >= 0) lds[0][pofs[k]] = cur[k];
+        }
+        double B[NP0];
+#pragma unroll
+        for (int k = 0; k < NP0; ++k) B[k] = cur[k];
+        if (t + 1 < nsteps) fetch0(t + 1);
+        __syncthreads();
+#pragma unroll
+        for (int l = 1; l <= K; ++l) {
+            const double* P = lds[l - 1];
+            double nxt[NP0];
 #pragma unroll
             for (int k = 0; k < NP0; ++k) {
-                const int e = tid + k * kNT;
-                if (e < W0 * H0) {
-                    const int rx = ax + e % W0, ry = ay + e / W0;
-                    const double v = src[zo + (size_t)gmap(ry) * n + gmap(rx)];
-                    stg[k] = (zout || (bounded && (outside(rx) || outside(ry)))) ? 0.0 : v;
-                }
+                nxt[k] = 0.0;
+                if (pofs[k] < 0) continue;
+                const int pi = pofs[k];
+                const double sn = DIR == 0 ? (P[pi - 1] + P[pi - WP]) + prev[l - 1][k]
+                                           : (P[pi + 1] + P[pi + WP]) + prev[l - 1][k];
+                double v = B[k] + c * sn;
+                if (bounded && (zout || ((zerom >> k) & 1u))) v = 0.0;
+                nxt[k] = v;
             }
-        }
-        if (t > 0) {
-            const int tp = t - 1;
-            const int z = DIR == 0 ? z0 - K + tp : z1 - 1 + K - tp;
-            const bool out_plane = DIR == 0 ? (z >= z0) : (z < z1);
-            const bool zout = bounded && outside(z);
-            const double* B = lds + cur * W0 * H0;  // level 0, this plane
+            // the previous plane's level l-1 values are consumed: keep this plane's
 #pragma unroll
-            for (int l = 1; l <= K; ++l) {
-                const int Wp = TX + K - l + 1, Hp = TY + K - l + 1;
-                const int Wl = Wp - 1, Hl = Hp - 1;
-                const double* P = lds + ssor_level_off(K, TX, TY, l - 1) + cur * Wp * Hp;
-                const double* Pz = lds + ssor_level_off(K, TX, TY, l - 1) + (cur ^ 1) * Wp * Hp;
-                double* Q = lds + ssor_level_off(K, TX, TY, l) + cur * Wl * Hl;
-                // this level's region inside level l-1's (offset o1) and level 0's (ol)
-                const int o1 = DIR == 0 ? 1 : 0, ol = DIR == 0 ? l : 0;
-                // thread (tx, ty) takes columns tx, tx + TX and rows ty, ty + RT, ...
+            for (int k = 0; k < NP0; ++k) prev[l - 1][k] = cur[k];
+            if (l < K) {
+                // level l's plane was last read by level l+1 of the previous
+                // plane, before the end-of-plane barrier
 #pragma unroll
-                for (int cp = 0; cp < 2; ++cp) {
-                    const int lx = tx + cp * TX;
-                    if (lx >= Wl) continue;
-#pragma unroll
-                    for (int rp = 0; rp < (TY + K + RT - 1) / RT; ++rp) {
-                        const int ly = ty + rp * RT;
-                        if (ly >= Hl) continue;
-                        const int e = ly * Wl + lx;
-                        const int pi = (ly + o1) * Wp + (lx + o1);
-                        const double sn = DIR == 0 ? (P[pi - 1] + P[pi - Wp]) + Pz[pi]
-                                                   : (P[pi + 1] + P[pi + Wp]) + Pz[pi];
-                        double v = B[(ly + ol) * W0 + (lx + ol)] + c * sn;
-                        if (l < K) {
-                            // level l's region starts K - l points upwind of the tile
-                            const int rx = DIR == 0 ? x0 - (K - l) + lx : x0 + lx;
-                            const int ry = DIR == 0 ? y0 - (K - l) + ly : y0 + ly;
-                            if (bounded && (zout || outside(rx) || outside(ry))) v = 0.0;
-                            Q[e] = v;
-                        } else if (out_plane) {
-                            const size_t g = (size_t)z * nn + (size_t)(y0 + ly) * n + (x0 + lx);
-                            double o = oscale == 1.0 ? v : oscale * v;
-                            if (add) o = o + add[g];
-                            dst[g] = o;
-                            if (rdot) acc[0] += rdot[g] * o;
-                        }
-                    }
-                }
+                for (int k = 0; k < NP0; ++k)
+                    if (pofs[k] >= 0) lds[l][pofs[k]] = nxt[k];
                 __syncthreads();
-            }
-            cur ^= 1;
-        }
-        if (t < nsteps) {
-            double* L0 = lds + cur * W0 * H0;
 #pragma unroll
-            for (int k = 0; k < NP0; ++k) {
-                const int e = tid + k * kNT;
-                if (e < W0 * H0) L0[e] = s0 == 1.0 ? stg[k] : s0 * stg[k];
+                for (int k = 0; k < NP0; ++k) cur[k] = nxt[k];
+            } else if (out_plane) {
+#pragma unroll
+                for (int k = 0; k < NP0; ++k) {
+                    if (!((outm >> k) & 1u)) continue;
+                    const size_t g = (size_t)z * nn + goff[k];
+                    double o = oscale == 1.0 ? nxt[k] : oscale * nxt[k];
+                    if (add) o = o + add[g];
+                    dst[g] = o;
+                    if (rdot) acc[0] += rdot[g] * o;
+                }
             }
-            __syncthreads();
         }
+        __syncthreads();  // level K's reads of level K-1 done before the next plane
     }
     block_sum<kNT, 1>(acc, red);
     if (tid == 0) part[lb] = acc[0];
