@@ -675,7 +675,6 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
     const SweepGeo& g = c->geo;
     const int64_t n3 = c->n3;
     double* z = c->sv[0];
-    double* q = c->sv[1];
     HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 1, c->p.rtol, c->p.max_iter, c->st,
                              c->partials, s));
     RETCHK(read_state(c, s));
@@ -699,16 +698,17 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
     int cur = 0;      // p2[cur] holds the current direction
     int64_t it = 0;
     while (it < c->p.max_iter) {
-        // p_new = z + beta p, q = A p_new, p_new . q
-        HIPCHK(launch_aqz(g, z, c->p2[cur], c->p2[cur ^ 1], q, beta, restart, c->inv_h2, c->st,
-                          c->partials, s));
+        // p_new = z + beta p and p_new . A p_new (A p_new not stored)
+        HIPCHK(launch_aqz(g, z, c->p2[cur], c->p2[cur ^ 1], nullptr, beta, restart, c->inv_h2,
+                          c->st, c->partials, s));
         cur ^= 1;
         double* p = c->p2[cur];
         RETCHK(read_state(c, s));
         const double pq = c->st_host->flex_pq;
         const double alpha = rz / pq;
         if (!std::isfinite(alpha) || !(pq > 0.0)) break;
-        HIPCHK(launch_fcg_update(n3, x, c->r, p, q, alpha, c->st, c->partials, s));
+        // x += alpha p, r -= alpha A p (A p recomputed), r . r
+        HIPCHK(launch_updp(g, p, x, c->r, alpha, c->inv_h2, c->st, c->partials, s));
         RETCHK(read_state(c, s));
         ++it;
         rn = std::sqrt(c->st_host->flex_rr);

@@ -108,6 +108,8 @@ hipError_t launch_ssor_half(const SweepGeo& g, const double* src, const double* 
 hipError_t launch_aqz(const SweepGeo& g, const double* z, const double* p_old, double* p_new,
                       double* q, double beta, int restart, double inv_h2, DevState* st,
                       double* partials, hipStream_t s);
+hipError_t launch_updp(const SweepGeo& g, const double* p, double* x, double* r, double alpha,
+                       double inv_h2, DevState* st, double* partials, hipStream_t s);
 hipError_t launch_aq(const SweepGeo& g, const double* p, double* q, double inv_h2, DevState* st,
                      double* partials, hipStream_t s);
 hipError_t launch_fcg_update(int64_t n3, double* x, double* r, const double* p, const double* q,

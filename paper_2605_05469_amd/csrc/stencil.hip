@@ -452,9 +452,9 @@ struct OpOuterResid {
 };
 
 // Flexible CG: q = A p (stored), reduce p . q.
-// p_new = z + beta p_old (p_new = z on a restart), q = A p_new (stored);
-// reduce p_new . q into st->flex_pq.  The direction update of a PCG with a
-// general preconditioner, fused into its product sweep.
+// p_new = z + beta p_old (p_new = z on a restart), q = A p_new (stored when
+// q is not null); reduce p_new . q into st->flex_pq.  The direction update
+// of a PCG with a general preconditioner, fused into its product sweep.
 struct OpAqZ {
     using T = double;
     struct In {
@@ -488,11 +488,49 @@ struct OpAqZ {
     __device__ void out(const Nothing&, size_t g, double c, double xm, double xp, double ym,
                         double yp, double zm, double zp, double (&acc)[1]) const {
         const double qv = apply_A<double>(c, xm, xp, ym, yp, zm, zp, inv_h2);
-        st_own(qv, q + g);
+        if (q) st_own(qv, q + g);
         acc[0] += c * qv;
     }
     __device__ void finish(double (&t)[1]) const { st->flex_pq = t[0]; }
     __device__ uint32_t* ticket() const { return &st->tickets[1]; }
+    __device__ double* partials() const { return part; }
+};
+
+// x += alpha p, r -= alpha A p (A p recomputed from the staged p, so q is
+// never stored); reduce r . r into st->flex_rr.
+struct OpUpdP {
+    using T = double;
+    using In = double;
+    struct Own {
+        double x, r;
+    };
+    static constexpr int NACC = 1;
+    const double* p;
+    double* x;
+    double* r;
+    double alpha, inv_h2;
+    DevState* st;
+    double* part;
+    __device__ bool active() const { return true; }
+    __device__ void prepare() {}
+    __device__ double fetch(size_t g) const { return p[g]; }
+    __device__ double make(double v, size_t, bool) const { return v; }
+    __device__ Own pre(size_t g) const {
+        Own o;
+        o.x = ld_own(x + g);
+        o.r = ld_own(r + g);
+        return o;
+    }
+    __device__ void out(const Own& o, size_t g, double c, double xm, double xp, double ym,
+                        double yp, double zm, double zp, double (&acc)[1]) const {
+        const double q = apply_A<double>(c, xm, xp, ym, yp, zm, zp, inv_h2);
+        st_own(o.x + alpha * c, x + g);
+        const double rv = o.r - alpha * q;
+        st_own(rv, r + g);
+        acc[0] += rv * rv;
+    }
+    __device__ void finish(double (&t)[1]) const { st->flex_rr = t[0]; }
+    __device__ uint32_t* ticket() const { return &st->tickets[2]; }
     __device__ double* partials() const { return part; }
 };
 
@@ -1129,6 +1167,12 @@ hipError_t launch_aqz(const SweepGeo& g, const double* z, const double* p_old, d
                       double* q, double beta, int restart, double inv_h2, DevState* st,
                       double* partials, hipStream_t s) {
     OpAqZ op{z, p_old, p_new, q, beta, restart, inv_h2, st, partials};
+    return launch_sweep(op, g, s);
+}
+
+hipError_t launch_updp(const SweepGeo& g, const double* p, double* x, double* r, double alpha,
+                       double inv_h2, DevState* st, double* partials, hipStream_t s) {
+    OpUpdP op{p, x, r, alpha, inv_h2, st, partials};
     return launch_sweep(op, g, s);
 }
 
