@@ -697,6 +697,13 @@ static double or_dot32(int64_t n, const float *a, const float *b)
  * the scaled variables of each inner solve (r / ||r||) this is
  *   p~' = M r~' + beta~ p~_j,  beta~ = (nr' / nr) (r~'.M r~') / (r~_j.M r~_j),
  * nr, nr' the outer residual norms before and after the refinement.
+ * Residual replacement keeps CG's recurrences only while the replaced
+ * residual stays close to the recursive one; FP32 inner solves drift from
+ * their true residual by about eps32 kappa(A), which at large N exceeds a
+ * tight inner tolerance.  So the direction is carried only if the
+ * refinement's true reduction nr'/nr is within a factor 4 of the inner
+ * solve's recursive one ||r~_in|| / ||r~_0||; otherwise the inner solve
+ * restarts from p = M r.
  * info: [0]=outer steps, [1]=total inner iterations, [2]=true rel. residual,
  *       [3]=converged.                                                    */
 void or_mixed_pcg_ex(int N, double L, const double *b, double *x, double rtol,
@@ -724,7 +731,7 @@ void or_mixed_pcg_ex(int N, double L, const double *b, double *x, double rtol,
         return;
     }
     int have_dir = 0;        /* reliable form: p holds the last direction */
-    double rz_last = 0.0, nr_prev = 0.0;
+    double rz_last = 0.0, nr_prev = 0.0, rec_last = 0.0;
     for (;;) {
         double nr = or_true_residual(N, L, 0, b, x, r);
         trel = nr / nb;
@@ -736,6 +743,8 @@ void or_mixed_pcg_ex(int N, double L, const double *b, double *x, double rtol,
         double n0 = sqrt(or_dot32(n3, ri, ri));
         for (int64_t i = 0; i < n3; ++i) zz[i] = minvf * ri[i];
         double rz = or_dot32(n3, ri, zz);
+        /* carry the direction only while the replacement is consistent */
+        if (have_dir && !(nr <= 4.0 * rec_last * nr_prev)) have_dir = 0;
         double bc = reliable && have_dir ? (nr / nr_prev) * (rz / rz_last) : 0.0;
         if (reliable && have_dir && isfinite(bc)) {
             float bf = (float)bc;
@@ -761,6 +770,7 @@ void or_mixed_pcg_ex(int N, double L, const double *b, double *x, double rtol,
             if (rn <= inner_rtol * n0 || k + 1 == max_inner) {
                 rz_last = rz; /* r_j.M r_j of the residual p_j was built from */
                 have_dir = isfinite(rn);
+                rec_last = rn / n0; /* the inner solve's recursive reduction */
                 break;
             }
             float bf = (float)(rz_new / rz);

@@ -842,8 +842,13 @@ __global__ __launch_bounds__(kNT) void convert32_kernel(int64_t n3, const double
         if (threadIdx.x == 0) {
             CgScalars& cg = st->cg;
             const double n0 = sqrt(tot[0]);
+            // carry the direction only while the refinement's true reduction
+            // stays within a factor 4 of the last inner solve's recursive one
+            // (FP32 drift of about eps32 kappa makes the replaced residual
+            // inconsistent with the recursion at tight inner tolerances)
+            const double rec = sqrt(cg.rr) / cg.nb;
             const bool cont = reliable && (cg.state == CG_CANDIDATE || cg.state == CG_MAXIT) &&
-                              st->prev_nr > 0.0;
+                              st->prev_nr > 0.0 && st->out_nr <= 4.0 * rec * st->prev_nr;
             const double bt = cont ? (st->out_nr / st->prev_nr) * (tot[1] / cg.rz_prev) : 0.0;
             cg.nb = n0;
             cg.tol = inner_rtol * n0;

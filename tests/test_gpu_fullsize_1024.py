@@ -1,9 +1,9 @@
 """Parity at the largest workload: a 1024^3 grid with 2^30 particles (one
 per cell), the size of the learned-preconditioner and mixed-precision runs,
 in the launch configuration the benchmark's solve forms use.  The deposit is
-checked on a sample of vertices and by charge conservation, the FP64 solve by
-its true residual under the oracle's operator, and the field over all
-points."""
+checked on a sample of vertices and by charge conservation, the FP64 and the
+mixed-precision (reliable updates, inner tolerance 0.1) solves by their true
+residuals under the oracle's operator, and the field over all points."""
 import numpy as np
 import pytest
 
@@ -30,7 +30,8 @@ def test_fullsize_1024_deposit_solves_field(orc):
     props = torch.cuda.get_device_properties(0)
     if props.total_memory < 200 * 2 ** 30:
         pytest.skip("needs ~190 GiB of device memory")
-    p = P.landau_params(N, PPC, check_every=32)
+    # inner_rtol is used by the mixed form only (end of the test)
+    p = P.landau_params(N, PPC, check_every=32, inner_rtol=0.1)
     ctx = P.Context(p)
     sim = P.Simulation(ctx, *synth.landau_particles_torch(N, PPC, seed=SEED, device="cuda"))
     _say("particles drawn")
@@ -81,3 +82,14 @@ def test_fullsize_1024_deposit_solves_field(orc):
         assert np.max(np.abs(_host(a) - r)) <= 1e-12 * np.abs(r).max()
     del rphi, rex, rey, rez
     _say("field checked")
+
+    # the mixed form (reliable updates, inner tolerance 0.1) on the same
+    # right-hand side, cold start
+    ctx.set_solver("pcg_mixed")
+    ctx.set_flags(P.FLAG_MIXED_RELIABLE)
+    x = torch.zeros_like(sim.phi)
+    minfo = ctx.poisson(sim.rho, x)
+    _say("mixed solve: %d inner iterations, %d refinements" % (minfo["iterations"],
+                                                            minfo["outer_iterations"]))
+    assert minfo["converged"], minfo
+    assert orc.residual_norm(N, L, b, _host(x)) <= 1.001 * p.rtol * nb
