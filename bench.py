@@ -10,9 +10,10 @@ solve (warm start) -> field.  Inputs are synthetic and seeded, drawn on the
 device; initialisation and the t = 0 solve are not timed (Sec. 4.1 times the
 run minus initialisation).
 
-Prints ONE JSON line.  `roofline` is for the dominant kernel (the PCG update
-sweep), timed with HIP events on the stream it runs on during the timed
-steps; `cpu_baseline` times the CPU oracle on a bounded sample of the same
+Prints ONE JSON line.  `roofline` is for the dominant kernel (the FP64
+PCG's single-reduction sweep; with --two-sweep, or for the other solver
+forms, the PCG update sweep), timed with HIP events on the stream it runs on
+during the timed steps; `cpu_baseline` times the CPU oracle on a bounded sample of the same
 workload on the host cores.
 """
 from __future__ import annotations
@@ -35,10 +36,14 @@ PEAK_HBM_GBS = 8000.0
 SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 40),
                "pcg_ssor": (24, 40), "fft": (24, 40),
                "pif": (24, 40)}
-# HBM bytes per launch of the FP64 update sweep at 512^3, from rocprofv3
+# The Jacobi-PCG single-reduction sweep (the default on the periodic box)
+# reads r, p_old, x and writes r, p, x: 48 bytes per grid point in FP64 (24 for
+# the mixed form's FP32 inner sweeps).
+SINGLE_SWEEP_BYTES = 48
+# HBM bytes per launch of the dominant kernel at 512^3, from rocprofv3
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
-UPDATE_SWEEP_TRAFFIC = {(512, "pcg_fp64"): 5.571e9}
+SWEEP_TRAFFIC = {(512, "pcg_fp64", "pcg_update_sweep"): 5.571e9}
 
 
 def log(*a):
@@ -175,7 +180,8 @@ def bench_poisson(args):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()  # the library allocates the network outside torch
     forms = {}
-    all_forms = ("pcg_fp64", "pcg_mixed", "pcg_mixed_reliable", "pcg_ssor", "pcg_ssor_unfused",
+    all_forms = ("pcg_fp64", "pcg_fp64_two_sweep", "pcg_mixed", "pcg_mixed_reliable",
+                 "pcg_ssor", "pcg_ssor_unfused",
                  "fcg_learned",
                  "learned_warm_start_only", "learned_warm_start_mixed", "fft", "fft_spectral")
     for form in (args.forms.split(",") if args.forms else all_forms):
@@ -184,7 +190,8 @@ def bench_poisson(args):
         solver = ("fcg_learned" if form.startswith("learned") else
                   "pcg_mixed" if form.startswith("pcg_mixed") else
                   "pcg_ssor" if form.startswith("pcg_ssor") else
-                  "fft" if form.startswith("fft") else form)
+                  "fft" if form.startswith("fft") else
+                  "pcg_fp64" if form.startswith("pcg_fp64") else form)
         if solver == "fcg_learned":
             try:
                 load_weights(ctx, args.weights)
@@ -197,7 +204,8 @@ def bench_poisson(args):
                                                            "learned_warm_start_mixed") else 0)
                       | (P.FLAG_LEARNED_MIXED if form == "learned_warm_start_mixed" else 0)
                       | (P.FLAG_FFT_SPECTRAL if form == "fft_spectral" else 0)
-                      | (P.FLAG_SSOR_UNFUSED if form == "pcg_ssor_unfused" else 0))
+                      | (P.FLAG_SSOR_UNFUSED if form == "pcg_ssor_unfused" else 0)
+                      | (P.FLAG_PCG_TWO_SWEEP if form == "pcg_fp64_two_sweep" else 0))
         ctx.set_solver(solver)
         phi = torch.zeros_like(rho)
         torch.cuda.synchronize()
@@ -325,6 +333,9 @@ def main():
                     help="learned form: hand over to the mixed form (not FP64 PCG)")
     ap.add_argument("--mixed-reliable", action="store_true",
                     help="mixed form: keep the inner direction across refinements")
+    ap.add_argument("--two-sweep", action="store_true",
+                    help="FP64 Jacobi-PCG as a direction and an update sweep per iteration "
+                         "(instead of the single-reduction sweep)")
     ap.add_argument("--warm-start-only", action="store_true",
                     help="learned form: network warm start, then Jacobi-PCG")
     ap.add_argument("--accuracy-vs-fp64", action="store_true",
@@ -362,6 +373,8 @@ def main():
         p.flags |= P.FLAG_LEARNED_MIXED
     if args.fft_spectral:
         p.flags |= P.FLAG_FFT_SPECTRAL
+    if args.two_sweep:
+        p.flags |= P.FLAG_PCG_TWO_SWEEP
     ctx = P.Context(p)
     if args.solver == "fcg_learned":
         load_weights(ctx, args.weights)
@@ -395,9 +408,28 @@ def main():
     ms_upd, cnt_upd = P.Context.kernel_time(ctx, 1)
     # (pic_step accumulates the sampled kernel times over all timed steps)
     ctx.set_kernel_timing(False)
-    gbs_upd = bupd * n3 / (ms_upd * 1e-3) / 1e9 if ms_upd > 0 else 0.0
-    gbs_dir = bdir * n3 / (ms_dir * 1e-3) / 1e9 if ms_dir > 0 else 0.0
-    gbs_iter = (bdir + bupd) * n3 / ((ms_dir + ms_upd) * 1e-3) / 1e9 if ms_upd > 0 else 0.0
+    # Jacobi-PCG (FP64, the mixed form's FP32 inner solves, the learned form's
+    # hand-over) runs as one kernel per iteration on the periodic box unless
+    # --two-sweep; its launches are sampled in timing slot 0
+    single = (args.solver in ("pcg_fp64", "pcg_mixed", "fcg_learned") and not args.two_sweep
+              and N % 32 == 0)
+    if single:
+        fp32 = args.solver == "pcg_mixed" or args.learned_mixed
+        b1 = SINGLE_SWEEP_BYTES // 2 if fp32 else SINGLE_SWEEP_BYTES
+        dom = "pcg_single_sweep_fp32" if fp32 else "pcg_single_sweep"
+        gbs_one = b1 * n3 / (ms_dir * 1e-3) / 1e9 if ms_dir > 0 else 0.0
+        kernels = {dom: {"avg_ms": ms_dir, "launches_timed": cnt_dir, "bytes_per_point": b1,
+                         "gbs": gbs_one}}
+        gbs_dom, gbs_iter = gbs_one, gbs_one
+    else:
+        gbs_upd = bupd * n3 / (ms_upd * 1e-3) / 1e9 if ms_upd > 0 else 0.0
+        gbs_dir = bdir * n3 / (ms_dir * 1e-3) / 1e9 if ms_dir > 0 else 0.0
+        gbs_iter = (bdir + bupd) * n3 / ((ms_dir + ms_upd) * 1e-3) / 1e9 if ms_upd > 0 else 0.0
+        kernels = {"pcg_direction_sweep": {"avg_ms": ms_dir, "launches_timed": cnt_dir,
+                                           "bytes_per_point": bdir, "gbs": gbs_dir},
+                   "pcg_update_sweep": {"avg_ms": ms_upd, "launches_timed": cnt_upd,
+                                        "bytes_per_point": bupd, "gbs": gbs_upd}}
+        dom, gbs_dom = "pcg_update_sweep", gbs_upd
     phases = {k: sum(i[k] for i in infos) / len(infos)
               for k in ("ms_push", "ms_sort", "ms_deposit", "ms_solve", "ms_field")}
     for i, inf in enumerate(infos):
@@ -419,6 +451,7 @@ def main():
         "config": {"workload": "landau_damping_%d^3_%dppc_%s" % (N, ppc, args.solver),
                    "grid": N, "ppc": ppc, "particles": npart, "solver": args.solver,
                    "rtol": args.rtol, "dt": p.dt, "k": 0.5, "alpha": 0.05,
+                   "pcg_form": "single_reduction_sweep" if single else "two_sweeps",
                    "parallelism": "single_gpu"},
         "particles_per_s": npart / s_step,
         "pcg_iterations_per_step": iters,
@@ -426,13 +459,10 @@ def main():
         "all_converged": all(i["converged"] for i in infos),
         "max_rel_res": max(i["rel_res"] for i in infos),
         "phases_ms": phases,
-        "kernels": {"pcg_direction_sweep": {"avg_ms": ms_dir, "launches_timed": cnt_dir,
-                                            "bytes_per_point": bdir, "gbs": gbs_dir},
-                    "pcg_update_sweep": {"avg_ms": ms_upd, "launches_timed": cnt_upd,
-                                         "bytes_per_point": bupd, "gbs": gbs_upd}},
-        "roofline": {"bound": "hbm", "kernel": "pcg_update_sweep", "achieved": gbs_upd,
-                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs_upd / PEAK_HBM_GBS,
-                     "traffic": UPDATE_SWEEP_TRAFFIC.get((N, args.solver))},
+        "kernels": kernels,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": gbs_dom,
+                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs_dom / PEAK_HBM_GBS,
+                     "traffic": SWEEP_TRAFFIC.get((N, args.solver, dom))},
     }
     if args.accuracy_vs_fp64 and args.solver != "pcg_fp64":
         out["accuracy_vs_fp64"] = accuracy_vs_fp64(args, sim, p)

@@ -106,6 +106,16 @@ enum {
                                       sweep of its own instead of one fused
                                       z-march per triangular solve (same
                                       arithmetic; for comparison) */
+#define PIC_FLAG_PCG_TWO_SWEEP 64  /* Jacobi-PCG on the periodic box (the FP64
+                                      solve and the mixed form's FP32 inner
+                                      solves): one direction sweep and one
+                                      update sweep per iteration (two
+                                      reductions) instead of the default
+                                      single-reduction sweep (the
+                                      Chronopoulos-Gear arrangement of the same
+                                      iteration: 48 instead of 64 bytes per
+                                      grid point in FP64).  Bounded boxes
+                                      always take the two-sweep form. */
 
 typedef struct pic_params {
     int32_t n;            /* grid points per axis N                         */
@@ -228,7 +238,12 @@ int pic_deposit_cic(pic_ctx *ctx, int64_t np, const double *x, const double *y,
  * operator on the context's box (periodic unless pic_params.bc says
  * otherwise), by the solver form selected in the context, starting from the
  * phi passed in (the previous step's solution, Sec. 4.1), to
- * ||rho - A phi|| <= rtol ||rho||.  rho must have zero mean (not so on a
+ * ||rho - A phi|| <= rtol ||rho||.  Jacobi-PCG on the periodic box runs as
+ * one sweep per iteration with a single reduction (Chronopoulos-Gear: the
+ * same iterates as the textbook recurrences in exact arithmetic; see
+ * PIC_FLAG_PCG_TWO_SWEEP).  Every candidate that meets the tolerance by its
+ * recursive residual is verified by the true residual, which replaces the
+ * recursive one when it does not.  rho must have zero mean (not so on a
  * Dirichlet box).  If ex, ey, ez are all non-NULL, the field is computed as
  * pic_efield does (Sec. 2, Eq. poisson).  info: host out. */
 int pic_poisson_pcg(pic_ctx *ctx, const double *rho, double *phi, double *ex,

@@ -24,6 +24,7 @@ FLAG_MIXED_RELIABLE = 4
 FLAG_LEARNED_MIXED = 8
 FLAG_FFT_SPECTRAL = 16
 FLAG_SSOR_UNFUSED = 32
+FLAG_PCG_TWO_SWEEP = 64
 
 # pic_params.bc: the box's boundary kind (the particle phases need PERIODIC)
 BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
@@ -235,7 +236,8 @@ class Context:
     def set_flags(self, flags: int):
         """FLAG_NO_WARM_START | FLAG_WARM_START_ONLY (learned form),
         FLAG_MIXED_RELIABLE (mixed form), FLAG_LEARNED_MIXED (learned form),
-        FLAG_FFT_SPECTRAL (FFT form), FLAG_SSOR_UNFUSED (SSOR form)."""
+        FLAG_FFT_SPECTRAL (FFT form), FLAG_SSOR_UNFUSED (SSOR form),
+        FLAG_PCG_TWO_SWEEP (FP64 Jacobi-PCG as two sweeps per iteration)."""
         _check(lib().pic_set_flags(self._h, int(flags)))
 
     def cell_keys(self, x, y, z, key, stream=None):

@@ -95,7 +95,8 @@ static bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 
 constexpr int32_t kKnownFlags = PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY |
                                  PIC_FLAG_MIXED_RELIABLE | PIC_FLAG_LEARNED_MIXED |
-                                 PIC_FLAG_FFT_SPECTRAL | PIC_FLAG_SSOR_UNFUSED;
+                                 PIC_FLAG_FFT_SPECTRAL | PIC_FLAG_SSOR_UNFUSED |
+                                 PIC_FLAG_PCG_TWO_SWEEP;
 
 // The solver forms that take a bounded box: the matrix-free stencil ones.
 // The FFT form and the network (periodic convolutions) need the periodic box.
@@ -300,11 +301,72 @@ static int timing_collect(pic_ctx* c, int launched, int64_t valid) {
     return PIC_OK;
 }
 
+// Single-kernel iterations: one sampled (start, end) pair per iteration, in
+// slot 0.
+static int timing_collect_one(pic_ctx* c, int launched, int64_t valid) {
+    for (int k = 0; k < launched && k < valid; k += kTimeStride) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[4 * k], c->ev[4 * k + 1]));
+        c->t_sum[0] += ms;
+        c->t_cnt[0] += 1;
+    }
+    return PIC_OK;
+}
+
 // ------------------------------------------------------------- FP64 PCG ----
+
+static bool use_cg1(const pic_ctx* c) {
+    return !(c->p.flags & PIC_FLAG_PCG_TWO_SWEEP) && cg1_supported(c->geo);
+}
+
+// Single-reduction form: batches of one sweep per iteration.  The residual
+// and the direction alternate between two buffers each (a sweep never writes
+// what neighbouring workgroups read as halo); sweeps queued after the state
+// left RUNNING return at once, and every (re)computed residual lands in c->r
+// and restarts the recurrence, so the host's buffer parity only matters while
+// RUNNING.  Timing samples go to slot 0.
+static int pcg64_iterate_cg1(pic_ctx* c, const double* b, double* x, hipStream_t s) {
+    const SweepGeo& g = c->geo;
+    const int K = c->p.check_every > 0 ? c->p.check_every : 16;
+    double* rb[2] = {c->r, c->t3};
+    int rcur = 0, pcur = 0;
+    if (c->timing) RETCHK(timing_events(c, (size_t)4 * K));
+    HIPCHK(launch_cg1_start(g, c->r, c->minv, c->inv_h2, c->st, c->partials, s));
+    for (;;) {
+        CgScalars& cg = c->st_host->cg;
+        if (cg.state == CG_RUNNING) {
+            const int64_t it0 = cg.iter;
+            for (int k = 0; k < K; ++k) {
+                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
+                HIPCHK(launch_cg1(g, rb[rcur], rb[rcur ^ 1], c->p2[pcur], c->p2[pcur ^ 1], x,
+                                  c->minv, c->inv_h2, c->st, c->partials, s));
+                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
+                rcur ^= 1;
+                pcur ^= 1;
+            }
+            RETCHK(read_state(c, s));
+            if (c->timing) RETCHK(timing_collect_one(c, K, c->st_host->cg.iter - it0));
+            if (c->st_host->cg.state == CG_RUNNING && c->st_host->cg.iter == it0)
+                return fail(PIC_ERR_STATE, "solver made no progress (iteration %lld)",
+                            (long long)it0);
+            continue;
+        }
+        if (cg.state == CG_CANDIDATE) {
+            HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 0, c->p.rtol, c->p.max_iter,
+                                     c->st, c->partials, s));
+            HIPCHK(launch_cg1_start(g, c->r, c->minv, c->inv_h2, c->st, c->partials, s));
+            rcur = 0;
+            RETCHK(read_state(c, s));
+            continue;
+        }
+        return PIC_OK;  // CONVERGED, MAXIT, BREAKDOWN, ZERO_RHS
+    }
+}
 
 // Runs batches of (direction, update) sweeps until the device state leaves
 // RUNNING; handles candidate verification (residual replacement).
 static int pcg64_iterate(pic_ctx* c, const double* b, double* x, hipStream_t s) {
+    if (use_cg1(c)) return pcg64_iterate_cg1(c, b, x, s);
     const SweepGeo& g = c->geo;
     const int K = c->p.check_every > 0 ? c->p.check_every : 16;
     int cur = 0;
@@ -376,6 +438,7 @@ static int solve_fp64(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
 static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* out, hipStream_t s) {
     RETCHK(ensure_mixed(c));
     const SweepGeo& g = c->geo;
+    const bool one = use_cg1(c);
     const int K = c->p.check_every > 0 ? c->p.check_every : 16;
     HIPCHK(launch_sum(c->n3, b, c->st, c->partials, 1, s));
     hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, c->st, (int32_t)CG_RUNNING);
@@ -409,10 +472,37 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
                                 (c->p.flags & PIC_FLAG_MIXED_RELIABLE) ? 1 : 0, c->p.inner_rtol,
                                 c->p.max_inner, c->st, c->partials, s));
         RETCHK(read_state(c, s));
+        // single-reduction inner sweeps: the residual alternates between r32
+        // and the (here unused) FP64 scratch vector viewed as FP32; a fresh
+        // inner solve starts with the start reduction, a continued one with
+        // a direction sweep (the carried direction and its exact curvature)
+        float* rb32[2] = {c->r32, (float*)c->t3};
+        int rcur = 0, pgiven = 0;
+        if (one && c->st_host->cg.state == CG_RUNNING) {
+            if (c->st_host->cg.restart) {
+                HIPCHK(launch_cg1_start32(g, c->r32, c->minvf, c->inv_h2f, c->st, c->partials, s));
+            } else {
+                HIPCHK(launch_dir32(g, c->r32, c->p32[cur], c->p32[cur ^ 1], c->minvf, c->inv_h2f,
+                                    c->st, c->partials, s));
+                cur ^= 1;
+                pgiven = 1;
+            }
+        }
         const int cur0 = cur;
         while (c->st_host->cg.state == CG_RUNNING) {
             const int64_t it0 = c->st_host->cg.iter;
             for (int k = 0; k < K; ++k) {
+                if (one) {
+                    if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
+                    HIPCHK(launch_cg1_32(g, rb32[rcur], rb32[rcur ^ 1], c->p32[cur], c->p32[cur ^ 1],
+                                         c->d32, c->minvf, c->inv_h2f, pgiven, c->st, c->partials,
+                                         s));
+                    if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
+                    pgiven = 0;
+                    rcur ^= 1;
+                    cur ^= 1;
+                    continue;
+                }
                 if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
                 HIPCHK(launch_dir32(g, c->r32, c->p32[cur], c->p32[cur ^ 1], c->minvf, c->inv_h2f,
                                     c->st, c->partials, s));
@@ -424,13 +514,17 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
                 cur ^= 1;
             }
             RETCHK(read_state(c, s));
-            if (c->timing) RETCHK(timing_collect(c, K, c->st_host->cg.iter - it0));
+            if (c->timing) {
+                if (one) RETCHK(timing_collect_one(c, K, c->st_host->cg.iter - it0));
+                else RETCHK(timing_collect(c, K, c->st_host->cg.iter - it0));
+            }
             if (c->st_host->cg.state == CG_RUNNING && c->st_host->cg.iter == it0)
                 return fail(PIC_ERR_STATE, "inner solver made no progress");
         }
         inner_total += c->st_host->cg.iter;
         // the last direction written (the next inner solve may continue it):
-        // each active iteration's direction sweep wrote p32[cur ^ 1]
+        // each active iteration's direction sweep (or single sweep) wrote
+        // p32[cur ^ 1]
         cur = cur0 ^ (int)(c->st_host->cg.iter & 1);
         if (c->st_host->cg.state == CG_BREAKDOWN) {
             // an FP32 breakdown still leaves a usable correction; the next outer

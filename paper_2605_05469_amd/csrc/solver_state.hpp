@@ -72,6 +72,23 @@ hipError_t launch_dir64(const SweepGeo& g, const double* r, const double* p_old,
                         double minv, double inv_h2, DevState* st, double* partials, hipStream_t s);
 hipError_t launch_upd64(const SweepGeo& g, const double* p_new, double* x, double* r,
                         double minv, double inv_h2, DevState* st, double* partials, hipStream_t s);
+// Single-reduction (Chronopoulos-Gear) Jacobi-PCG, periodic box: the start
+// reduction after a (re)computed residual, then one sweep per iteration
+// (r_in/r_out and p_in/p_out alternate between two buffers; x in place).
+bool cg1_supported(const SweepGeo& g);
+hipError_t launch_cg1_start(const SweepGeo& g, const double* r, double minv, double inv_h2,
+                            DevState* st, double* partials, hipStream_t s);
+hipError_t launch_cg1(const SweepGeo& g, const double* r_in, double* r_out, const double* p_in,
+                      double* p_out, double* x, double minv, double inv_h2, DevState* st,
+                      double* partials, hipStream_t s);
+// The same in FP32 for the inner solve of the mixed form (d: the inner
+// solution); pgiven: p_in already holds this step's direction (a direction
+// sweep formed it and its curvature: the continued first step).
+hipError_t launch_cg1_start32(const SweepGeo& g, const float* r, float minvf, float inv_h2f,
+                              DevState* st, double* partials, hipStream_t s);
+hipError_t launch_cg1_32(const SweepGeo& g, const float* r_in, float* r_out, const float* p_in,
+                         float* p_out, float* d, float minvf, float inv_h2f, int pgiven,
+                         DevState* st, double* partials, hipStream_t s);
 // Mixed-precision pieces.
 hipError_t launch_outer_resid(const SweepGeo& g, const double* b, const double* x, double* r,
                               double inv_h2, DevState* st, double* partials, double tol,

@@ -410,6 +410,46 @@ struct OpUpd {
     __device__ double* partials() const { return part; }
 };
 
+// Start of the single-reduction form after a (re)computed residual: reduce
+// r.r, gamma = r.M^{-1} r and delta = (M^{-1} r).A (M^{-1} r) with the same
+// expressions as the single-reduction sweep; the first step takes
+// p = M^{-1} r and alpha = gamma / delta.
+template <class V>
+struct OpCg1Start {
+    using T = V;
+    using In = V;
+    using Own = Nothing;
+    static constexpr int NACC = 3;
+    const V* r;
+    V minv, inv_h2;
+    DevState* st;
+    double* part;
+    __device__ bool active() const { return st->cg.state == CG_RUNNING && st->cg.restart; }
+    __device__ void prepare() {}
+    __device__ V fetch(size_t g) const { return r[g]; }
+    __device__ V make(V v, size_t, bool) const { return v; }
+    __device__ Nothing pre(size_t) const { return Nothing{}; }
+    __device__ void out(const Nothing&, size_t, V rv, V xm, V xp, V ym, V yp, V zm, V zp,
+                        double (&acc)[3]) const {
+        const V ar = apply_A<V>(rv, xm, xp, ym, yp, zm, zp, inv_h2);
+        const V u = minv * rv;
+        acc[0] += (double)rv * (double)rv;
+        acc[1] += (double)rv * (double)u;
+        acc[2] += (double)u * (double)(minv * ar);
+    }
+    __device__ void finish(double (&t)[3]) const {
+        CgScalars& cg = st->cg;
+        cg.rz = t[1];
+        cg.pq = t[2];
+        cg.alpha = t[1] / t[2];
+        cg.beta = 0.0;
+        cg.restart = 1;
+        if (!(t[2] > 0.0) || !isfinite(cg.alpha)) cg.state = CG_BREAKDOWN;
+    }
+    __device__ uint32_t* ticket() const { return &st->tickets[1]; }
+    __device__ double* partials() const { return part; }
+};
+
 // Mixed form, outer step: r = b - A x in FP64; reduce r.r; the last block
 // decides.  (The correction x += ||r_prev|| d is a separate pass before it:
 // a sweep never writes the array it stages, because neighbouring workgroups
@@ -769,6 +809,243 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int bounded, int
     }
 }
 
+// --------------------------------------------------------------------------
+// Single-reduction Jacobi-PCG sweep: the arrangement of Chronopoulos and
+// Gear, which produces the same iterates as the direction + update pair in
+// exact arithmetic but needs one reduction per iteration.  From r_k, p_{k-1},
+// x_k and the scalars alpha_k, beta_k one sweep forms
+//   p_k = M^{-1} r_k + beta_k p_{k-1},  x_{k+1} = x_k + alpha_k p_k,
+//   r_{k+1} = r_k - alpha_k A p_k,
+// and reduces, with u = M^{-1} r_{k+1} and q = A p_k,
+//   r.r,  gamma = r.u,  delta = u.A u,  sigma = u.q,  pi = p_k.q;
+// the last block forms beta_{k+1} = gamma_{k+1} / gamma_k and
+//   alpha_{k+1} = gamma_{k+1} / p_{k+1}.A p_{k+1},
+//   p_{k+1}.A p_{k+1} = delta + 2 beta sigma + beta^2 pi
+// (the expansion of p_{k+1} = u + beta p_k; Chronopoulos and Gear shorten it
+// to delta - beta gamma / alpha_k by the orthogonality of the residuals,
+// which a continued inner solve of the mixed form does not keep exactly).
+// Each of r, p, x is read once and written once: 48 bytes per grid point and
+// iteration against 64 for the pair.
+//
+// Tiling: a TX x TY tile of (x, y) marches over its share of the z planes.
+// A r_{k+1} at the tile needs r_{k+1} on a one-point ring, which needs p_k on
+// a two-point ring; every stage is evaluated on the whole (TX+4) x (TY+4)
+// region (the outer values are never used), so each thread owns the same
+// region points at every stage and plane, keeps their z neighbours in
+// registers and passes only in-plane neighbours through LDS.  At step j the
+// block forms p_k(j) (staged two planes ahead), r_{k+1}(j), and the outputs
+// of plane j-1.  Two LDS slots per stage leave one barrier per plane.  The
+// padded border of each LDS plane is never written (zero), which keeps the
+// region edge's reads in bounds.  Periodic box only: r_in and p_in are read
+// as halos by neighbouring blocks and are never written here.
+// V = double: the FP64 solve; V = float: the inner solve of the mixed form
+// (dot products accumulated in FP64 as in the two-sweep form).  pgiven: p_in
+// already holds p_k (formed, with its exact p.A p, by a direction sweep: the
+// first step of an inner solve that continues the previous direction).
+template <class V, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nbz,
+                                                  const V* __restrict__ r_in,
+                                                  V* __restrict__ r_out,
+                                                  const V* __restrict__ p_in,
+                                                  V* __restrict__ p_out, V* x, V minv, V inv_h2,
+                                                  DevState* st, double* part, int pgiven) {
+    constexpr int W0 = TX + 4, H0 = TY + 4;
+    constexpr int WP = W0 + 2, HP = H0 + 2;
+    constexpr int PLANE = WP * HP;
+    constexpr int NP = (W0 * H0 + NT - 1) / NT;
+    __shared__ V lp[2][PLANE];
+    __shared__ V lr[2][PLANE];
+    __shared__ double red[5 * (NT / kWave)];
+    __shared__ int lflag;
+    if (st->cg.state != CG_RUNNING) return;
+    const int restart = st->cg.restart;
+    const V alpha = (V)st->cg.alpha;
+    const V beta = (V)st->cg.beta;
+
+    const int tid = threadIdx.x;
+    const uint32_t nb = (uint32_t)(nbx * nby * nbz);
+    const uint32_t lb = remap_xcd(blockIdx.x, nb);
+    const int bx = (int)(lb % nbx), by = (int)((lb / nbx) % nby), bz = (int)(lb / (nbx * nby));
+    const int x0 = bx * TX, y0 = by * TY;
+    const int z0 = (int)(((int64_t)bz * n) / nbz);
+    const int z1 = (int)((((int64_t)bz + 1) * n) / nbz);
+    const size_t nn = (size_t)n * n;
+    auto wrap = [n](int v) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+
+    int pofs[NP];       // padded LDS offset of region point k, -1: none
+    uint32_t goff[NP];  // its in-plane global offset (periodic image)
+    uint32_t ownm = 0;  // bit k: point k is in the tile
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int e = tid + k * NT;
+        pofs[k] = -1;
+        goff[k] = 0;
+        if (e < W0 * H0) {
+            const int lx = e % W0, ly = e / W0;
+            pofs[k] = (ly + 1) * WP + lx + 1;
+            goff[k] = (uint32_t)wrap(y0 - 2 + ly) * (uint32_t)n + (uint32_t)wrap(x0 - 2 + lx);
+            if (lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2) ownm |= 1u << k;
+        }
+    }
+    for (int i = tid; i < 2 * PLANE; i += NT) {
+        (&lp[0][0])[i] = V(0);
+        (&lr[0][0])[i] = V(0);
+    }
+
+    V ldr[NP], ldp[NP];  // r_k, p_{k-1} (p_k if pgiven) of the plane being staged
+    auto fetch = [&](int zr) {
+        const size_t zo = (size_t)wrap(zr) * nn;
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            ldr[k] = V(0);
+            ldp[k] = V(0);
+            if (pofs[k] < 0) continue;
+            ldr[k] = r_in[zo + goff[k]];
+            if (!restart) ldp[k] = p_in[zo + goff[k]];
+        }
+    };
+    // p_k from the staged loads, in the direction sweep's order
+    auto dir = [&](int k) {
+        if (pgiven) return ldp[k];
+        V v = minv * ldr[k];
+        if (!restart) v = v + beta * ldp[k];
+        return v;
+    };
+    V pm[NP], pc[NP], pn[NP];  // p_k at planes j-1, j, j+1
+    V rc[NP], rn[NP];          // r_k at planes j, j+1
+    V s2[NP], s1[NP];          // r_{k+1} at planes j-2, j-1
+    V xo[NP], xn[NP];          // x_k at planes j-1, j (tile points)
+    V qm[NP];                  // A p_k at plane j-1
+    fetch(z0 - 2);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) pm[k] = dir(k);
+    fetch(z0 - 1);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        pc[k] = dir(k);
+        rc[k] = ldr[k];
+    }
+    fetch(z0);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        pn[k] = dir(k);
+        rn[k] = ldr[k];
+        s2[k] = s1[k] = xo[k] = xn[k] = qm[k] = V(0);
+    }
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    __syncthreads();  // LDS cleared before the first stores
+
+    const int nsteps = z1 - z0 + 2;  // j = z0 - 1 .. z1
+    for (int s = 0; s < nsteps; ++s) {
+        const int j = z0 - 1 + s;
+        const int slot = s & 1;
+        V* LP = lp[slot];
+        V* LR = lr[slot];
+        const V* LRo = lr[slot ^ 1];
+#pragma unroll
+        for (int k = 0; k < NP; ++k)
+            if (pofs[k] >= 0) LP[pofs[k]] = pc[k];
+        if (j + 2 <= z1 + 1) fetch(j + 2);
+        if (j >= z0 && j < z1) {
+            const size_t zo = (size_t)j * nn;
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                if ((ownm >> k) & 1u) xn[k] = ld_own(x + zo + goff[k]);
+        }
+        __syncthreads();
+        // r_{k+1}(j) on the region
+        V r1[NP], q1[NP];
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            r1[k] = q1[k] = V(0);
+            if (pofs[k] < 0) continue;
+            const int pi = pofs[k];
+            q1[k] = apply_A<V>(pc[k], LP[pi - 1], LP[pi + 1], LP[pi - WP], LP[pi + WP], pm[k],
+                               pn[k], inv_h2);
+            r1[k] = rc[k] - alpha * q1[k];
+            LR[pi] = r1[k];
+        }
+        // outputs of plane j-1 (its in-plane r_{k+1} neighbours were stored
+        // in the previous step, before this step's barrier)
+        if (j - 1 >= z0 && j - 1 < z1) {
+            const size_t zo = (size_t)(j - 1) * nn;
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                if (!((ownm >> k) & 1u)) continue;
+                const int pi = pofs[k];
+                const V rv = s1[k];
+                const V ar = apply_A<V>(rv, LRo[pi - 1], LRo[pi + 1], LRo[pi - WP], LRo[pi + WP],
+                                        s2[k], r1[k], inv_h2);
+                const V u = minv * rv;
+                acc[0] += (double)rv * (double)rv;
+                acc[1] += (double)rv * (double)u;
+                acc[2] += (double)u * (double)(minv * ar);
+                acc[3] += (double)u * (double)qm[k];
+                acc[4] += (double)pm[k] * (double)qm[k];
+                const size_t g = zo + goff[k];
+                st_own(xo[k] + alpha * pm[k], x + g);
+                st_own(rv, r_out + g);
+                st_own(pm[k], p_out + g);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            s2[k] = s1[k];
+            s1[k] = r1[k];
+            qm[k] = q1[k];
+            pm[k] = pc[k];
+            pc[k] = pn[k];
+            rc[k] = rn[k];
+            xo[k] = xn[k];
+            pn[k] = dir(k);
+            rn[k] = ldr[k];
+        }
+    }
+
+    block_sum<NT, 5>(acc, red);
+    if (tid == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) part[(size_t)k * nb + lb] = acc[k];
+    }
+    if (last_block(&st->tickets[2], nb, &lflag)) {
+        double t[5];
+        sum_partials<NT, 5>(part, (int)nb, t, red);
+        if (tid == 0) {
+            CgScalars& cg = st->cg;
+            cg.rz_prev = cg.rz;
+            cg.iter += 1;
+            cg.rr = t[0];
+            const double rn2 = sqrt(t[0]);
+            if (!isfinite(rn2)) {
+                cg.state = CG_BREAKDOWN;
+                return;
+            }
+            if (rn2 <= cg.tol) {
+                cg.state = CG_CANDIDATE;
+                return;
+            }
+            const double b = t[1] / cg.rz;
+            const double den = t[2] + 2.0 * b * t[3] + b * b * t[4];
+            if (den > 0.0 && isfinite(den)) {
+                cg.beta = b;
+                cg.alpha = t[1] / den;
+                cg.pq = den;
+                cg.restart = 0;
+            } else {
+                // p.A p lost to cancellation: restart from p = M^{-1} r
+                // (its curvature is delta)
+                cg.beta = 0.0;
+                cg.alpha = t[1] / t[2];
+                cg.pq = t[2];
+                cg.restart = 1;
+                if (!(t[2] > 0.0) || !isfinite(cg.alpha)) cg.state = CG_BREAKDOWN;
+            }
+            cg.rz = t[1];
+            if (cg.state == CG_RUNNING && cg.iter >= cg.max_iter) cg.state = CG_MAXIT;
+        }
+    }
+}
+
 // Field: E = -grad (phi - mean) from the gauge-fixed values, W_x =
 // (1/2) h^3 sum Ex^2.  phi itself is shifted by a separate pass afterwards.
 struct OpField {
@@ -978,6 +1255,80 @@ hipError_t launch_upd64(const SweepGeo& g, const double* p_new, double* x, doubl
                         double inv_h2, DevState* st, double* partials, hipStream_t s) {
     OpUpd<double> op{p_new, x, r, minv, inv_h2, st, partials, 0.0};
     return launch_sweep(op, g, s);
+}
+
+bool cg1_supported(const SweepGeo& g) { return g.bc == 0 && g.n % 32 == 0 && g.n >= 32; }
+
+hipError_t launch_cg1_start(const SweepGeo& g, const double* r, double minv, double inv_h2,
+                            DevState* st, double* partials, hipStream_t s) {
+    OpCg1Start<double> op{r, minv, inv_h2, st, partials};
+    return launch_sweep(op, g, s);
+}
+
+hipError_t launch_cg1_start32(const SweepGeo& g, const float* r, float minvf, float inv_h2f,
+                              DevState* st, double* partials, hipStream_t s) {
+    OpCg1Start<float> op{r, minvf, inv_h2f, st, partials};
+    return launch_sweep(op, g, s);
+}
+
+// One resident wave of workgroups: TX x TY tiles, the z planes of each tile
+// column split evenly over nbz blocks.  Shapes measured at 512^3 (FP64):
+// 64 x 32 tiles of 512 threads and 128 x 16 x 512 alike (one workgroup per
+// CU, 2 waves per SIMD, halo ring 1.2-1.3x the tile), 8% faster than
+// 64 x 16 x 256, which beats 64 x 16 x 512 and 64 x 32 x 1024 by 6% and
+// 32 x 16 x 256 and 64 x 8 x 256 by 20%; FP32: 64 x 32 x 1024 5% faster than
+// 64 x 16 x 256.
+template <class V, int TX, int TY, int NT>
+static hipError_t cg1_t(int n, const V* r_in, V* r_out, const V* p_in, V* p_out, V* x, V minv,
+                        V inv_h2, DevState* st, double* partials, int pgiven, hipStream_t s) {
+    static int occ = 0, cus = 0;
+    if (occ == 0) {
+        int o = 0, c = 0, dev = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, cg1_kernel<V, TX, TY, NT>, NT, 0) !=
+                hipSuccess || o < 1)
+            o = 1;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            c < 1)
+            c = 1;
+        cus = c;
+        occ = o;
+    }
+    const int nbx = n / TX, nby = n / TY;
+    const int tiles = nbx * nby;
+    int nbz = occ * cus / tiles;
+    // five partials per block in the partials array (4 x kMaxSweepBlocks)
+    constexpr int kMaxBlocks = 4 * kMaxSweepBlocks / 5;
+    if (nbz > kMaxBlocks / tiles) nbz = kMaxBlocks / tiles;
+    if (nbz > n / 4) nbz = n / 4;
+    if (nbz < 1) nbz = 1;
+    const int nb = tiles * nbz;
+    if (nb > kMaxBlocks) return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL((cg1_kernel<V, TX, TY, NT>), dim3(nb), dim3(NT), 0, s, n, nbx, nby, nbz,
+                       r_in, r_out, p_in, p_out, x, minv, inv_h2, st, partials, pgiven);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg1(const SweepGeo& g, const double* r_in, double* r_out, const double* p_in,
+                      double* p_out, double* x, double minv, double inv_h2, DevState* st,
+                      double* partials, hipStream_t s) {
+    if (!cg1_supported(g)) return hipErrorInvalidValue;
+    if (g.n % 64 == 0)
+        return cg1_t<double, 64, 32, 512>(g.n, r_in, r_out, p_in, p_out, x, minv, inv_h2, st,
+                                          partials, 0, s);
+    return cg1_t<double, 32, 16, 256>(g.n, r_in, r_out, p_in, p_out, x, minv, inv_h2, st, partials,
+                                      0, s);
+}
+
+hipError_t launch_cg1_32(const SweepGeo& g, const float* r_in, float* r_out, const float* p_in,
+                         float* p_out, float* d, float minvf, float inv_h2f, int pgiven,
+                         DevState* st, double* partials, hipStream_t s) {
+    if (!cg1_supported(g)) return hipErrorInvalidValue;
+    if (g.n % 64 == 0)
+        return cg1_t<float, 64, 32, 1024>(g.n, r_in, r_out, p_in, p_out, d, minvf, inv_h2f, st,
+                                          partials, pgiven, s);
+    return cg1_t<float, 32, 16, 256>(g.n, r_in, r_out, p_in, p_out, d, minvf, inv_h2f, st,
+                                     partials, pgiven, s);
 }
 
 hipError_t launch_dir32(const SweepGeo& g, const float* r, const float* p_old, float* p_new,

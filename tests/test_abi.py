@@ -49,7 +49,7 @@ def test_abi_version_and_errors_without_gpu(lib):
     assert lib.pic_workspace_bytes(ctypes.byref(p)) > 3 * 8 * 32 ** 3
     h = ctypes.c_void_p()
     for field, bad in (("n", 33), ("n", 16), ("n", 2048), ("rtol", 0.0), ("length", -1.0),
-                       ("solver", 7), ("np_max", -5), ("flags", 64),
+                       ("solver", 7), ("np_max", -5), ("flags", 128),
                        ("ssor_omega", 2.5), ("ssor_inner", -1), ("bc", 3), ("bc", -1)):
         q = P.landau_params(32, 8)
         setattr(q, field, bad)

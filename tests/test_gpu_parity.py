@@ -214,9 +214,14 @@ def _rhs(orc, N, ppc, seed):
     return b
 
 
+@pytest.mark.parametrize("two_sweep", [False, True])
 @pytest.mark.parametrize("N", [32, 64, 96])
-def test_pcg_fp64_parity(pic, orc, N):
-    ctx, p = _ctx(pic, N, 8, np_max=0, check_every=8)
+def test_pcg_fp64_parity(pic, orc, N, two_sweep):
+    """Both arrangements of Jacobi-PCG on the GPU (the single-reduction sweep,
+    64- and 32-wide tiles, and the direction + update pair) against the
+    oracle's textbook recurrences."""
+    ctx, p = _ctx(pic, N, 8, np_max=0, check_every=8,
+                  flags=pic.FLAG_PCG_TWO_SWEEP if two_sweep else 0)
     b = _rhs(orc, N, 8, 6000 + N)
     x0 = np.zeros(N ** 3)
     db, dx = _dev(b), _dev(x0)
