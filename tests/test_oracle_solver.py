@@ -273,3 +273,43 @@ def test_fcg_fallback_on_bad_preconditioner(orc, bad):
     assert info["converged"] and info["true_rel_res"] <= 1e-10
     if bad != "noise":
         assert info["fell_back"]
+
+
+def test_single_reduction_arrangement_reproduces_textbook_pcg(orc):
+    """The GPU's single-reduction arrangement of Jacobi-PCG (one set of dot
+    products per iteration: r.r, gamma = r.u, delta = u.A u, sigma = u.A p,
+    pi = p.A p with u = M^{-1} r; alpha = gamma / (delta + 2 beta sigma +
+    beta^2 pi)), written out here with the oracle's operator, takes the same
+    iterations as the oracle's textbook recurrences and reaches the same
+    solution to rounding (host check of the recurrence the sweep uses)."""
+    N = 16
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=77)
+    b, nb = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    h = P.L / N
+    minv = h * h / 6.0
+    x = np.zeros(N ** 3)
+    r = b.copy()
+    u = minv * r
+    gamma, delta = r @ u, u @ orc.apply_A(N, P.L, u)
+    alpha, beta = gamma / delta, 0.0
+    p = np.zeros(N ** 3)
+    it = 0
+    while True:
+        p = minv * r + beta * p
+        q = orc.apply_A(N, P.L, p)
+        x = x + alpha * p
+        r = r - alpha * q
+        it += 1
+        if np.linalg.norm(r) <= 1e-10 * nb or it >= 5000:
+            break
+        u = minv * r
+        g1 = r @ u
+        d1, s1, p1 = u @ orc.apply_A(N, P.L, u), u @ q, p @ q
+        beta = g1 / gamma
+        alpha = g1 / (d1 + 2 * beta * s1 + beta * beta * p1)
+        gamma = g1
+    ref, info = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 5000)
+    assert info["converged"] and info["replacements"] == 0
+    assert it == info["iters"]
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
