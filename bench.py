@@ -43,7 +43,8 @@ SINGLE_SWEEP_BYTES = 48
 # HBM bytes per launch of the dominant kernel at 512^3, from rocprofv3
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
-SWEEP_TRAFFIC = {(512, "pcg_fp64", "pcg_update_sweep"): 5.571e9}
+SWEEP_TRAFFIC = {(512, "pcg_fp64", "pcg_update_sweep"): 5.571e9,
+                 (512, "pcg_fp64", "pcg_single_sweep"): 7.037e9}
 
 
 def log(*a):
