@@ -852,7 +852,15 @@ __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nb
     constexpr int W0 = TX + 4, H0 = TY + 4;
     constexpr int WP = W0 + 2, HP = H0 + 2;
     constexpr int PLANE = WP * HP;
-    constexpr int NP = (W0 * H0 + NT - 1) / NT;
+    // Region points per thread.  With tiles a multiple of 64 wide each wave
+    // takes 64 aligned columns of one row of the tile (whole cache lines for
+    // the loads and the stores) and the spare waves of the last slot take the
+    // four halo columns; otherwise points are dealt out in row-major order.
+    constexpr bool ROWS = TX % kWave == 0;
+    constexpr int NW = NT / kWave;
+    constexpr int SEG = TX / kWave;  // wave segments per row
+    constexpr int NP = ROWS ? (H0 * SEG + (4 * H0 + kWave - 1) / kWave + NW - 1) / NW
+                            : (W0 * H0 + NT - 1) / NT;
     __shared__ V lp[2][PLANE];
     __shared__ V lr[2][PLANE];
     __shared__ double red[5 * (NT / kWave)];
@@ -877,11 +885,30 @@ __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nb
     uint32_t ownm = 0;  // bit k: point k is in the tile
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int e = tid + k * NT;
+        int lx = -1, ly = -1;
+        if constexpr (ROWS) {
+            const int unit = k * NW + tid / kWave, lane = tid % kWave;
+            if (unit < H0 * SEG) {
+                lx = 2 + (unit % SEG) * kWave + lane;
+                ly = unit / SEG;
+            } else {
+                const int e = (unit - H0 * SEG) * kWave + lane;  // halo column entry
+                if (e < 4 * H0) {
+                    const int c = e & 3;
+                    lx = c < 2 ? c : TX + c;  // columns 0, 1, TX+2, TX+3
+                    ly = e >> 2;
+                }
+            }
+        } else {
+            const int e = tid + k * NT;
+            if (e < W0 * H0) {
+                lx = e % W0;
+                ly = e / W0;
+            }
+        }
         pofs[k] = -1;
         goff[k] = 0;
-        if (e < W0 * H0) {
-            const int lx = e % W0, ly = e / W0;
+        if (ly >= 0) {
             pofs[k] = (ly + 1) * WP + lx + 1;
             goff[k] = (uint32_t)wrap(y0 - 2 + ly) * (uint32_t)n + (uint32_t)wrap(x0 - 2 + lx);
             if (lx >= 2 && lx < TX + 2 && ly >= 2 && ly < TY + 2) ownm |= 1u << k;
@@ -1276,8 +1303,9 @@ hipError_t launch_cg1_start32(const SweepGeo& g, const float* r, float minvf, fl
 // 64 x 32 tiles of 512 threads and 128 x 16 x 512 alike (one workgroup per
 // CU, 2 waves per SIMD, halo ring 1.2-1.3x the tile), 8% faster than
 // 64 x 16 x 256, which beats 64 x 16 x 512 and 64 x 32 x 1024 by 6% and
-// 32 x 16 x 256 and 64 x 8 x 256 by 20%; FP32: 64 x 32 x 1024 5% faster than
-// 64 x 16 x 256.
+// 32 x 16 x 256 and 64 x 8 x 256 by 20%; FP32: 128 x 16 x 512 4% faster than
+// 64 x 32 x 1024, which beats 64 x 16 x 256 by 5% and 64 x 32 x 512 by 12%
+// (these with points dealt out in row-major order).
 template <class V, int TX, int TY, int NT>
 static hipError_t cg1_t(int n, const V* r_in, V* r_out, const V* p_in, V* p_out, V* x, V minv,
                         V inv_h2, DevState* st, double* partials, int pgiven, hipStream_t s) {
@@ -1324,6 +1352,9 @@ hipError_t launch_cg1_32(const SweepGeo& g, const float* r_in, float* r_out, con
                          float* p_out, float* d, float minvf, float inv_h2f, int pgiven,
                          DevState* st, double* partials, hipStream_t s) {
     if (!cg1_supported(g)) return hipErrorInvalidValue;
+    if (g.n % 128 == 0)
+        return cg1_t<float, 128, 16, 512>(g.n, r_in, r_out, p_in, p_out, d, minvf, inv_h2f, st,
+                                          partials, pgiven, s);
     if (g.n % 64 == 0)
         return cg1_t<float, 64, 32, 1024>(g.n, r_in, r_out, p_in, p_out, d, minvf, inv_h2f, st,
                                           partials, pgiven, s);

@@ -298,7 +298,7 @@ def test_mixed_precision_reaches_tolerance(pic, orc):
     assert abs(minfo["inner"] - info["iterations"]) <= 2 * info["outer_iterations"]
 
 
-@pytest.mark.parametrize("N,inner_rtol", [(64, 1e-1), (96, 1e-2)])
+@pytest.mark.parametrize("N,inner_rtol", [(64, 1e-1), (96, 1e-2), (128, 1e-1)])
 def test_mixed_reliable_matches_oracle(pic, orc, N, inner_rtol):
     """Reliable updates: the inner direction carries over between refinements;
     same refinement count as the oracle, inner count within a few per step."""
