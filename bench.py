@@ -44,7 +44,7 @@ SINGLE_SWEEP_BYTES = 48
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
 SWEEP_TRAFFIC = {(512, "pcg_fp64", "pcg_update_sweep"): 5.571e9,
-                 (512, "pcg_fp64", "pcg_single_sweep"): 7.037e9}
+                 (512, "pcg_fp64", "pcg_single_sweep"): 6.645e9}
 
 
 def log(*a):
