@@ -681,7 +681,11 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int bounded, int
     constexpr int W0 = TX + K, H0 = TY + K;
     constexpr int WP = W0 + 1, HP = H0 + 1;  // padded plane
     constexpr int PLANE = WP * HP;
-    constexpr int NP0 = (W0 * H0 + kNT - 1) / kNT;
+    // Region points per thread: TX consecutive lanes take the TX tile columns
+    // of one region row (whole cache lines for the loads and the stores); the
+    // spare lane groups of the last slot take the K halo columns.
+    constexpr int GPS = kNT / TX;  // row groups per slot
+    constexpr int NP0 = (H0 + (K * H0 + TX - 1) / TX + GPS - 1) / GPS;
     __shared__ double lds[K][PLANE];
     __shared__ double red[kNT / kWave];
     __shared__ int lflag;
@@ -709,11 +713,21 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int bounded, int
     uint32_t zerom = 0;       // bit k: point k lies outside a bounded grid
 #pragma unroll
     for (int k = 0; k < NP0; ++k) {
-        const int e = tid + k * kNT;
+        const int unit = k * GPS + tid / TX, lane = tid % TX;
+        int lx = -1, ly = -1;
+        if (unit < H0) {
+            lx = (DIR == 0 ? K : 0) + lane;  // the tile's columns
+            ly = unit;
+        } else {
+            const int e = (unit - H0) * TX + lane;  // halo column entry
+            if (e < K * H0) {
+                lx = (DIR == 0 ? 0 : TX) + e % K;
+                ly = e / K;
+            }
+        }
         pofs[k] = -1;
         goff[k] = 0;
-        if (e < W0 * H0) {
-            const int lx = e % W0, ly = e / W0;
+        if (ly >= 0) {
             const int rx = ax + lx, ry = ay + ly;
             pofs[k] = PO + ly * WP + lx;
             goff[k] = (uint32_t)gmap(ry) * (uint32_t)n + (uint32_t)gmap(rx);
