@@ -1319,7 +1319,8 @@ hipError_t launch_cg1_start32(const SweepGeo& g, const float* r, float minvf, fl
 // 64 x 16 x 256, which beats 64 x 16 x 512 and 64 x 32 x 1024 by 6% and
 // 32 x 16 x 256 and 64 x 8 x 256 by 20%; FP32: 128 x 16 x 512 4% faster than
 // 64 x 32 x 1024, which beats 64 x 16 x 256 by 5% and 64 x 32 x 512 by 12%
-// (these with points dealt out in row-major order).
+// (these with points dealt out in row-major order; with whole rows per wave
+// 64 x 32 x 1024 and 128 x 16 x 512 are within 1%).
 template <class V, int TX, int TY, int NT>
 static hipError_t cg1_t(int n, const V* r_in, V* r_out, const V* p_in, V* p_out, V* x, V minv,
                         V inv_h2, DevState* st, double* partials, int pgiven, hipStream_t s) {
