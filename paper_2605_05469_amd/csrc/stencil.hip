@@ -85,7 +85,10 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
     constexpr int PX = TX + 2;
     constexpr int PY = kTY + 2;
     constexpr int PLANE = PX * PY;
-    constexpr int NE = (PLANE + kNT - 1) / kNT;  // staged entries per thread
+    // staged entries per thread (whole-row dealing for 64-wide tiles, below)
+    constexpr int NE = TX == kWave
+                           ? (PY + (2 * PY + kWave - 1) / kWave + kNT / kWave - 1) / (kNT / kWave)
+                           : (PLANE + kNT - 1) / kNT;
     constexpr int RPT = kNT / TX;                // thread rows
     constexpr int PPT = kTY / RPT;               // own points per thread per plane
     __shared__ T buf[2][PLANE];
@@ -117,17 +120,42 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
         if (bc == 0) return v < 0 ? v + n : v - n;
         return v < 0 ? 0 : n - 1;
     };
+    // With 64-wide tiles each wave stages the 64 tile columns of one plane
+    // row (whole cache lines) and the spare waves of the last slot the two
+    // halo columns; otherwise entries are dealt out in row-major order.
     uint32_t eoff[NE];
+    int eidx[NE];  // LDS index of entry j in the staged plane, -1: none
     uint32_t eown = 0, ezero = 0;
 #pragma unroll
     for (int j = 0; j < NE; ++j) {
-        const int e = tid + j * kNT;
-        const int ly = e / PX;
-        const int lxx = e - ly * PX;
+        int ly = -1, lxx = 0;
+        if constexpr (TX == kWave) {
+            const int unit = j * (kNT / kWave) + tid / kWave, lane = tid % kWave;
+            if (unit < PY) {
+                ly = unit;
+                lxx = 1 + lane;
+            } else {
+                const int e2 = (unit - PY) * kWave + lane;
+                if (e2 < 2 * PY) {
+                    ly = e2 >> 1;
+                    lxx = (e2 & 1) ? TX + 1 : 0;
+                }
+            }
+        } else {
+            const int e = tid + j * kNT;
+            if (e < PLANE) {
+                ly = e / PX;
+                lxx = e - ly * PX;
+            }
+        }
+        eidx[j] = -1;
+        eoff[j] = 0;
+        if (ly < 0) continue;
+        eidx[j] = ly * PX + lxx;
         const int rx = x0 + lxx - 1, ry = y0 + ly - 1;
         const int gx = gmap(rx), gy = gmap(ry);
         eoff[j] = (uint32_t)gy * (uint32_t)n + (uint32_t)gx;
-        if (e < PLANE && lxx >= 1 && lxx <= TX && ly >= 1 && ly <= kTY) eown |= 1u << j;
+        if (lxx >= 1 && lxx <= TX && ly >= 1 && ly <= kTY) eown |= 1u << j;
         if (bc == 1 && (rx != gx || ry != gy)) ezero |= 1u << j;
     }
     auto zwrap = [&gmap](int z) { return gmap(z); };
@@ -147,7 +175,7 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
         const size_t zo = (size_t)gz * nn;
 #pragma unroll
         for (int j = 0; j < NE; ++j)
-            if (tid + j * kNT < PLANE) fin[j] = op.fetch(zo + eoff[j]);
+            if (eidx[j] >= 0) fin[j] = op.fetch(zo + eoff[j]);
     };
     // zr: the plane's coordinate before the boundary rule
     auto commit_plane = [&](T* dst, int zr, bool ownz) {
@@ -155,8 +183,8 @@ __global__ __launch_bounds__(kNT) void sweep_kernel(Op op_in, SweepGeo g) {
         const uint32_t zmask = zzero(zr) ? ~0u : ezero;
 #pragma unroll
         for (int j = 0; j < NE; ++j) {
-            const int e = tid + j * kNT;
-            if (e < PLANE)
+            const int e = eidx[j];
+            if (e >= 0)
                 dst[e] = ((zmask >> j) & 1u) ? T(0)
                                              : op.make(fin[j], zo + eoff[j], ownz && ((eown >> j) & 1u));
         }
