@@ -158,8 +158,19 @@ typedef struct pic_solve_info {
     double wx;                 /* (1/2) h^3 sum Ex^2 if the field was computed  */
     int32_t converged;         /* 1 if rel_res <= rtol                          */
     int32_t replacements;      /* residual replacements performed               */
-    int32_t fell_back;         /* learned: switched to Jacobi-PCG               */
+    int32_t fell_back;         /* learned: switched to Jacobi-PCG; mixed: the
+                                  progress stop handed the solve to FP64
+                                  Jacobi-PCG (3 refinements in a row without
+                                  bringing the true residual below 0.9 times
+                                  the smallest so far)                        */
     int32_t warm_start_used;   /* learned: network warm start accepted          */
+    int32_t gap_restarts;      /* mixed, reliable form: refinements whose
+                                  carried direction the residual-gap test
+                                  refused (true reduction more than 4 times
+                                  the inner solve's recursive one)            */
+    int32_t reserved;
+    int64_t fp64_iterations;   /* mixed: FP64 PCG iterations after the progress
+                                  stop (included in `iterations`)            */
 } pic_solve_info;
 
 typedef struct pic_particle_arrays {

@@ -86,7 +86,7 @@ def lib():
         L.or_pcg_ssor_bc.argtypes = [c_int, c_dbl, c_int, _dp, _dp, c_dbl, c_i64, c_dbl, c_int,
                                      c_int, _dp]
         L.or_mixed_pcg_ex.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_dbl, c_i64,
-                                      ctypes.c_int, _dp]
+                                      ctypes.c_int, c_i64, _dp]
         L.or_deposit_vertices.argtypes = [c_i64, c_int, c_dbl, c_dbl, _dp, _dp, _dp, c_i64, _i64p, _dp]
         L.or_fcg.argtypes = [c_int, c_dbl, _dp, _dp, c_dbl, c_i64, c_int, PRECOND_FN,
                              ctypes.c_void_p, _dp]
@@ -232,16 +232,20 @@ def gather_scalar(N, L, x, y, z, F) -> np.ndarray:
 
 
 def mixed_pcg(N, L, b, x0, rtol, max_outer=50, inner_rtol=1e-3, max_inner=20000,
-              reliable=False):
+              reliable=False, max_iter=20000):
     """FP32-inner / FP64-outer refinement; `reliable` keeps the inner
-    direction across refinements (reliable updates) instead of restarting."""
+    direction across refinements (reliable updates) instead of restarting.
+    `refused`: refinements whose carried direction the residual-gap test
+    refused; `switched`: the progress stop handed the solve to FP64 PCG,
+    which took `fp64_iters` iterations (at most max_iter)."""
     b = _f64(b).reshape(-1)
     x = _f64(x0).reshape(-1).copy()
-    info = np.zeros(4)
+    info = np.zeros(7)
     lib().or_mixed_pcg_ex(N, L, b, x, rtol, max_outer, inner_rtol, max_inner,
-                          1 if reliable else 0, info)
+                          1 if reliable else 0, max_iter, info)
     return x, dict(outer=int(info[0]), inner=int(info[1]), true_rel_res=info[2],
-                   converged=bool(info[3]))
+                   converged=bool(info[3]), refused=int(info[4]), switched=bool(info[5]),
+                   fp64_iters=int(info[6]))
 
 
 def fcg(N, L, b, x0, rtol, max_iter, precond, window=10):

@@ -703,12 +703,25 @@ static double or_dot32(int64_t n, const float *a, const float *b)
  * tight inner tolerance.  So the direction is carried only if the
  * refinement's true reduction nr'/nr is within a factor 4 of the inner
  * solve's recursive one ||r~_in|| / ||r~_0||; otherwise the inner solve
- * restarts from p = M r.
+ * restarts from p = M r.  (This is a residual-gap test in the sense of van
+ * der Vorst and Ye, SIAM J. Sci. Comput. 22 (2000): the gap between the
+ * true residual nr' and the recursively updated one, rec * nr, is at least
+ * nr' - rec * nr, so the test refuses the carry once that lower bound of the
+ * gap exceeds three times the recursive residual.  The factor is this
+ * library's choice.)
+ * Progress stop: a refinement makes progress when its true residual falls
+ * below 0.9 times the smallest one so far; after 3 refinements in a row
+ * without progress the refinement loop ends and FP64 Jacobi-PCG (or_pcg)
+ * finishes the solve from the current x with at most max_iter iterations.
  * info: [0]=outer steps, [1]=total inner iterations, [2]=true rel. residual,
- *       [3]=converged.                                                    */
+ *       [3]=converged, [4]=refinements whose carried direction the gap test
+ *       refused (reliable form), [5]=1 if the progress stop switched to FP64
+ *       PCG, [6]=FP64 PCG iterations after that switch.                   */
+#define OR_MIXED_STALL 3
+#define OR_MIXED_PROGRESS 0.9
 void or_mixed_pcg_ex(int N, double L, const double *b, double *x, double rtol,
                      int64_t max_outer, double inner_rtol, int64_t max_inner, int reliable,
-                     double *info)
+                     int64_t max_iter, double *info)
 {
     int64_t n3 = (int64_t)N * N * N;
     double inv_h = (double)N / L;
@@ -724,18 +737,25 @@ void or_mixed_pcg_ex(int N, double L, const double *b, double *x, double rtol,
     int converged = 0;
     double nb = sqrt(or_dot(n3, b, b));
     double trel = 0.0;
+    for (int k = 0; k < 7; ++k) info[k] = 0.0;
     if (nb == 0.0) {
         for (int64_t i = 0; i < n3; ++i) x[i] = 0.0;
-        info[0] = 0; info[1] = 0; info[2] = 0.0; info[3] = 1;
+        info[3] = 1;
         free(r); free(ri); free(d); free(p); free(q); free(zz);
         return;
     }
     int have_dir = 0;        /* reliable form: p holds the last direction */
     double rz_last = 0.0, nr_prev = 0.0, rec_last = 0.0;
+    double best = 0.0;       /* smallest true residual so far */
+    int stall = 0, switched = 0;
+    int64_t refused = 0;
     for (;;) {
         double nr = or_true_residual(N, L, 0, b, x, r);
         trel = nr / nb;
         if (nr <= rtol * nb) { converged = 1; break; }
+        if (!isfinite(nr)) break;
+        if (outer == 0 || nr < OR_MIXED_PROGRESS * best) { best = nr; stall = 0; }
+        else if (++stall >= OR_MIXED_STALL) { switched = 1; break; }
         if (outer >= max_outer) break;
         ++outer;
         double sc = 1.0 / nr;
@@ -744,7 +764,10 @@ void or_mixed_pcg_ex(int N, double L, const double *b, double *x, double rtol,
         for (int64_t i = 0; i < n3; ++i) zz[i] = minvf * ri[i];
         double rz = or_dot32(n3, ri, zz);
         /* carry the direction only while the replacement is consistent */
-        if (have_dir && !(nr <= 4.0 * rec_last * nr_prev)) have_dir = 0;
+        if (have_dir && !(nr <= 4.0 * rec_last * nr_prev)) {
+            have_dir = 0;
+            if (reliable) ++refused;
+        }
         double bc = reliable && have_dir ? (nr / nr_prev) * (rz / rz_last) : 0.0;
         if (reliable && have_dir && isfinite(bc)) {
             float bf = (float)bc;
@@ -780,14 +803,24 @@ void or_mixed_pcg_ex(int N, double L, const double *b, double *x, double rtol,
         for (int64_t i = 0; i < n3; ++i) x[i] = x[i] + nr * (double)d[i];
         nr_prev = nr;
     }
-    info[0] = (double)outer; info[1] = (double)inner_total; info[2] = trel; info[3] = converged;
     free(r); free(ri); free(d); free(p); free(q); free(zz);
+    if (switched) {
+        double pinfo[5];
+        or_pcg(N, L, b, x, rtol, max_iter, pinfo);
+        converged = (int)pinfo[3];
+        trel = pinfo[2];
+        info[6] = pinfo[0];
+    }
+    info[0] = (double)outer; info[1] = (double)inner_total; info[2] = trel; info[3] = converged;
+    info[4] = (double)refused; info[5] = switched;
 }
 
 void or_mixed_pcg(int N, double L, const double *b, double *x, double rtol,
                   int64_t max_outer, double inner_rtol, int64_t max_inner, double *info)
 {
-    or_mixed_pcg_ex(N, L, b, x, rtol, max_outer, inner_rtol, max_inner, 0, info);
+    double full[7];
+    or_mixed_pcg_ex(N, L, b, x, rtol, max_outer, inner_rtol, max_inner, 0, 20000, full);
+    for (int k = 0; k < 4; ++k) info[k] = full[k];
 }
 
 /* ------------------------------------------------------------------------ */

@@ -54,7 +54,9 @@ class pic_solve_info(ctypes.Structure):
                 ("flex_iterations", ctypes.c_int64), ("rel_res", ctypes.c_double),
                 ("norm_b", ctypes.c_double), ("wx", ctypes.c_double),
                 ("converged", ctypes.c_int32), ("replacements", ctypes.c_int32),
-                ("fell_back", ctypes.c_int32), ("warm_start_used", ctypes.c_int32)]
+                ("fell_back", ctypes.c_int32), ("warm_start_used", ctypes.c_int32),
+                ("gap_restarts", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("fp64_iterations", ctypes.c_int64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

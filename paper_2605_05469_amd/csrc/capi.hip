@@ -118,6 +118,8 @@ static int validate_params(const pic_params* p) {
         return fail(PIC_ERR_INVALID, "np_max must be in [0, 2^32)");
     if (!(p->rtol > 0.0) || !std::isfinite(p->rtol)) return fail(PIC_ERR_INVALID, "rtol must be > 0");
     if (p->max_iter < 0) return fail(PIC_ERR_INVALID, "max_iter must be >= 0");
+    if (p->max_inner < 1 || p->max_outer < 0)
+        return fail(PIC_ERR_INVALID, "max_inner must be >= 1 and max_outer >= 0");
     if (p->solver < PIC_SOLVER_PCG_FP64 || p->solver > PIC_SOLVER_PIF)
         return fail(PIC_ERR_INVALID, "unknown solver %d", p->solver);
     if (p->pif_tol != 0.0 && pif_width(p->pif_tol) == 0)
@@ -261,6 +263,7 @@ static int read_state(pic_ctx* c, hipStream_t s) {
 __global__ void state_init_kernel(DevState* st, int32_t outer_state) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         st->outer_state = outer_state;
+        st->gap_restarts = 0;
         st->cg.state = CG_RUNNING;
         st->cg.iter = 0;
         st->cg.replacements = 0;
@@ -434,6 +437,13 @@ static int solve_fp64(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
 }
 
 // ---------------------------------------------------------- mixed form -----
+// FP32 inner Jacobi-PCG inside FP64 iterative refinement (not in the paper).
+// The refinement loop ends when the FP64 true residual meets the tolerance,
+// after max_outer refinements, or when kMixedStall refinements in a row fail
+// to bring it below kMixedProgress times the smallest so far; FP64 Jacobi-PCG
+// (max_iter iterations) then finishes from the current iterate.
+constexpr int kMixedStall = 3;
+constexpr double kMixedProgress = 0.9;
 
 static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* out, hipStream_t s) {
     RETCHK(ensure_mixed(c));
@@ -455,6 +465,12 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
     const double tol = c->p.rtol * nb;
     int64_t outer = 0, inner_total = 0;
     int cur = 0;
+    // progress stop: a refinement makes progress when its true residual falls
+    // below kMixedProgress times the smallest so far; after kMixedStall
+    // refinements in a row without progress FP64 Jacobi-PCG finishes the solve
+    double best = 0.0;
+    int stall = 0;
+    bool switched = false;
     if (c->timing) RETCHK(timing_events(c, (size_t)4 * K));
     for (;;) {
         if (outer > 0) HIPCHK(launch_update_x(c->n3, x, c->d32, c->st, s));
@@ -464,6 +480,13 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
         if (!std::isfinite(nr)) break;
         if (nr <= tol) {
             out->converged = 1;
+            break;
+        }
+        if (outer == 0 || nr < kMixedProgress * best) {
+            best = nr;
+            stall = 0;
+        } else if (++stall >= kMixedStall) {
+            switched = true;
             break;
         }
         if (outer >= c->p.max_outer) break;
@@ -534,6 +557,18 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
     out->iterations = inner_total;
     out->outer_iterations = outer;
     out->rel_res = c->st_host->out_nr / nb;
+    out->gap_restarts = c->st_host->gap_restarts;
+    if (switched) {
+        pic_solve_info pi;
+        std::memset(&pi, 0, sizeof pi);
+        RETCHK(solve_fp64(c, b, x, &pi, s));
+        out->fell_back = 1;
+        out->fp64_iterations = pi.iterations;
+        out->iterations = inner_total + pi.iterations;
+        out->replacements += pi.replacements;
+        out->rel_res = pi.rel_res;
+        out->converged = pi.converged;
+    }
     return PIC_OK;
 }
 
@@ -908,7 +943,7 @@ static int field(pic_ctx* c, double* phi, double* ex, double* ey, double* ez, hi
 
 extern "C" {
 
-int pic_abi_version(void) { return 1; }
+int pic_abi_version(void) { return 2; }
 
 const char* pic_last_error(void) { return g_err.c_str(); }
 

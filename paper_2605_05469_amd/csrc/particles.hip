@@ -10,11 +10,14 @@
 // then x; v += (dt*qm)*E; x = wrap(x + dt*v)), so keys, positions and
 // velocities match the oracle bit for bit given the same field.
 //
-// Deposit on cell-sorted particles is written as a gather over the eight
-// cells around each vertex: every vertex sums its contributions in one fixed
-// order (cells in increasing key order, particles in sorted order) -- no
-// atomics, deterministic, and the same accumulation order as a sequential
-// scatter over the sorted particle list.
+// Deposit on cell-sorted particles, without atomics: each cell's particles
+// are summed in sorted order into the cell's eight corner sums, the two cells
+// of a row that touch a vertex are added, and each vertex adds its four cell
+// rows in increasing key order.  The result is deterministic and every term
+// is the oracle's (the same weight products), but the association differs
+// from a sequential scatter over the sorted particles: the two agree within
+// 2 gamma(n_v) of the vertex's weight sum (n_v particles in the eight cells
+// around the vertex, gamma(n) = n u / (1 - n u)), not bit for bit.
 #include "common.hpp"
 #include "particles.hpp"
 #include "particle_math.hpp"

@@ -49,7 +49,7 @@ struct DevState {
     double flex_rr;    // learned: r . r
     double prev_nr;    // mixed: ||r|| of the previous outer step (reliable updates)
     int32_t outer_state;
-    int32_t pad;
+    int32_t gap_restarts;  // mixed: carried directions the residual-gap test refused
     uint32_t tickets[8];
 };
 

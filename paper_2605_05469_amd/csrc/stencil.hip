@@ -1191,10 +1191,14 @@ __global__ __launch_bounds__(kNT) void convert32_kernel(int64_t n3, const double
             // carry the direction only while the refinement's true reduction
             // stays within a factor 4 of the last inner solve's recursive one
             // (FP32 drift of about eps32 kappa makes the replaced residual
-            // inconsistent with the recursion at tight inner tolerances)
+            // inconsistent with the recursion at tight inner tolerances): a
+            // residual-gap test, the gap between the true and the recursive
+            // residual being at least out_nr - rec * prev_nr
             const double rec = sqrt(cg.rr) / cg.nb;
-            const bool cont = reliable && (cg.state == CG_CANDIDATE || cg.state == CG_MAXIT) &&
-                              st->prev_nr > 0.0 && st->out_nr <= 4.0 * rec * st->prev_nr;
+            const bool ended = reliable && (cg.state == CG_CANDIDATE || cg.state == CG_MAXIT) &&
+                               st->prev_nr > 0.0;
+            const bool cont = ended && st->out_nr <= 4.0 * rec * st->prev_nr;
+            if (ended && !cont) st->gap_restarts += 1;
             const double bt = cont ? (st->out_nr / st->prev_nr) * (tot[1] / cg.rz_prev) : 0.0;
             cg.nb = n0;
             cg.tol = inner_rtol * n0;

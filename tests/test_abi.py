@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_abi_version_and_errors_without_gpu(lib):
     import paper_2605_05469_amd as P
-    assert lib.pic_abi_version() >= 1
+    assert lib.pic_abi_version() == 2
     p = P.landau_params(32, 8)
     assert lib.pic_workspace_bytes(ctypes.byref(p)) > 3 * 8 * 32 ** 3
     h = ctypes.c_void_p()

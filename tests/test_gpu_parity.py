@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2605_05469_amd import synth
+from deposit_bound import check_deposit
 
 pytestmark = pytest.mark.gpu
 
@@ -163,12 +164,16 @@ def test_deposit_sorted_and_atomic(pic, orc, N, ppc):
     keys = orc.cell_keys(N, p.length, *parts[:3])
     perm, cs = orc.sort_by_key(keys, N ** 3)
     xs = [a[perm] for a in parts[:3]]
-    ref_b, ref_nb = orc.deposit(N, p.length, p.charge, p.rho_bg, *xs)
+    ref_b, ref_nb, rho_e = orc.deposit(N, p.length, p.charge, p.rho_bg, *xs, want_rho_e=True)
     d = [_dev(a) for a in xs]
     rho = torch.empty(N ** 3, dtype=torch.float64, device="cuda")
     nb = ctx.deposit(*d, _dev(cs.astype(np.uint32).view(np.int32)), rho, want_norm=True)
     got = _host(rho)
     scale = np.abs(ref_b).max()
+    # same terms, summed per cell, per cell row and per vertex (GPU) instead
+    # of sequentially over the sorted particles (oracle): within the
+    # association bound of every vertex
+    check_deposit(N, got, ref_b, rho_e, p.rho_bg, np.diff(cs))
     assert np.max(np.abs(got - ref_b)) <= 1e-13 * scale
     assert abs(nb - ref_nb) <= 1e-12 * ref_nb
     # unsorted path (atomics): same values up to summation order
@@ -215,13 +220,18 @@ def _rhs(orc, N, ppc, seed):
 
 
 @pytest.mark.parametrize("two_sweep", [False, True])
-@pytest.mark.parametrize("N", [32, 64, 96])
+@pytest.mark.parametrize("N", [32, 64, 96, 128])
 def test_pcg_fp64_parity(pic, orc, N, two_sweep):
     """Both arrangements of Jacobi-PCG on the GPU (the single-reduction sweep,
     64- and 32-wide tiles, and the direction + update pair) against the
-    oracle's textbook recurrences."""
-    ctx, p = _ctx(pic, N, 8, np_max=0, check_every=8,
-                  flags=pic.FLAG_PCG_TWO_SWEEP if two_sweep else 0)
+    oracle's textbook recurrences.  At 128^3 the 64 x 32 tiles of the
+    single-reduction sweep (the 512^3 launch shape) sit two to a row, so
+    halos cross tiles in x and y.  When the two sides stop one iteration
+    apart (dot products summed in another order), the side that ran longer is
+    run again with the other's count, so the iterates are always compared
+    after the same number of iterations."""
+    flags = pic.FLAG_PCG_TWO_SWEEP if two_sweep else 0
+    ctx, p = _ctx(pic, N, 8, np_max=0, check_every=8, flags=flags)
     b = _rhs(orc, N, 8, 6000 + N)
     x0 = np.zeros(N ** 3)
     db, dx = _dev(b), _dev(x0)
@@ -232,8 +242,17 @@ def test_pcg_fp64_parity(pic, orc, N, two_sweep):
     got = _host(dx)
     # true residual under the oracle's operator
     assert orc.residual_norm(N, p.length, b, got) <= p.rtol * np.linalg.norm(b)
-    if info["iterations"] == rinfo["iters"]:
-        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+    m = min(info["iterations"], rinfo["iters"])
+    if rinfo["iters"] > m:
+        ref, rinfo = orc.pcg(N, p.length, b, x0, p.rtol, m)
+        assert rinfo["iters"] == m
+    elif info["iterations"] > m:
+        ctx_m, _ = _ctx(pic, N, 8, np_max=0, check_every=8, flags=flags, max_iter=m)
+        dx = _dev(x0)
+        info_m = ctx_m.poisson(db, dx)
+        assert info_m["iterations"] == m
+        got = _host(dx)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
 def test_pcg_warm_start_and_zero_rhs(pic, orc):
@@ -318,6 +337,57 @@ def test_mixed_reliable_matches_oracle(pic, orc, N, inner_rtol):
     assert info["iterations"] <= 1.3 * pinfo["iters"]
 
 
+@pytest.mark.parametrize("N,inner_rtol,fires", [(32, 1e-6, True), (64, 1e-6, True),
+                                                (32, 1e-1, False), (64, 1e-1, False)])
+def test_mixed_gap_restarts_match_oracle(pic, orc, N, inner_rtol, fires):
+    """The residual-gap test of the reliable form: it refuses to carry the
+    inner direction when the FP32 drift (eps32 kappa) exceeds the inner
+    tolerance, on the GPU as in the oracle, and never at a loose tolerance."""
+    ctx, p = _ctx(pic, N, 8, np_max=0, solver="pcg_mixed", inner_rtol=inner_rtol,
+                  flags=pic.FLAG_MIXED_RELIABLE)
+    b = _rhs(orc, N, 8, 6700 + N)
+    dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.poisson(_dev(b), dx)
+    assert info["converged"] and not info["fell_back"], info
+    assert orc.residual_norm(N, p.length, b, _host(dx)) <= p.rtol * np.linalg.norm(b)
+    _, minfo = orc.mixed_pcg(N, p.length, b, np.zeros(N ** 3), p.rtol, inner_rtol=inner_rtol,
+                             max_inner=p.max_inner, reliable=True)
+    assert minfo["converged"] and not minfo["switched"]
+    assert (info["gap_restarts"] > 0) == fires == (minfo["refused"] > 0), (info, minfo)
+    assert abs(info["gap_restarts"] - minfo["refused"]) <= 1
+    assert abs(minfo["outer"] - info["outer_iterations"]) <= 1
+
+
+@pytest.mark.parametrize("reliable", [False, True])
+def test_mixed_progress_stop_matches_oracle(pic, orc, reliable):
+    """One inner iteration per refinement stalls the refinement loop; after
+    three refinements without progress FP64 Jacobi-PCG finishes the solve, on
+    the GPU as in the oracle.  An unattainable tolerance ends in
+    PIC_NOT_CONVERGED after max_iter FP64 iterations, not after max_outer
+    refinements of max_inner inner iterations."""
+    N = 32
+    flags = pic.FLAG_MIXED_RELIABLE if reliable else 0
+    ctx, p = _ctx(pic, N, 8, np_max=0, solver="pcg_mixed", inner_rtol=1e-3, max_inner=1,
+                  flags=flags)
+    b = _rhs(orc, N, 8, 6800)
+    dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.poisson(_dev(b), dx)
+    assert info["converged"] and info["fell_back"], info
+    assert orc.residual_norm(N, p.length, b, _host(dx)) <= p.rtol * np.linalg.norm(b)
+    _, minfo = orc.mixed_pcg(N, p.length, b, np.zeros(N ** 3), p.rtol, inner_rtol=1e-3,
+                             max_inner=1, reliable=reliable)
+    assert minfo["switched"] and minfo["converged"]
+    assert info["outer_iterations"] == minfo["outer"]
+    assert abs(info["fp64_iterations"] - minfo["fp64_iters"]) <= 1
+    assert info["iterations"] == info["outer_iterations"] + info["fp64_iterations"]
+    ctx2, p2 = _ctx(pic, N, 8, np_max=0, solver="pcg_mixed", inner_rtol=0.1, rtol=1e-17,
+                    max_iter=300, flags=pic.FLAG_MIXED_RELIABLE)
+    dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    info = ctx2.poisson(_dev(b), dx)
+    assert info["status"] == 1 and not info["converged"] and info["fell_back"], info
+    assert info["fp64_iterations"] == 300 and info["outer_iterations"] < 50
+
+
 @pytest.mark.parametrize("unfused", [False, True])
 @pytest.mark.parametrize("N,inner,outer", [(32, 4, 2), (64, 4, 2), (64, 2, 1), (96, 3, 2),
                                            (64, 1, 3)])
@@ -387,3 +457,59 @@ def test_step_parity_config0(pic, orc):
     assert key_mismatch == 0
     phi = _host(sim.phi)
     assert np.linalg.norm(phi - st.phi) <= 1e-9 * np.linalg.norm(st.phi)
+
+
+def test_mixed_form_error_vs_fp64_oracle(pic, orc):
+    """The mixed form (FP32 inner solves inside FP64 refinement, reliable
+    updates) driving the PIC loop beside the FP64 oracle from the same
+    particles, 64^3 x 8 ppc, 6 steps.  Both solves stop at relative residual
+    1e-10, so their solutions may differ by up to ||A^+|| (||r_m|| + ||r_o||):
+    relative to ||phi|| at most 2 kappa rtol, kappa = 3 / sin^2(pi/N).  The
+    field differs by at most ||grad_h|| <= sqrt(3)/h times the potential's
+    difference, and the leapfrog carries the gathered field's difference
+    into positions as dt^2 |q/m| summed twice over the steps (doubled for
+    the gather at displaced positions).  The errors are printed and held to
+    these bounds; keys stay identical."""
+    N, ppc, nsteps = 64, 8, 6
+    p = pic.landau_params(N, ppc, solver="pcg_mixed", inner_rtol=0.1,
+                          flags=pic.FLAG_MIXED_RELIABLE)
+    ctx = pic.Context(p)
+    parts = _landau(N, ppc, 20300)
+    sim = pic.Simulation(ctx, *[_dev(a) for a in parts])
+    st = orc.State(N, p.length, p.charge, p.qm, p.dt, *parts)
+    gi = sim.init()
+    st.init(p.rtol, p.max_iter)
+    assert gi["converged"]
+    h = p.length / N
+    kappa = 3.0 / math.sin(math.pi / N) ** 2
+    bound_phi = 2.0 * kappa * p.rtol
+    dx_bound, dv_bound = 0.0, 0.0
+    errs = []
+    for s in range(nsteps + 1):
+        if s > 0:
+            g = sim.step()
+            st.step(p.rtol, p.max_iter)
+            assert g["converged"] and g["outer_iterations"] >= 1
+        phi = _host(sim.phi)
+        e_phi = np.linalg.norm(phi - st.phi) / np.linalg.norm(st.phi)
+        dE = [_host(a) - r for a, r in zip((sim.ex, sim.ey, sim.ez), (st.ex, st.ey, st.ez))]
+        nE = math.sqrt(sum(float(np.dot(r, r)) for r in (st.ex, st.ey, st.ez)))
+        e_E = math.sqrt(sum(float(np.dot(d, d)) for d in dE)) / nE
+        bound_E = bound_phi * (math.sqrt(3.0) / h) * np.linalg.norm(st.phi) / nE
+        x = [_host(a) for a in sim.particles[:3]]
+        dxs = [np.abs(a - r) for a, r in zip(x, (st.x, st.y, st.z))]
+        dxs = [np.minimum(d, p.length - d) for d in dxs]  # periodic distance
+        e_x = max(float(d.max()) for d in dxs) / h
+        errs.append((s, e_phi, e_E, e_x))
+        assert e_phi <= bound_phi, (s, e_phi, bound_phi)
+        assert e_E <= bound_E, (s, e_E, bound_E)
+        assert e_x <= dx_bound / h + 1e-15, (s, e_x, dx_bound / h)
+        # the next step's push: dv += dt |qm| max|dE| (doubled), dx += dt dv
+        maxdE = max(float(np.abs(d).max()) for d in dE)
+        dv_bound += 2.0 * p.dt * abs(p.qm) * maxdE
+        dx_bound += p.dt * dv_bound
+    for s, a, b, c in errs:
+        print("step %d: phi %.2e  E %.2e  max|dx|/h %.2e" % (s, a, b, c))
+    gk = orc.cell_keys(N, p.length, *[_host(a) for a in sim.particles[:3]])
+    ok = orc.cell_keys(N, p.length, st.x, st.y, st.z)
+    assert np.array_equal(gk, ok)

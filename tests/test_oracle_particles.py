@@ -261,3 +261,26 @@ def test_deposit_vertices_matches_full_deposit(orc):
     vid = np.array([0, 7, 63, 64, 200, N ** 3 - 1])
     got = orc.deposit_vertices(N, P.L, P.q, *parts[:3], vid)
     assert np.allclose(got, re[vid], rtol=1e-13, atol=1e-13 * np.abs(re).max())
+
+
+def test_deposit_order_bound_holds_and_is_tight(orc):
+    """The association bound used to compare two deposits that add the same
+    terms in different orders: an unsorted and a sorted oracle deposit of the
+    same particles stay within it, and dropping one particle (a deposit that
+    is wrong by a single weight) breaks it."""
+    from deposit_bound import check_deposit
+    N, ppc = 32, 8
+    P = synth.LandauParams(N=N, ppc=ppc)
+    parts = synth.landau_particles_np(N, ppc, seed=41)
+    keys = orc.cell_keys(N, P.L, *parts[:3])
+    perm, cs = orc.sort_by_key(keys, N ** 3)
+    xs = [a[perm] for a in parts[:3]]
+    b_sorted, _, rho_e = orc.deposit(N, P.L, P.q, P.rho_bg, *xs, want_rho_e=True)
+    rng = np.random.default_rng(2)
+    shuf = rng.permutation(xs[0].size)
+    b_shuf, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *[a[shuf] for a in xs])
+    assert not np.array_equal(b_shuf, b_sorted)  # the order does change bits
+    check_deposit(N, b_shuf, b_sorted, rho_e, P.rho_bg, np.diff(cs))
+    b_drop, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *[a[1:] for a in xs])
+    with pytest.raises(AssertionError):
+        check_deposit(N, b_drop, b_sorted, rho_e, P.rho_bg, np.diff(cs))

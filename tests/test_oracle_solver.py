@@ -227,6 +227,62 @@ def test_mixed_reliable_updates_keep_cg_convergence(orc, inner_rtol):
     assert abs(rel["outer"] - rst["outer"]) <= 1
 
 
+def test_mixed_gap_test_fires_when_fp32_drift_exceeds_inner_tolerance(orc):
+    """The reliable form carries the inner direction across a refinement only
+    while the refinement's true reduction is within 4x the inner solve's
+    recursive one.  FP32 inner solves drift from their true residual by about
+    eps32 * kappa(A) (1.9e-5 at 32^3): an inner tolerance of 1e-6 lies below
+    that drift, so the test must refuse a carry; at 1e-1 (above it) it must
+    never fire.  Either way the solve reaches the FP64 tolerance under an
+    operator applied independently of the oracle (FFT)."""
+    N = 32
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=17)
+    b, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    kappa = 3.0 / math.sin(math.pi / N) ** 2
+    drift = float(np.finfo(np.float32).eps) * kappa
+    assert 1e-6 < drift < 1e-1
+    for inner_rtol, fires in ((1e-6, True), (1e-7, True), (1e-1, False), (1e-2, False)):
+        x, info = orc.mixed_pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, inner_rtol=inner_rtol,
+                                reliable=True)
+        assert info["converged"] and not info["switched"], info
+        assert (info["refused"] > 0) == fires, (inner_rtol, info)
+        r = b - _fft_apply(N, P.L, x)
+        assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(b)
+    # the restarted form never carries a direction, so nothing is refused
+    _, rst = orc.mixed_pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, inner_rtol=1e-6)
+    assert rst["converged"] and rst["refused"] == 0
+
+
+def test_mixed_progress_stop_hands_over_to_fp64_pcg(orc):
+    """Three refinements in a row that do not bring the FP64 true residual
+    below 0.9x the best so far end the refinement loop; FP64 Jacobi-PCG then
+    finishes from the current iterate.  With one inner iteration per
+    refinement the loop stalls (CG's residual norm is not monotone); with an
+    unattainable tolerance (1e-17, below FP64 rounding of the residual) the
+    loop stops long before max_outer and the FP64 solve reports failure."""
+    N = 32
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=17)
+    b, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    _, pinfo = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 20000)
+    for reliable in (False, True):
+        x, info = orc.mixed_pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, inner_rtol=1e-3,
+                                max_inner=1, reliable=reliable)
+        assert info["switched"] and info["converged"], info
+        assert info["inner"] == info["outer"] <= 10
+        assert 0 < info["fp64_iters"] <= pinfo["iters"] + 10
+        r = b - _fft_apply(N, P.L, x)
+        assert np.linalg.norm(r) <= 1.0001e-10 * np.linalg.norm(b)
+    _, info = orc.mixed_pcg(N, P.L, b, np.zeros(N ** 3), 1e-17, inner_rtol=0.1, reliable=True,
+                            max_iter=300)
+    assert info["switched"] and not info["converged"] and info["fp64_iters"] == 300
+    assert info["outer"] < 50
+    # an ordinary solve never takes the stop
+    _, info = orc.mixed_pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, inner_rtol=0.1, reliable=True)
+    assert info["converged"] and not info["switched"] and info["fp64_iters"] == 0
+
+
 def _fft_apply(N, L, u):
     h = L / N
     m = np.arange(N)
