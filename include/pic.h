@@ -245,6 +245,24 @@ int pic_deposit_cic(pic_ctx *ctx, int64_t np, const double *x, const double *y,
                     const double *z, const uint32_t *cell_start, double *rho,
                     double *norm_b, void *stream);
 
+/* No-allocation deposit, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): pic_deposit_cic without a context.  The scratch (four n^3 FP64
+ * row-sum arrays, reduction partials and state, about 8.1 MiB) is a static
+ * device array of the library sized for n <= PIC_NOALLOC_MAX_N, held by every
+ * GPU the library runs on until the process ends; the call allocates nothing.
+ * `params` supplies n, length, charge, rho_bg and bc (periodic only); the
+ * other fields are ignored.  Arguments, layout, ownership and results as in
+ * pic_deposit_cic (the same kernels: the same bits).  n > PIC_NOALLOC_MAX_N,
+ * a bounded box, np outside [0, 2^32) or NULL/misaligned arrays return
+ * PIC_ERR_INVALID and launch nothing.  All calls on one GPU share the scratch:
+ * calls that overlap in time on one GPU (other streams, other threads) race
+ * and must be serialised by the caller.  norm_b: host out (synchronises). */
+#define PIC_NOALLOC_MAX_N 64
+int pic_deposit_cic_noalloc(const pic_params *params, int64_t np, const double *x,
+                            const double *y, const double *z, const uint32_t *cell_start,
+                            double *rho, double *norm_b, void *stream);
+
 /* Solve (Sec. 3.2): A phi = rho with A = -Lap_h, the 7-point second-order
  * operator on the context's box (periodic unless pic_params.bc says
  * otherwise), by the solver form selected in the context, starting from the

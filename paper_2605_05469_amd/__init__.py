@@ -100,7 +100,7 @@ EXPORTS = ["pic_create", "pic_destroy", "pic_workspace_bytes", "pic_last_error",
            "pic_net_backward", "pic_net_train_step", "pic_net_precondition",
            "pic_conv3d_frag_elems", "pic_conv3d_pack", "pic_conv3d_fwd", "pic_conv3d_bwd_data",
            "pic_conv3d_wgrad_scratch_elems", "pic_conv3d_bwd_weight", "pic_adam_step",
-           "pic_pif_field"]
+           "pic_pif_field", "pic_deposit_cic_noalloc"]
 
 
 def lib():
@@ -125,6 +125,8 @@ def lib():
     L.pic_cell_keys.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     L.pic_sort_cells.argtypes = [vp, i64, vp, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, vp, vp]
     L.pic_deposit_cic.argtypes = [vp, i64, vp, vp, vp, vp, vp, ctypes.POINTER(dbl), vp]
+    L.pic_deposit_cic_noalloc.argtypes = [ctypes.POINTER(pic_params), i64, vp, vp, vp, vp, vp,
+                                          ctypes.POINTER(dbl), vp]
     L.pic_poisson_pcg.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(pic_solve_info), vp]
     L.pic_gather_push.argtypes = [vp, i64] + [vp] * 10 + [vp]
     L.pic_half_kick.argtypes = [vp, i64] + [vp] * 9 + [vp]
@@ -368,6 +370,20 @@ class Simulation:
         d = info.as_dict()
         d["status"] = rc
         return d
+
+
+NOALLOC_MAX_N = 64  # PIC_NOALLOC_MAX_N
+
+
+def deposit_cic_noalloc(params, x, y, z, cell_start, rho, want_norm=False, stream=None):
+    """pic_deposit_cic_noalloc: the deposit without a context (static scratch,
+    n <= NOALLOC_MAX_N); returns ||rho|| when want_norm."""
+    nb = ctypes.c_double(0.0)
+    _check(lib().pic_deposit_cic_noalloc(ctypes.byref(params), 0 if x is None else x.numel(),
+                                         _ptr(x), _ptr(y), _ptr(z), _ptr(cell_start), _ptr(rho),
+                                         ctypes.byref(nb) if want_norm else None,
+                                         _stream(stream)))
+    return nb.value if want_norm else None
 
 
 def unet_param_count() -> int:

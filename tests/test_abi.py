@@ -67,6 +67,13 @@ def test_abi_version_and_errors_without_gpu(lib):
     assert lib.pic_gather_push(None, 0, *([None] * 10), None) == P.PIC_ERR_INVALID
     assert lib.pic_deposit_cic(None, 0, None, None, None, None, None, None, None) == P.PIC_ERR_INVALID
     assert lib.pic_set_flags(None, 0) == P.PIC_ERR_INVALID
+    # the no-allocation deposit refuses grids beyond its static scratch
+    for n in (128, 16, 33):
+        q = P.landau_params(n, 1)
+        assert lib.pic_deposit_cic_noalloc(ctypes.byref(q), 0, None, None, None, None, None, None,
+                                           None) == P.PIC_ERR_INVALID
+        assert b"n must be" in lib.pic_last_error()
+    assert lib.pic_deposit_cic_noalloc(None, 0, *([None] * 7)) == P.PIC_ERR_INVALID
 
 
 def test_single_hip_runtime_is_loaded(lib):
