@@ -37,14 +37,19 @@ SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 
                "pcg_ssor": (24, 40), "fft": (24, 40),
                "pif": (24, 40)}
 # The Jacobi-PCG single-reduction sweep (the default on the periodic box)
-# reads r, p_old, x and writes r, p, x: 48 bytes per grid point in FP64 (24 for
-# the mixed form's FP32 inner sweeps).
-SINGLE_SWEEP_BYTES = 48
+# reads r and p_old and writes r and p at every iteration, and reads and
+# writes x every other iteration (the two steps of a pair applied together):
+# 32 and 48 bytes per grid point in FP64, 40 on average over the sampled
+# pairs; the mixed form's FP32 inner sweeps likewise (their correction d
+# every other iteration): 16 and 24, 20 on average.
+SINGLE_SWEEP_BYTES = 40
+SINGLE_SWEEP_BYTES_FP32 = 20
 # HBM bytes per launch of the dominant kernel at 512^3, from rocprofv3
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
-SWEEP_TRAFFIC = {(512, "pcg_fp64", "pcg_update_sweep"): 5.571e9,
-                 (512, "pcg_fp64", "pcg_single_sweep"): 6.645e9}
+SWEEP_TRAFFIC = {(512, "pcg_fp64", "pcg_update_sweep"): 5.571e9}
+TRAFFIC_SOURCE = ("rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of this kernel "
+                  "(profiles/pcg_sweeps_landau512_hbm_counters.md)")
 
 
 def log(*a):
@@ -339,6 +344,8 @@ def main():
                          "(instead of the single-reduction sweep)")
     ap.add_argument("--warm-start-only", action="store_true",
                     help="learned form: network warm start, then Jacobi-PCG")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="default run: skip the learned + mixed form and the 32^3 line")
     ap.add_argument("--accuracy-vs-fp64", action="store_true",
                     help="rerun the same steps with the FP64 solver and report the differences")
     ap.add_argument("--workload", default="pic", choices=["pic", "poisson", "network"],
@@ -357,27 +364,165 @@ def main():
     from paper_2605_05469_amd import synth
 
     torch.cuda.set_device(0)
+    # the achievable-bandwidth reference first, on fresh device memory
+    triad = bench_triad() if args.workload == "pic" and not args.no_learned else None
     if args.workload == "poisson":
         return bench_poisson(args)
     if args.workload == "network":
         return bench_network(args)
     N, ppc = args.grid, args.ppc
-    p = P.landau_params(N, ppc, rtol=args.rtol, solver=args.solver, check_every=32,
-                        inner_rtol=args.inner_rtol)
+    flags = 0
     if args.no_warm_start:
-        p.flags |= P.FLAG_NO_WARM_START
+        flags |= P.FLAG_NO_WARM_START
     if args.warm_start_only:
-        p.flags |= P.FLAG_WARM_START_ONLY
+        flags |= P.FLAG_WARM_START_ONLY
     if args.mixed_reliable:
-        p.flags |= P.FLAG_MIXED_RELIABLE
+        flags |= P.FLAG_MIXED_RELIABLE
     if args.learned_mixed:
-        p.flags |= P.FLAG_LEARNED_MIXED
+        flags |= P.FLAG_LEARNED_MIXED
     if args.fft_spectral:
-        p.flags |= P.FLAG_FFT_SPECTRAL
+        flags |= P.FLAG_FFT_SPECTRAL
     if args.two_sweep:
-        p.flags |= P.FLAG_PCG_TWO_SWEEP
+        flags |= P.FLAG_PCG_TWO_SWEEP
+    fp32_inner = args.solver == "pcg_mixed" or args.learned_mixed
+    run = run_pic(args, args.solver, flags, args.inner_rtol, fp32_inner, "main")
+    sim, ctx, p, infos = run.pop("_sim"), run.pop("_ctx"), run.pop("_p"), run.pop("_infos")
+    out = {
+        "metric": METRIC,
+        "value": run["s_per_step"],
+        "unit": "s/step",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * run["s_per_step"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if fp32_inner else "f64",
+        "data": "synthetic",
+        "config": {"workload": "landau_damping_%d^3_%dppc_%s" % (N, ppc, args.solver),
+                   "grid": N, "ppc": ppc, "particles": ppc * N ** 3, "solver": args.solver,
+                   "rtol": args.rtol, "dt": p.dt, "k": 0.5, "alpha": 0.05,
+                   "pcg_form": run["pcg_form"], "parallelism": "single_gpu"},
+    }
+    out.update({k: v for k, v in run.items() if k not in ("s_per_step", "pcg_form")})
+    if args.accuracy_vs_fp64 and args.solver != "pcg_fp64":
+        out["accuracy_vs_fp64"] = accuracy_vs_fp64(args, sim, p)
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(N, ppc, p, sim, run["pcg_iterations_per_step"],
+                                               args.cpu_budget)
+        except Exception as e:  # the GPU line must still be printed
+            out["cpu_baseline"] = {"error": repr(e)}
+    default_run = (args.solver == "pcg_fp64" and not flags and not args.no_learned)
+    if default_run:
+        # the metric's second half: the mixed-precision + learned form on the
+        # same seeded state, same steps; then its difference from this run
+        ref = save_state(sim)
+        del sim
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+        mixed_desc = ("the mixed form: FP32 inner Jacobi-PCG (single-reduction sweeps, dot "
+                      "products in FP64), reliable updates, inner tolerance 0.1, FP64 "
+                      "refinement to the same rtol")
+        forms = (("mixed", "pcg_mixed", P.FLAG_MIXED_RELIABLE, mixed_desc),
+                 ("learned_mixed", "fcg_learned",
+                  P.FLAG_WARM_START_ONLY | P.FLAG_LEARNED_MIXED | P.FLAG_MIXED_RELIABLE,
+                  "the trained network's warm start, then " + mixed_desc))
+        for key, solver, fl, desc in forms:
+            r2 = run_pic(args, solver, fl, 0.1, True, key)
+            s2, c2, p2 = r2.pop("_sim"), r2.pop("_ctx"), r2.pop("_p")
+            infos2 = r2.pop("_infos")
+            r2["accuracy_vs_fp64"] = compare_state(s2, ref, p2)
+            if solver == "fcg_learned":
+                r2["warm_start_used_steps"] = sum(1 for i in infos2 if i["warm_start_used"])
+            r2["config"] = {"solver": solver, "form": desc, "rtol": args.rtol}
+            if solver == "fcg_learned":
+                r2["config"]["weights"] = "unet_landau128.npy"
+            out[key] = r2
+            del s2
+            c2.close()
+            del c2
+            torch.cuda.empty_cache()
+        out["learned_vs_plain"] = {
+            "plain_s_per_step": out["value"],
+            "mixed_s_per_step": out["mixed"]["s_per_step"],
+            "learned_mixed_s_per_step": out["learned_mixed"]["s_per_step"],
+            "speedup_learned_mixed": out["value"] / out["learned_mixed"]["s_per_step"],
+            "speedup_mixed": out["value"] / out["mixed"]["s_per_step"],
+            "learned_over_mixed": out["mixed"]["s_per_step"] / out["learned_mixed"]["s_per_step"]}
+        del ref
+        out["config0"] = bench_config0(args)
+        out["hbm_triad"] = triad
+    print(json.dumps(out), flush=True)
+
+
+def bench_triad():
+    """The library's STREAM triad (a = b + s c, 24 bytes per element) on
+    three 2 GiB arrays: the achievable HBM bandwidth beside the 8 TB/s peak."""
+    import torch
+
+    import paper_2605_05469_amd as P
+
+    n = 1 << 28
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.rand(n, dtype=torch.float64, device="cuda")
+    a = torch.empty_like(b)
+    ms = P.stream_triad(b, c, a, 3.0, 20)
+    ok = bool(torch.equal(a[-1024:], b[-1024:] + 3.0 * c[-1024:]))
+    del a, b, c
+    torch.cuda.empty_cache()
+    return {"kernel": "pic_stream_triad (16-byte loads and non-temporal stores)",
+            "elements": n, "bytes_per_launch": 24 * n, "avg_ms": ms,
+            "gbs": 24 * n / (ms * 1e-3) / 1e9, "frac_of_peak": 24 * n / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "checked": ok}
+
+
+def save_state(sim):
+    """Host copies of phi, E and positions (for the accuracy comparison)."""
+    return {"phi": sim.phi.cpu(), "E": [t.cpu() for t in (sim.ex, sim.ey, sim.ez)],
+            "x": [t.cpu() for t in sim.particles[:3]]}
+
+
+def compare_state(sim, ref, p):
+    """Relative L2 differences of phi and E and the largest periodic position
+    difference (in cells) against the saved FP64 state."""
+    import torch
+
+    def rel(a, b):
+        b = b.to(a.device)
+        return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+    h = p.length / p.n
+    dx, far = 0.0, 0
+    for a, b in zip(sim.particles[:3], ref["x"]):
+        d = torch.remainder(a - b.to(a.device) + 0.5 * p.length, p.length) - 0.5 * p.length
+        d = torch.abs(d)
+        far += int(torch.count_nonzero(d > 1e-6 * h))
+        dx = max(dx, float(torch.max(d)))
+        del d
+    return {"reference": "the FP64 Jacobi-PCG run of this benchmark (same seeded state, same "
+                         "steps; its solver matches the CPU oracle in the parity tests)",
+            "phi_rel_l2": rel(sim.phi, ref["phi"]),
+            "E_rel_l2": max(rel(a, b) for a, b in zip((sim.ex, sim.ey, sim.ez), ref["E"])),
+            "max_position_diff_over_h": dx / h,
+            "position_slots_differing_by_more_than_1e-6_h": far}
+
+
+def run_pic(args, solver, flags, inner_rtol, fp32_inner, label):
+    """Init (untimed), warm-up steps, then `args.steps` timed PIC steps with
+    the dominant PCG kernel sampled by HIP events on its stream."""
+    import torch
+
+    import paper_2605_05469_amd as P
+    from paper_2605_05469_amd import synth
+
+    N, ppc = args.grid, args.ppc
+    p = P.landau_params(N, ppc, rtol=args.rtol, solver=solver, check_every=32,
+                        inner_rtol=inner_rtol, flags=flags)
     ctx = P.Context(p)
-    if args.solver == "fcg_learned":
+    if solver == "fcg_learned":
         load_weights(ctx, args.weights)
     t0 = time.perf_counter()
     parts = synth.landau_particles_torch(N, ppc, seed=args.seed, device="cuda")
@@ -385,11 +530,12 @@ def main():
     del parts
     info0 = sim.init()
     torch.cuda.synchronize()
-    log("init: %.1f s, t=0 solve %d iterations" % (time.perf_counter() - t0, info0["iterations"]))
+    log("%s init: %.1f s, t=0 solve %d iterations" % (label, time.perf_counter() - t0,
+                                                       info0["iterations"]))
     for k in range(args.warmup):
         w = sim.step()
-        log("warmup %d: %d iterations, %.1f ms solve" % (k, w["iterations"], w["ms_solve"]))
-
+        log("%s warmup %d: %d iterations, %.1f ms solve" % (label, k, w["iterations"],
+                                                             w["ms_solve"]))
     ctx.set_kernel_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -402,22 +548,18 @@ def main():
     iters = sum(i["iterations"] for i in infos) / len(infos)
     n3 = N ** 3
     npart = ppc * n3
-    # the timed sweeps are the FP32 inner ones when the learned form hands over
-    # to the mixed form
-    bdir, bupd = SWEEP_BYTES["pcg_mixed" if args.learned_mixed else args.solver]
+    bdir, bupd = SWEEP_BYTES["pcg_mixed" if fp32_inner else solver]
     ms_dir, cnt_dir = P.Context.kernel_time(ctx, 0)
     ms_upd, cnt_upd = P.Context.kernel_time(ctx, 1)
-    # (pic_step accumulates the sampled kernel times over all timed steps)
     ctx.set_kernel_timing(False)
     # Jacobi-PCG (FP64, the mixed form's FP32 inner solves, the learned form's
     # hand-over) runs as one kernel per iteration on the periodic box unless
-    # --two-sweep; its launches are sampled in timing slot 0
-    single = (args.solver in ("pcg_fp64", "pcg_mixed", "fcg_learned") and not args.two_sweep
-              and N % 32 == 0)
+    # two sweeps are asked for; its launches are sampled in timing slot 0
+    single = (solver in ("pcg_fp64", "pcg_mixed", "fcg_learned")
+              and not (flags & P.FLAG_PCG_TWO_SWEEP) and N % 32 == 0)
     if single:
-        fp32 = args.solver == "pcg_mixed" or args.learned_mixed
-        b1 = SINGLE_SWEEP_BYTES // 2 if fp32 else SINGLE_SWEEP_BYTES
-        dom = "pcg_single_sweep_fp32" if fp32 else "pcg_single_sweep"
+        b1 = SINGLE_SWEEP_BYTES_FP32 if fp32_inner else SINGLE_SWEEP_BYTES
+        dom = "pcg_single_sweep_fp32" if fp32_inner else "pcg_single_sweep"
         gbs_one = b1 * n3 / (ms_dir * 1e-3) / 1e9 if ms_dir > 0 else 0.0
         kernels = {dom: {"avg_ms": ms_dir, "launches_timed": cnt_dir, "bytes_per_point": b1,
                          "gbs": gbs_one}}
@@ -434,28 +576,15 @@ def main():
     phases = {k: sum(i[k] for i in infos) / len(infos)
               for k in ("ms_push", "ms_sort", "ms_deposit", "ms_solve", "ms_field")}
     for i, inf in enumerate(infos):
-        log("step %d: %d iterations, rel_res %.2e, solve %.0f ms" % (i, inf["iterations"],
-                                                                     inf["rel_res"], inf["ms_solve"]))
-    out = {
-        "metric": METRIC,
-        "value": s_step,
-        "unit": "s/step",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * s_step,
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64" if (args.solver == "pcg_mixed" or args.learned_mixed) else "f64",
-        "data": "synthetic",
-        "config": {"workload": "landau_damping_%d^3_%dppc_%s" % (N, ppc, args.solver),
-                   "grid": N, "ppc": ppc, "particles": npart, "solver": args.solver,
-                   "rtol": args.rtol, "dt": p.dt, "k": 0.5, "alpha": 0.05,
-                   "pcg_form": "single_reduction_sweep" if single else "two_sweeps",
-                   "parallelism": "single_gpu"},
+        log("%s step %d: %d iterations, rel_res %.2e, solve %.0f ms" % (
+            label, i, inf["iterations"], inf["rel_res"], inf["ms_solve"]))
+    traffic = SWEEP_TRAFFIC.get((N, "pcg_mixed" if fp32_inner else solver, dom))
+    return {
+        "s_per_step": s_step,
+        "pcg_form": "single_reduction_sweep" if single else "two_sweeps",
         "particles_per_s": npart / s_step,
         "pcg_iterations_per_step": iters,
+        "pcg_outer_iterations_per_step": sum(i["outer_iterations"] for i in infos) / len(infos),
         "pcg_gbs_per_iteration": gbs_iter,
         "all_converged": all(i["converged"] for i in infos),
         "max_rel_res": max(i["rel_res"] for i in infos),
@@ -463,16 +592,37 @@ def main():
         "kernels": kernels,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": gbs_dom,
                      "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs_dom / PEAK_HBM_GBS,
-                     "traffic": SWEEP_TRAFFIC.get((N, args.solver, dom))},
+                     "traffic": traffic,
+                     "traffic_source": TRAFFIC_SOURCE if traffic else None},
+        "_sim": sim, "_ctx": ctx, "_p": p, "_infos": infos,
     }
-    if args.accuracy_vs_fp64 and args.solver != "pcg_fp64":
-        out["accuracy_vs_fp64"] = accuracy_vs_fp64(args, sim, p)
-    if not args.no_cpu_baseline:
-        try:
-            out["cpu_baseline"] = cpu_baseline(N, ppc, p, sim, iters, args.cpu_budget)
-        except Exception as e:  # the GPU line must still be printed
-            out["cpu_baseline"] = {"error": repr(e)}
-    print(json.dumps(out), flush=True)
+
+
+def bench_config0(args):
+    """The small configuration (32^3, 8 ppc, plain FP64 Jacobi-PCG, dt 0.05,
+    20 steps after 2 warm-up steps): seconds per step and iterations."""
+    import torch
+
+    import paper_2605_05469_amd as P
+    from paper_2605_05469_amd import synth
+
+    N, ppc, steps = 32, 8, 20
+    p = P.landau_params(N, ppc, rtol=args.rtol, check_every=32)
+    ctx = P.Context(p)
+    sim = P.Simulation(ctx, *synth.landau_particles_torch(N, ppc, seed=20260, device="cuda"))
+    sim.init()
+    for _ in range(2):
+        sim.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [sim.step() for _ in range(steps)]
+    torch.cuda.synchronize()
+    s = (time.perf_counter() - t0) / steps
+    ctx.close()
+    return {"workload": "landau_damping_32^3_8ppc_pcg_fp64", "steps": steps, "warmup": 2,
+            "s_per_step": s, "particles_per_s": ppc * N ** 3 / s,
+            "pcg_iterations_per_step": sum(i["iterations"] for i in infos) / steps,
+            "all_converged": all(i["converged"] for i in infos)}
 
 
 if __name__ == "__main__":

@@ -336,6 +336,16 @@ int pic_pif_field(pic_ctx *ctx, int64_t np, const double *x, const double *y,
 int pic_set_kernel_timing(pic_ctx *ctx, int32_t enable);
 int pic_kernel_time(pic_ctx *ctx, int32_t kernel_id, double *avg_ms, int64_t *count);
 
+/* Measurement aid (no context): the STREAM triad a = b + scalar * c over n
+ * FP64 values (device arrays, n in [1, 2^40)), two consecutive elements per
+ * thread as 16-byte accesses when the arrays allow (else one), run
+ * once untimed and then `reps` times between two HIP events on `stream`;
+ * avg_ms (host out; synchronises) receives the average time per launch.
+ * 24 bytes per element over avg_ms is the achievable HBM bandwidth that the
+ * stencil sweeps are measured against beside the nominal peak. */
+int pic_stream_triad(int64_t n, const double *b, const double *c, double *a, double scalar,
+                     int32_t reps, double *avg_ms, void *stream);
+
 /* ---- learned warm start / preconditioner -------------------------------
  * Not in the paper: this library's extension of the PCG solve of Sec. 3.2.
  * A three-level 3-D convolutional U-Net (channels 16-32-64, 3^3 periodic
@@ -379,6 +389,18 @@ int pic_net_train_step(pic_net *net, const float *rhs, const float *target, doub
                        double lr, double *loss, void *stream);
 /* z = s NN(h^2 r / s) - mean on the network's grid (r, z device FP64). */
 int pic_net_precondition(pic_net *net, const double *r, double h, double *z, void *stream);
+/* The loss above at (rhs, target) without an update (training != 0); loss:
+ * host out. */
+int pic_net_loss(pic_net *net, const float *rhs, const float *target, double lam, double *loss,
+                 void *stream);
+/* A training pair in the network's scale-free form from a solved step:
+ * u = h^2 rho (or h^2 (rho - rho_prev)), e = phi (or phi - phi_prev), and with
+ * s = rms(u): rhs = u / s, target = e / s (device FP32, n^3 each; rho, phi and
+ * the nullable pair rho_prev, phi_prev device FP64).  By linearity of A a step
+ * difference is an exact pair too.  scale (host out, nullable) receives s.  */
+int pic_net_make_pair(pic_net *net, const double *rho, const double *phi,
+                      const double *rho_prev, const double *phi_prev, double h, float *rhs,
+                      float *target, double *scale, void *stream);
 
 /* ---- single-layer primitives (3^3 periodic convolution, channels-last) ---
  * x, y, gy: BF16 bit patterns (uint16_t), [z][y][x][C]; gx FP32; weights FP32

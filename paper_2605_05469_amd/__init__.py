@@ -100,7 +100,8 @@ EXPORTS = ["pic_create", "pic_destroy", "pic_workspace_bytes", "pic_last_error",
            "pic_net_backward", "pic_net_train_step", "pic_net_precondition",
            "pic_conv3d_frag_elems", "pic_conv3d_pack", "pic_conv3d_fwd", "pic_conv3d_bwd_data",
            "pic_conv3d_wgrad_scratch_elems", "pic_conv3d_bwd_weight", "pic_adam_step",
-           "pic_pif_field", "pic_deposit_cic_noalloc"]
+           "pic_pif_field", "pic_deposit_cic_noalloc", "pic_stream_triad", "pic_net_loss",
+           "pic_net_make_pair"]
 
 
 def lib():
@@ -137,6 +138,7 @@ def lib():
     L.pic_step.argtypes = L.pic_init.argtypes
     L.pic_set_kernel_timing.argtypes = [vp, i32]
     L.pic_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    L.pic_stream_triad.argtypes = [i64, vp, vp, vp, dbl, i32, ctypes.POINTER(dbl), vp]
     L.pic_unet_param_count.restype = i64
     L.pic_set_unet.argtypes = [vp, vp, vp]
     L.pic_unet_precondition.argtypes = [vp, vp, vp, vp]
@@ -148,6 +150,8 @@ def lib():
     L.pic_net_backward.argtypes = [vp, vp, vp, vp]
     L.pic_net_train_step.argtypes = [vp, vp, vp, dbl, dbl, ctypes.POINTER(dbl), vp]
     L.pic_net_precondition.argtypes = [vp, vp, dbl, vp, vp]
+    L.pic_net_loss.argtypes = [vp, vp, vp, dbl, ctypes.POINTER(dbl), vp]
+    L.pic_net_make_pair.argtypes = [vp, vp, vp, vp, vp, dbl, vp, vp, ctypes.POINTER(dbl), vp]
     L.pic_conv3d_frag_elems.argtypes = [i32, i32]
     L.pic_conv3d_frag_elems.restype = ctypes.c_size_t
     L.pic_conv3d_pack.argtypes = [i32, i32, vp, vp, vp, vp]
@@ -372,6 +376,14 @@ class Simulation:
         return d
 
 
+def stream_triad(b, c, a, scalar=3.0, reps=10, stream=None):
+    """pic_stream_triad: a = b + scalar c; returns the average ms per launch."""
+    ms = ctypes.c_double(0.0)
+    _check(lib().pic_stream_triad(a.numel(), _ptr(b), _ptr(c), _ptr(a), scalar, reps,
+                                  ctypes.byref(ms), _stream(stream)))
+    return ms.value
+
+
 NOALLOC_MAX_N = 64  # PIC_NOALLOC_MAX_N
 
 
@@ -435,6 +447,21 @@ class Net:
     def precondition(self, r, h, z, stream=None):
         _check(lib().pic_net_precondition(self._h, _ptr(r), h, _ptr(z), _stream(stream)))
         return z
+
+    def loss(self, rhs, target, lam=1.0, stream=None):
+        """The training loss at one pair, no update (pic_net_loss)."""
+        L = ctypes.c_double(0.0)
+        _check(lib().pic_net_loss(self._h, _ptr(rhs), _ptr(target), lam, ctypes.byref(L),
+                                  _stream(stream)))
+        return L.value
+
+    def make_pair(self, rho, phi, h, rhs, target, rho_prev=None, phi_prev=None, stream=None):
+        """Scale-free training pair (pic_net_make_pair); returns the scale s."""
+        sc = ctypes.c_double(0.0)
+        _check(lib().pic_net_make_pair(self._h, _ptr(rho), _ptr(phi), _ptr(rho_prev),
+                                       _ptr(phi_prev), h, _ptr(rhs), _ptr(target),
+                                       ctypes.byref(sc), _stream(stream)))
+        return sc.value
 
 
 def conv3d_frag_elems(ci, co):

@@ -304,18 +304,6 @@ static int timing_collect(pic_ctx* c, int launched, int64_t valid) {
     return PIC_OK;
 }
 
-// Single-kernel iterations: one sampled (start, end) pair per iteration, in
-// slot 0.
-static int timing_collect_one(pic_ctx* c, int launched, int64_t valid) {
-    for (int k = 0; k < launched && k < valid; k += kTimeStride) {
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, c->ev[4 * k], c->ev[4 * k + 1]));
-        c->t_sum[0] += ms;
-        c->t_cnt[0] += 1;
-    }
-    return PIC_OK;
-}
-
 // ------------------------------------------------------------- FP64 PCG ----
 
 static bool use_cg1(const pic_ctx* c) {
@@ -328,11 +316,17 @@ static bool use_cg1(const pic_ctx* c) {
 // left RUNNING return at once, and every (re)computed residual lands in c->r
 // and restarts the recurrence, so the host's buffer parity only matters while
 // RUNNING.  Timing samples go to slot 0.
+// x is updated every other sweep (xm 1 / 2 alternate, starting with 1 after
+// every (re)start); a step left pending when the state leaves RUNNING is
+// applied (launch_cg1_flush) before x is used: the true residual of a
+// candidate, or the caller's iterate.  Timing samples the two sweeps of a
+// pair alike (k mod 4 = 0 and 1), so their average is the mean sweep.
 static int pcg64_iterate_cg1(pic_ctx* c, const double* b, double* x, hipStream_t s) {
     const SweepGeo& g = c->geo;
     const int K = c->p.check_every > 0 ? c->p.check_every : 16;
     double* rb[2] = {c->r, c->t3};
-    int rcur = 0, pcur = 0;
+    int rcur = 0, pcur = 0, xm = 1;
+    auto timed = [c](int k) { return c->timing && (k % kTimeStride) < 2; };
     if (c->timing) RETCHK(timing_events(c, (size_t)4 * K));
     HIPCHK(launch_cg1_start(g, c->r, c->minv, c->inv_h2, c->st, c->partials, s));
     for (;;) {
@@ -340,28 +334,41 @@ static int pcg64_iterate_cg1(pic_ctx* c, const double* b, double* x, hipStream_t
         if (cg.state == CG_RUNNING) {
             const int64_t it0 = cg.iter;
             for (int k = 0; k < K; ++k) {
-                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
+                if (timed(k)) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
                 HIPCHK(launch_cg1(g, rb[rcur], rb[rcur ^ 1], c->p2[pcur], c->p2[pcur ^ 1], x,
-                                  c->minv, c->inv_h2, c->st, c->partials, s));
-                if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
+                                  c->minv, c->inv_h2, c->st, c->partials, xm, pcur ^ 1, s));
+                if (timed(k)) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
                 rcur ^= 1;
                 pcur ^= 1;
+                xm = xm == 1 ? 2 : 1;
             }
             RETCHK(read_state(c, s));
-            if (c->timing) RETCHK(timing_collect_one(c, K, c->st_host->cg.iter - it0));
+            if (c->timing) {
+                const int64_t valid = c->st_host->cg.iter - it0;
+                for (int k = 0; k < K && k < valid; ++k) {
+                    if (!timed(k)) continue;
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, c->ev[4 * k], c->ev[4 * k + 1]));
+                    c->t_sum[0] += ms;
+                    c->t_cnt[0] += 1;
+                }
+            }
             if (c->st_host->cg.state == CG_RUNNING && c->st_host->cg.iter == it0)
                 return fail(PIC_ERR_STATE, "solver made no progress (iteration %lld)",
                             (long long)it0);
             continue;
         }
+        if (cg.xpend) HIPCHK(launch_cg1_flush(c->n3, c->p2[0], c->p2[1], x, c->st, s));
         if (cg.state == CG_CANDIDATE) {
             HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 0, c->p.rtol, c->p.max_iter,
                                      c->st, c->partials, s));
             HIPCHK(launch_cg1_start(g, c->r, c->minv, c->inv_h2, c->st, c->partials, s));
             rcur = 0;
+            xm = 1;
             RETCHK(read_state(c, s));
             continue;
         }
+        if (cg.xpend) RETCHK(read_state(c, s));
         return PIC_OK;  // CONVERGED, MAXIT, BREAKDOWN, ZERO_RHS
     }
 }
@@ -512,18 +519,23 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
             }
         }
         const int cur0 = cur;
+        // single-reduction inner sweeps update d every other iteration (as the
+        // FP64 solve updates x); both sweeps of a pair are timing samples
+        int xm = 1;
+        auto timed1 = [c](int k) { return c->timing && (k % kTimeStride) < 2; };
         while (c->st_host->cg.state == CG_RUNNING) {
             const int64_t it0 = c->st_host->cg.iter;
             for (int k = 0; k < K; ++k) {
                 if (one) {
-                    if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
+                    if (timed1(k)) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
                     HIPCHK(launch_cg1_32(g, rb32[rcur], rb32[rcur ^ 1], c->p32[cur], c->p32[cur ^ 1],
                                          c->d32, c->minvf, c->inv_h2f, pgiven, c->st, c->partials,
-                                         s));
-                    if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
+                                         xm, cur ^ 1, s));
+                    if (timed1(k)) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
                     pgiven = 0;
                     rcur ^= 1;
                     cur ^= 1;
+                    xm = xm == 1 ? 2 : 1;
                     continue;
                 }
                 if (timed_iter(c, k)) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
@@ -538,12 +550,25 @@ static int solve_mixed(pic_ctx* c, const double* b, double* x, pic_solve_info* o
             }
             RETCHK(read_state(c, s));
             if (c->timing) {
-                if (one) RETCHK(timing_collect_one(c, K, c->st_host->cg.iter - it0));
-                else RETCHK(timing_collect(c, K, c->st_host->cg.iter - it0));
+                const int64_t valid = c->st_host->cg.iter - it0;
+                if (one) {
+                    for (int k = 0; k < K && k < valid; ++k) {
+                        if (!timed1(k)) continue;
+                        float ms = 0.f;
+                        HIPCHK(hipEventElapsedTime(&ms, c->ev[4 * k], c->ev[4 * k + 1]));
+                        c->t_sum[0] += ms;
+                        c->t_cnt[0] += 1;
+                    }
+                } else {
+                    RETCHK(timing_collect(c, K, valid));
+                }
             }
             if (c->st_host->cg.state == CG_RUNNING && c->st_host->cg.iter == it0)
                 return fail(PIC_ERR_STATE, "inner solver made no progress");
         }
+        // the last odd sweep's step, if pending, before d is used
+        if (one && c->st_host->cg.xpend)
+            HIPCHK(launch_cg1_flush32(c->n3, c->p32[0], c->p32[1], c->d32, c->st, s));
         inner_total += c->st_host->cg.iter;
         // the last direction written (the next inner solve may continue it):
         // each active iteration's direction sweep (or single sweep) wrote
@@ -826,10 +851,17 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
     int restart = 1;  // p = z (no previous direction)
     int cur = 0;      // p2[cur] holds the current direction
     int64_t it = 0;
+    // kernel timing: every kTimeStride-th iteration, the direction sweep
+    // (slot 0) and the update sweep (slot 1); the state is read back after
+    // each, so the events have completed when they are read
+    if (c->timing) RETCHK(timing_events(c, 4));
     while (it < c->p.max_iter) {
+        const bool timed = c->timing && (it % kTimeStride) == 0;
         // p_new = z + beta p and p_new . A p_new (A p_new not stored)
+        if (timed) HIPCHK(hipEventRecord(c->ev[0], s));
         HIPCHK(launch_aqz(g, z, c->p2[cur], c->p2[cur ^ 1], nullptr, beta, restart, c->inv_h2,
                           c->st, c->partials, s));
+        if (timed) HIPCHK(hipEventRecord(c->ev[1], s));
         cur ^= 1;
         double* p = c->p2[cur];
         RETCHK(read_state(c, s));
@@ -837,8 +869,11 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
         const double alpha = rz / pq;
         if (!std::isfinite(alpha) || !(pq > 0.0)) break;
         // x += alpha p, r -= alpha A p (A p recomputed), r . r
+        if (timed) HIPCHK(hipEventRecord(c->ev[2], s));
         HIPCHK(launch_updp(g, p, x, c->r, alpha, c->inv_h2, c->st, c->partials, s));
+        if (timed) HIPCHK(hipEventRecord(c->ev[3], s));
         RETCHK(read_state(c, s));
+        if (timed) RETCHK(timing_collect(c, 1, 1));
         ++it;
         rn = std::sqrt(c->st_host->flex_rr);
         out->rel_res = rn / nb;
@@ -1089,6 +1124,30 @@ int pic_set_kernel_timing(pic_ctx* c, int32_t enable) {
     if (!c) return fail(PIC_ERR_INVALID, "ctx is NULL");
     c->timing = enable != 0;
     timing_reset(c);
+    return PIC_OK;
+}
+
+int pic_stream_triad(int64_t n, const double* b, const double* cv, double* a, double scalar,
+                     int32_t reps, double* avg_ms, void* stream) {
+    if (n < 1 || n >= ((int64_t)1 << 40) || reps < 1 || !b || !cv || !a || !avg_ms)
+        return fail(PIC_ERR_INVALID, "pic_stream_triad: n in [1, 2^40), reps >= 1, non-NULL arrays");
+    if (!aligned8(b) || !aligned8(cv) || !aligned8(a))
+        return fail(PIC_ERR_INVALID, "pic_stream_triad: arrays must be 8-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e[2] = {nullptr, nullptr};
+    HIPCHK(hipEventCreate(&e[0]));
+    hipError_t err = hipEventCreate(&e[1]);
+    if (err == hipSuccess) err = launch_triad(n, b, cv, a, scalar, s);  // untimed first launch
+    if (err == hipSuccess) err = hipEventRecord(e[0], s);
+    for (int32_t k = 0; k < reps && err == hipSuccess; ++k) err = launch_triad(n, b, cv, a, scalar, s);
+    if (err == hipSuccess) err = hipEventRecord(e[1], s);
+    if (err == hipSuccess) err = hipEventSynchronize(e[1]);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e[0], e[1]);
+    (void)hipEventDestroy(e[0]);
+    if (e[1]) (void)hipEventDestroy(e[1]);
+    if (err != hipSuccess) return fail(PIC_ERR_HIP, "pic_stream_triad: %s", hipGetErrorString(err));
+    *avg_ms = (double)ms / reps;
     return PIC_OK;
 }
 

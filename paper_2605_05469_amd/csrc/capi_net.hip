@@ -94,6 +94,30 @@ int pic_net_train_step(pic_net* w, const float* rhs, const float* target, double
     return rc ? nfail(PIC_ERR_HIP) : PIC_OK;
 }
 
+int pic_net_loss(pic_net* w, const float* rhs, const float* target, double lam, double* loss,
+                 void* stream) {
+    NEEDNET(w);
+    if (!rhs || !target || !loss) return pic_set_error_(PIC_ERR_INVALID, "rhs/target/loss is NULL");
+    if (!(lam >= 0.0)) return pic_set_error_(PIC_ERR_INVALID, "lam must be >= 0");
+    const int rc = net::eval_loss(w->n, rhs, target, lam, loss, (hipStream_t)stream);
+    if (rc == -4) return nfail(PIC_ERR_STATE);
+    return rc ? nfail(PIC_ERR_HIP) : PIC_OK;
+}
+
+int pic_net_make_pair(pic_net* w, const double* rho, const double* phi, const double* rho_prev,
+                      const double* phi_prev, double h, float* rhs, float* target, double* scale,
+                      void* stream) {
+    NEEDNET(w);
+    if (!rho || !phi || !rhs || !target)
+        return pic_set_error_(PIC_ERR_INVALID, "rho/phi/rhs/target is NULL");
+    if ((rho_prev == nullptr) != (phi_prev == nullptr))
+        return pic_set_error_(PIC_ERR_INVALID, "rho_prev and phi_prev: both or neither");
+    if (!(h > 0.0)) return pic_set_error_(PIC_ERR_INVALID, "h must be > 0");
+    const int rc = net::make_pair(w->n, rho, rho_prev, phi, phi_prev, h * h, rhs, target, scale,
+                                  (hipStream_t)stream);
+    return rc ? nfail(PIC_ERR_HIP) : PIC_OK;
+}
+
 int pic_net_precondition(pic_net* w, const double* r, double h, double* z, void* stream) {
     NEEDNET(w);
     if (!r || !z) return pic_set_error_(PIC_ERR_INVALID, "r/z is NULL");

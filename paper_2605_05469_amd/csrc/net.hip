@@ -367,6 +367,48 @@ int train_step(Net* net, const float* rhs, const float* target, double lam, doub
     return 0;
 }
 
+int eval_loss(Net* net, const float* rhs, const float* target, double lam, double* loss,
+              hipStream_t s) {
+    if (!net->training) {
+        n_err = "network was created without training buffers";
+        return -4;
+    }
+    const int n = net->n;
+    const int64_t n1 = (int64_t)n * n * n;
+    NCHK(to_bf16(n1, rhs, net->in, s));
+    const int rc = fwd(net, s);
+    if (rc) return rc;
+    const int np = loss_parts(n);
+    double* normp = net->red;
+    double* lossp = net->red + 2 * np + 8;
+    NCHK(loss_norms(n, target, rhs, normp, s));
+    NCHK(loss_pass1(n, net->out, target, rhs, net->d2, lossp, s));
+    std::vector<double> h(2 * np), hl(2 * np);
+    NCHK(hipMemcpyAsync(h.data(), normp, 2 * np * sizeof(double), hipMemcpyDeviceToHost, s));
+    NCHK(hipMemcpyAsync(hl.data(), lossp, 2 * np * sizeof(double), hipMemcpyDeviceToHost, s));
+    NCHK(hipStreamSynchronize(s));
+    double a = 0, b = 0, nt = 0, nr = 0;
+    for (int i = 0; i < np; ++i) {
+        a += hl[2 * i];
+        b += hl[2 * i + 1];
+        nt += h[2 * i];
+        nr += h[2 * i + 1];
+    }
+    *loss = a / nt + lam * b / nr;
+    return 0;
+}
+
+int make_pair(Net* net, const double* b, const double* bp, const double* phi, const double* pp,
+              double h2, float* rhs, float* tgt, double* scale, hipStream_t s) {
+    const int64_t n1 = (int64_t)net->n * net->n * net->n;
+    NCHK(scale_pair(n1, b, bp, phi, pp, h2, net->red, net->scal + 1, rhs, tgt, s));
+    if (scale) {
+        NCHK(hipMemcpyAsync(scale, net->scal + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        NCHK(hipStreamSynchronize(s));
+    }
+    return 0;
+}
+
 int precondition(Net* net, const double* r, double h2, double* z, hipStream_t s) {
     const int64_t n1 = (int64_t)net->n * net->n * net->n;
     double* part = net->red;

@@ -47,6 +47,11 @@ hipError_t grad_round(int64_t count, const float* g, const uint16_t* act, uint16
 hipError_t add_bf16(int64_t count, const uint16_t* a, float* g, hipStream_t s);
 hipError_t to_bf16(int64_t count, const float* a, uint16_t* out, hipStream_t s);
 int loss_parts(int n);
+// Scale-free training pair: u = h2 (b - bp), e = phi - pp (bp, pp may be NULL),
+// rhs = u / rms(u), tgt = e / rms(u) in FP32; s_out = rms(u) (device).
+hipError_t scale_pair(int64_t n3, const double* b, const double* bp, const double* phi,
+                      const double* pp, double h2, double* part, double* s_out, float* rhs,
+                      float* tgt, hipStream_t s);
 hipError_t loss_norms(int n, const float* t, const float* r, double* part, hipStream_t s);
 hipError_t loss_pass1(int n, const float* o, const float* t, const float* r, float* d2,
                       double* part, hipStream_t s);
@@ -83,6 +88,12 @@ int forward_f32(Net* net, const float* x, float* out, hipStream_t s);
 int backward(Net* net, const float* dout, float* grads, hipStream_t s);
 // z = s * NN(h^2 r / s) - mean, s = rms(h^2 r): the preconditioner.
 int precondition(Net* net, const double* r, double h2, double* z, hipStream_t s);
+// Loss of one (rhs, target) pair without an update (training buffers needed).
+int eval_loss(Net* net, const float* rhs, const float* target, double lam, double* loss,
+              hipStream_t s);
+// A scale-free training pair from (b, phi) or from differences to (bp, pp).
+int make_pair(Net* net, const double* b, const double* bp, const double* phi, const double* pp,
+              double h2, float* rhs, float* tgt, double* scale, hipStream_t s);
 // One Adam step on the loss of one (rhs, target) pair; loss (host) optional.
 int train_step(Net* net, const float* rhs, const float* target, double lam, double lr,
                double* loss, hipStream_t s);

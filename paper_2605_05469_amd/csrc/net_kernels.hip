@@ -1204,6 +1204,49 @@ __global__ __launch_bounds__(kNT) void prep_kernel(int64_t n3, const double* __r
         x[p] = f2bf((float)(h2 * r[p] * inv));
 }
 
+// Training pairs in the scale-free form: u = h^2 (b - b_prev), e = phi - phi_prev
+// (b_prev, phi_prev NULL: no difference); partial sums of u^2.
+__global__ __launch_bounds__(kNT) void pair_sumsq_kernel(int64_t n3, const double* __restrict__ b,
+                                                         const double* __restrict__ bp, double h2,
+                                                         double* __restrict__ part) {
+    __shared__ double red[kNT / kWave];
+    double acc[1] = {0.0};
+    for (int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x; p < n3; p += (int64_t)gridDim.x * kNT) {
+        const double v = h2 * (bp ? b[p] - bp[p] : b[p]);
+        acc[0] += v * v;
+    }
+    block_sum<kNT, 1>(acc, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
+}
+
+// rhs = (float)(u / s), tgt = (float)(e / s), s = rms(u) from the partials.
+__global__ __launch_bounds__(kNT) void pair_kernel(int64_t n3, const double* __restrict__ b,
+                                                   const double* __restrict__ bp,
+                                                   const double* __restrict__ phi,
+                                                   const double* __restrict__ pp, double h2,
+                                                   const double* __restrict__ part, int nparts,
+                                                   double* __restrict__ s_out,
+                                                   float* __restrict__ rhs,
+                                                   float* __restrict__ tgt) {
+    __shared__ double red[kNT / kWave];
+    __shared__ double s_sh;
+    double t[1];
+    sum_partials<kNT, 1>(part, nparts, t, red);
+    if (threadIdx.x == 0) {
+        s_sh = sqrt(t[0] / (double)n3);
+        if (blockIdx.x == 0) *s_out = s_sh;
+    }
+    __syncthreads();
+    const double s = s_sh;
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * kNT + threadIdx.x; p < n3; p += (int64_t)gridDim.x * kNT) {
+        const double u = h2 * (bp ? b[p] - bp[p] : b[p]);
+        const double e = pp ? phi[p] - pp[p] : phi[p];
+        rhs[p] = (float)(u * inv);
+        tgt[p] = (float)(e * inv);
+    }
+}
+
 // z = s * o (FP64), partial sums of z for the mean.
 __global__ __launch_bounds__(kNT) void post_kernel(int64_t n3, const float* __restrict__ o,
                                                    const double* __restrict__ s_in,
@@ -1552,6 +1595,15 @@ hipError_t prep_input(int64_t n3, const double* r, double h2, double* part, doub
     hipLaunchKernelGGL(sumsq_kernel, dim3(nb), dim3(kNT), 0, s, n3, r, h2, part);
     hipLaunchKernelGGL(prep_kernel, dim3(nb), dim3(kNT), 0, s, n3, r, h2, (const double*)part, nb,
                        s_out, x);
+    return hipGetLastError();
+}
+hipError_t scale_pair(int64_t n3, const double* b, const double* bp, const double* phi,
+                      const double* pp, double h2, double* part, double* s_out, float* rhs,
+                      float* tgt, hipStream_t s) {
+    const int nb = pre_parts(n3);
+    hipLaunchKernelGGL(pair_sumsq_kernel, dim3(nb), dim3(kNT), 0, s, n3, b, bp, h2, part);
+    hipLaunchKernelGGL(pair_kernel, dim3(nb), dim3(kNT), 0, s, n3, b, bp, phi, pp, h2,
+                       (const double*)part, nb, s_out, rhs, tgt);
     return hipGetLastError();
 }
 hipError_t post_output(int64_t n3, const float* o, const double* s_in, double* z, double* part,

@@ -75,28 +75,51 @@ __global__ __launch_bounds__(kPT) void keys_kernel(int64_t np, const double* __r
         key[p] = key_of(x[p], y[p], z[p], n, inv_h);
 }
 
+// Each thread takes kPushK particles per trip (kPT apart, so every load and
+// store of a wave stays one contiguous run) and issues the loads of all of
+// them before the first gather: 6 kPushK streaming loads in flight per
+// thread instead of 6.  The outputs are written once and not read again by
+// this kernel, so they bypass L2 retention.
+constexpr int kPushK = 4;
 __global__ __launch_bounds__(kPT) void gather_push_kernel(
     int64_t np, double* __restrict__ x, double* __restrict__ y, double* __restrict__ z,
     double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
     const double* __restrict__ ex, const double* __restrict__ ey, const double* __restrict__ ez,
     uint32_t* __restrict__ key, int n, double inv_h, double L, double dt, double coef) {
-    for (int64_t p = (int64_t)blockIdx.x * kPT + threadIdx.x; p < np; p += (int64_t)gridDim.x * kPT) {
-        const double px = x[p], py = y[p], pz = z[p];
-        double sx, sy, sz;
-        gather3(px, py, pz, n, inv_h, ex, ey, ez, sx, sy, sz);
-        const double ux = vx[p] + coef * sx;
-        const double uy = vy[p] + coef * sy;
-        const double uz = vz[p] + coef * sz;
-        const double nx = wrap(px + dt * ux, L);
-        const double ny = wrap(py + dt * uy, L);
-        const double nz = wrap(pz + dt * uz, L);
-        vx[p] = ux;
-        vy[p] = uy;
-        vz[p] = uz;
-        x[p] = nx;
-        y[p] = ny;
-        z[p] = nz;
-        if (key) key[p] = key_of(nx, ny, nz, n, inv_h);
+    const int64_t stride = (int64_t)gridDim.x * kPT * kPushK;
+    for (int64_t p0 = (int64_t)blockIdx.x * kPT * kPushK + threadIdx.x; p0 < np; p0 += stride) {
+        double px[kPushK], py[kPushK], pz[kPushK], qx[kPushK], qy[kPushK], qz[kPushK];
+#pragma unroll
+        for (int k = 0; k < kPushK; ++k) {
+            const int64_t p = p0 + (int64_t)kPT * k;
+            const bool ok = p < np;
+            px[k] = ok ? x[p] : 0.0;
+            py[k] = ok ? y[p] : 0.0;
+            pz[k] = ok ? z[p] : 0.0;
+            qx[k] = ok ? vx[p] : 0.0;
+            qy[k] = ok ? vy[p] : 0.0;
+            qz[k] = ok ? vz[p] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kPushK; ++k) {
+            const int64_t p = p0 + (int64_t)kPT * k;
+            if (p >= np) break;
+            double sx, sy, sz;
+            gather3(px[k], py[k], pz[k], n, inv_h, ex, ey, ez, sx, sy, sz);
+            const double ux = qx[k] + coef * sx;
+            const double uy = qy[k] + coef * sy;
+            const double uz = qz[k] + coef * sz;
+            const double nx = wrap(px[k] + dt * ux, L);
+            const double ny = wrap(py[k] + dt * uy, L);
+            const double nz = wrap(pz[k] + dt * uz, L);
+            __builtin_nontemporal_store(ux, vx + p);
+            __builtin_nontemporal_store(uy, vy + p);
+            __builtin_nontemporal_store(uz, vz + p);
+            __builtin_nontemporal_store(nx, x + p);
+            __builtin_nontemporal_store(ny, y + p);
+            __builtin_nontemporal_store(nz, z + p);
+            if (key) __builtin_nontemporal_store(key_of(nx, ny, nz, n, inv_h), key + p);
+        }
     }
 }
 
@@ -304,8 +327,9 @@ hipError_t launch_gather_push(int64_t np, double* x, double* y, double* z, doubl
                               uint32_t* key, int n, double inv_h, double L, double dt,
                               double coef, hipStream_t s) {
     if (np == 0) return hipSuccess;
-    hipLaunchKernelGGL(gather_push_kernel, dim3(pblocks(np, 16384)), dim3(kPT), 0, s, np, x, y, z,
-                       vx, vy, vz, ex, ey, ez, key, n, inv_h, L, dt, coef);
+    const int64_t groups = (np + kPushK - 1) / kPushK;
+    hipLaunchKernelGGL(gather_push_kernel, dim3(pblocks(groups, 4096)), dim3(kPT), 0, s, np, x, y,
+                       z, vx, vy, vz, ex, ey, ez, key, n, inv_h, L, dt, coef);
     return hipGetLastError();
 }
 

@@ -32,6 +32,9 @@ struct CgScalars {
     int32_t state;
     int32_t restart;  // next direction = M^{-1} r (ignore the old direction)
     int32_t replacements;
+    int32_t xpend;      // single-reduction FP64 sweep: x lacks alpha_pend * p[pend_slot]
+    double alpha_pend;
+    int32_t pend_slot;  // which of the two direction buffers holds that direction
     int32_t pad;
 };
 
@@ -78,9 +81,14 @@ hipError_t launch_upd64(const SweepGeo& g, const double* p_new, double* x, doubl
 bool cg1_supported(const SweepGeo& g);
 hipError_t launch_cg1_start(const SweepGeo& g, const double* r, double minv, double inv_h2,
                             DevState* st, double* partials, hipStream_t s);
+// xm: 0 = x updated by every sweep; 1 / 2 alternate (x updated every other
+// sweep, the odd sweep's step pending in the state; pslot: index of p_out
+// among the two direction buffers); launch_cg1_flush applies a pending step.
 hipError_t launch_cg1(const SweepGeo& g, const double* r_in, double* r_out, const double* p_in,
                       double* p_out, double* x, double minv, double inv_h2, DevState* st,
-                      double* partials, hipStream_t s);
+                      double* partials, int xm, int pslot, hipStream_t s);
+hipError_t launch_cg1_flush(int64_t n3, const double* p0, const double* p1, double* x,
+                            DevState* st, hipStream_t s);
 // The same in FP32 for the inner solve of the mixed form (d: the inner
 // solution); pgiven: p_in already holds this step's direction (a direction
 // sweep formed it and its curvature: the continued first step).
@@ -88,7 +96,9 @@ hipError_t launch_cg1_start32(const SweepGeo& g, const float* r, float minvf, fl
                               DevState* st, double* partials, hipStream_t s);
 hipError_t launch_cg1_32(const SweepGeo& g, const float* r_in, float* r_out, const float* p_in,
                          float* p_out, float* d, float minvf, float inv_h2f, int pgiven,
-                         DevState* st, double* partials, hipStream_t s);
+                         DevState* st, double* partials, int xm, int pslot, hipStream_t s);
+hipError_t launch_cg1_flush32(int64_t n3, const float* p0, const float* p1, float* d,
+                              DevState* st, hipStream_t s);
 // Mixed-precision pieces.
 hipError_t launch_outer_resid(const SweepGeo& g, const double* b, const double* x, double* r,
                               double inv_h2, DevState* st, double* partials, double tol,
@@ -107,6 +117,9 @@ hipError_t launch_sum(int64_t n3, const double* v, DevState* st, double* partial
 hipError_t launch_field(const SweepGeo& g, double* phi, double* ex, double* ey, double* ez,
                         double ehalf, double h3, DevState* st, double* partials, hipStream_t s);
 hipError_t launch_fill(int64_t n, double* v, double val, hipStream_t s);
+// a = b + s c (n < 2^40), one element per thread, non-temporal stores.
+hipError_t launch_triad(int64_t n, const double* b, const double* c, double* a, double s,
+                        hipStream_t st);
 // r = b - A x and st->out_nr = ||r|| (no state change).
 hipError_t launch_resid_norm(const SweepGeo& g, const double* b, const double* x, double* r,
                              double inv_h2, DevState* st, double* partials, hipStream_t s);

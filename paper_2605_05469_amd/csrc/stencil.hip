@@ -3,22 +3,33 @@
 // field E = -grad phi (Sec. 2, Eq. poisson).
 //
 // Design (MI355X / gfx950):
-//  * One 256-thread workgroup owns a TX x 16 tile of (x, y) and marches over
-//    `zc` consecutive z-planes.  A ring of three LDS planes (z-1, z, z+1),
-//    each with a one-point periodic halo in x and y, holds the operand; every
-//    grid value is read from HBM once per sweep apart from the halo.
-//  * Each sweep fuses its vector updates and dot products: the direction
-//    sweep forms p_new = M^{-1} r + beta p_old while filling the ring and
-//    reduces p.(A p); the update sweep recomputes A p from p_new in LDS (no q
-//    vector is stored), updates x and r and reduces r.r and r.M^{-1} r.
-//    Per iteration this streams 24 + 40 = 64 bytes per grid point in FP64.
+//  * Jacobi-PCG on the periodic box runs ONE sweep per iteration
+//    (cg1_kernel, the single-reduction arrangement of the same iteration):
+//    a 512-thread workgroup owns a 64 x 32 (x, y) tile (128 x 16 for the
+//    mixed form's FP32 inner sweeps) and an equal share of its column's
+//    z-planes.  From r_k, p_{k-1}, x_k it forms p_k, x_{k+1} and r_{k+1} and
+//    reduces the five dot products that give the next beta and alpha, so it
+//    streams r, p and x once each: 48 bytes per grid point in FP64 (24 in
+//    FP32).  A r_{k+1} on the tile needs r_{k+1} on a one-point ring, which
+//    needs p_k on a two-point ring: every stage is evaluated on the 68 x 36
+//    region; each thread keeps the z-neighbours of its region points in
+//    registers and in-plane neighbours pass through two double-buffered LDS
+//    planes (one barrier per plane).  Each wave takes 64 aligned columns of
+//    one region row, so loads and stores are whole 128-byte lines.
+//  * The textbook two-sweep pair (bounded boxes, PIC_FLAG_PCG_TWO_SWEEP, and
+//    the SSOR form's PCG sweeps): a 256-thread workgroup owns a 64 x 32 tile,
+//    LDS holds two planes with their one-point halo, the z-1 neighbour stays
+//    in registers.  The direction sweep forms p_new = M^{-1} r + beta p_old
+//    while staging and reduces p.(A p) (24 B/point); the update sweep
+//    recomputes A p from p_new (no q vector), updates x and r and reduces
+//    r.r and r.M^{-1} r (40 B/point): 64 bytes per grid point per iteration.
 //  * Dot products are deterministic: wave tree + fixed-order block sum, one
 //    partial per block, summed in index order by the last block, which also
 //    advances the CG scalars held in device memory (alpha, beta, state).  The
 //    host polls the state only every few iterations; once the state leaves
 //    RUNNING the remaining queued sweeps return immediately.
 //  * Workgroup ids are remapped so that neighbouring tiles run on one XCD and
-//    share its L2 for their halos.
+//    share its L2 for their halos; own-point streams are non-temporal.
 //
 // Arithmetic order matches the CPU oracle's definition (neighbour sum
 // ((xm+xp)+(ym+yp))+(zm+zp), no contraction) so that A p is bit-identical;
@@ -292,6 +303,7 @@ struct OpResidual64 {
             cg.true_rn = sqrt(t[1]);
             return;
         }
+        cg.xpend = 0;  // a residual of x: no step of x is pending (the host flushed it)
         if (init) {
             st->bb = t[0];
             cg.nb = sqrt(t[0]);
@@ -472,6 +484,7 @@ struct OpCg1Start {
         cg.alpha = t[1] / t[2];
         cg.beta = 0.0;
         cg.restart = 1;
+        cg.xpend = 0;
         if (!(t[2] > 0.0) || !isfinite(cg.alpha)) cg.state = CG_BREAKDOWN;
     }
     __device__ uint32_t* ticket() const { return &st->tickets[1]; }
@@ -884,13 +897,23 @@ __global__ __launch_bounds__(kNT) void ssor_fused_kernel(int n, int bounded, int
 // (dot products accumulated in FP64 as in the two-sweep form).  pgiven: p_in
 // already holds p_k (formed, with its exact p.A p, by a direction sweep: the
 // first step of an inner solve that continues the previous direction).
-template <class V, int TX, int TY, int NT>
+//
+// XM: how the sweep treats x.  0: x_{k+1} = x_k + alpha_k p_k at every sweep
+// (48 B/point).  1 and 2 alternate (FP64 solve): x is not updated by an odd
+// (XM = 1) sweep, which records alpha_k and the buffer holding p_k as a
+// pending update; the next (XM = 2) sweep reads p_k as its p_in anyway and
+// applies x = (x + alpha_k p_k) + alpha_{k+1} p_{k+1}, the same two updates
+// in the same order (bit-identical x), so x is read and written every other
+// iteration: 32 and 48 B/point, 40 on average.  A pending update left when
+// the state leaves RUNNING is applied by cg1_flush_kernel before x is used.
+template <class V, int TX, int TY, int NT, int XM>
 __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nbz,
                                                   const V* __restrict__ r_in,
                                                   V* __restrict__ r_out,
                                                   const V* __restrict__ p_in,
                                                   V* __restrict__ p_out, V* x, V minv, V inv_h2,
-                                                  DevState* st, double* part, int pgiven) {
+                                                  DevState* st, double* part, int pgiven,
+                                                  int pslot) {
     constexpr int W0 = TX + 4, H0 = TY + 4;
     constexpr int WP = W0 + 2, HP = H0 + 2;
     constexpr int PLANE = WP * HP;
@@ -911,6 +934,7 @@ __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nb
     const int restart = st->cg.restart;
     const V alpha = (V)st->cg.alpha;
     const V beta = (V)st->cg.beta;
+    const V alpha_p = XM == 2 ? (V)st->cg.alpha_pend : V(0);
 
     const int tid = threadIdx.x;
     const uint32_t nb = (uint32_t)(nbx * nby * nbz);
@@ -970,7 +994,8 @@ __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nb
             ldp[k] = V(0);
             if (pofs[k] < 0) continue;
             ldr[k] = r_in[zo + goff[k]];
-            if (!restart) ldp[k] = p_in[zo + goff[k]];
+            // XM 2: p_in is the pending direction, needed for x even on a restart
+            if (!restart || XM == 2) ldp[k] = p_in[zo + goff[k]];
         }
     };
     // p_k from the staged loads, in the direction sweep's order
@@ -985,14 +1010,23 @@ __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nb
     V s2[NP], s1[NP];          // r_{k+1} at planes j-2, j-1
     V xo[NP], xn[NP];          // x_k at planes j-1, j (tile points)
     V qm[NP];                  // A p_k at plane j-1
+    V om[XM == 2 ? NP : 1], oc[XM == 2 ? NP : 1], on[XM == 2 ? NP : 1];  // pending p, j-1..j+1
     fetch(z0 - 2);
 #pragma unroll
     for (int k = 0; k < NP; ++k) pm[k] = dir(k);
+    if constexpr (XM == 2) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) om[k] = ldp[k];
+    }
     fetch(z0 - 1);
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         pc[k] = dir(k);
         rc[k] = ldr[k];
+    }
+    if constexpr (XM == 2) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) oc[k] = ldp[k];
     }
     fetch(z0);
 #pragma unroll
@@ -1000,6 +1034,10 @@ __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nb
         pn[k] = dir(k);
         rn[k] = ldr[k];
         s2[k] = s1[k] = xo[k] = xn[k] = qm[k] = V(0);
+    }
+    if constexpr (XM == 2) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) on[k] = ldp[k];
     }
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     __syncthreads();  // LDS cleared before the first stores
@@ -1015,7 +1053,7 @@ __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nb
         for (int k = 0; k < NP; ++k)
             if (pofs[k] >= 0) LP[pofs[k]] = pc[k];
         if (j + 2 <= z1 + 1) fetch(j + 2);
-        if (j >= z0 && j < z1) {
+        if (XM != 1 && j >= z0 && j < z1) {
             const size_t zo = (size_t)j * nn;
 #pragma unroll
             for (int k = 0; k < NP; ++k)
@@ -1052,7 +1090,8 @@ __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nb
                 acc[3] += (double)u * (double)qm[k];
                 acc[4] += (double)pm[k] * (double)qm[k];
                 const size_t g = zo + goff[k];
-                st_own(xo[k] + alpha * pm[k], x + g);
+                if constexpr (XM == 0) st_own(xo[k] + alpha * pm[k], x + g);
+                if constexpr (XM == 2) st_own((xo[k] + alpha_p * om[k]) + alpha * pm[k], x + g);
                 st_own(rv, r_out + g);
                 st_own(pm[k], p_out + g);
             }
@@ -1069,6 +1108,14 @@ __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nb
             pn[k] = dir(k);
             rn[k] = ldr[k];
         }
+        if constexpr (XM == 2) {
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                om[k] = oc[k];
+                oc[k] = on[k];
+                on[k] = ldp[k];
+            }
+        }
     }
 
     block_sum<NT, 5>(acc, red);
@@ -1081,6 +1128,11 @@ __global__ __launch_bounds__(NT) void cg1_kernel(int n, int nbx, int nby, int nb
         sum_partials<NT, 5>(part, (int)nb, t, red);
         if (tid == 0) {
             CgScalars& cg = st->cg;
+            if (XM == 1) {
+                cg.alpha_pend = cg.alpha;  // this sweep's step, not yet in x
+                cg.pend_slot = pslot;
+            }
+            cg.xpend = XM == 1 ? 1 : 0;
             cg.rz_prev = cg.rz;
             cg.iter += 1;
             cg.rr = t[0];
@@ -1208,6 +1260,7 @@ __global__ __launch_bounds__(kNT) void convert32_kernel(int64_t n3, const double
             cg.max_iter = max_inner;
             cg.restart = (cont && isfinite(bt)) ? 0 : 1;
             cg.beta = cg.restart ? 0.0 : bt;
+            cg.xpend = 0;
             cg.state = (n0 == 0.0 || !isfinite(n0)) ? CG_BREAKDOWN : CG_RUNNING;
         }
     }
@@ -1245,6 +1298,40 @@ __global__ __launch_bounds__(kNT) void sum_kernel(int64_t n3, const double* __re
             st->sum = tot[0];
         }
     }
+}
+
+// a = b + s c (24 bytes per element): the achievable-bandwidth reference the
+// sweeps are compared with.  Two consecutive elements per thread as 16-byte
+// loads and stores (arrays 16-byte aligned, n even), else one.
+typedef double triad_v2 __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(256) void triad2_kernel(int64_t n2, const triad_v2* __restrict__ b,
+                                                     const triad_v2* __restrict__ c,
+                                                     triad_v2* __restrict__ a, double s) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n2) {
+        const triad_v2 x = b[i], y = c[i];
+        triad_v2 r;
+        r.x = x.x + s * y.x;
+        r.y = x.y + s * y.y;
+        __builtin_nontemporal_store(r, a + i);
+    }
+}
+__global__ __launch_bounds__(256) void triad1_kernel(int64_t n, const double* __restrict__ b,
+                                                     const double* __restrict__ c,
+                                                     double* __restrict__ a, double s) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(b[i] + s * c[i], a + i);
+}
+
+hipError_t launch_triad(int64_t n, const double* b, const double* c, double* a, double s,
+                        hipStream_t st) {
+    if ((n % 2) == 0 && (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15u) == 0)
+        hipLaunchKernelGGL(triad2_kernel, dim3((uint32_t)((n / 2 + 255) / 256)), dim3(256), 0, st,
+                           n / 2, (const triad_v2*)b, (const triad_v2*)c, (triad_v2*)a, s);
+    else
+        hipLaunchKernelGGL(triad1_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, n,
+                           b, c, a, s);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(kNT) void fill_kernel(int64_t n, double* __restrict__ v, double val) {
@@ -1353,13 +1440,14 @@ hipError_t launch_cg1_start32(const SweepGeo& g, const float* r, float minvf, fl
 // 64 x 32 x 1024, which beats 64 x 16 x 256 by 5% and 64 x 32 x 512 by 12%
 // (these with points dealt out in row-major order; with whole rows per wave
 // 64 x 32 x 1024 and 128 x 16 x 512 are within 1%).
-template <class V, int TX, int TY, int NT>
+template <class V, int TX, int TY, int NT, int XM = 0>
 static hipError_t cg1_t(int n, const V* r_in, V* r_out, const V* p_in, V* p_out, V* x, V minv,
-                        V inv_h2, DevState* st, double* partials, int pgiven, hipStream_t s) {
+                        V inv_h2, DevState* st, double* partials, int pgiven, hipStream_t s,
+                        int pslot = 0) {
     static int occ = 0, cus = 0;
     if (occ == 0) {
         int o = 0, c = 0, dev = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, cg1_kernel<V, TX, TY, NT>, NT, 0) !=
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, cg1_kernel<V, TX, TY, NT, XM>, NT, 0) !=
                 hipSuccess || o < 1)
             o = 1;
         (void)hipGetDevice(&dev);
@@ -1379,34 +1467,100 @@ static hipError_t cg1_t(int n, const V* r_in, V* r_out, const V* p_in, V* p_out,
     if (nbz < 1) nbz = 1;
     const int nb = tiles * nbz;
     if (nb > kMaxBlocks) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((cg1_kernel<V, TX, TY, NT>), dim3(nb), dim3(NT), 0, s, n, nbx, nby, nbz,
-                       r_in, r_out, p_in, p_out, x, minv, inv_h2, st, partials, pgiven);
+    hipLaunchKernelGGL((cg1_kernel<V, TX, TY, NT, XM>), dim3(nb), dim3(NT), 0, s, n, nbx, nby,
+                       nbz, r_in, r_out, p_in, p_out, x, minv, inv_h2, st, partials, pgiven, pslot);
     return hipGetLastError();
+}
+
+template <class V, int TX, int TY, int NT>
+static hipError_t cg1_xm(int xm, int n, const V* r_in, V* r_out, const V* p_in, V* p_out, V* x,
+                         V minv, V inv_h2, DevState* st, double* partials, int pgiven, int pslot,
+                         hipStream_t s) {
+    if (xm == 1)
+        return cg1_t<V, TX, TY, NT, 1>(n, r_in, r_out, p_in, p_out, x, minv, inv_h2, st, partials,
+                                       pgiven, s, pslot);
+    if (xm == 2)
+        return cg1_t<V, TX, TY, NT, 2>(n, r_in, r_out, p_in, p_out, x, minv, inv_h2, st, partials,
+                                       pgiven, s, pslot);
+    return cg1_t<V, TX, TY, NT, 0>(n, r_in, r_out, p_in, p_out, x, minv, inv_h2, st, partials,
+                                   pgiven, s, pslot);
 }
 
 hipError_t launch_cg1(const SweepGeo& g, const double* r_in, double* r_out, const double* p_in,
                       double* p_out, double* x, double minv, double inv_h2, DevState* st,
-                      double* partials, hipStream_t s) {
-    if (!cg1_supported(g)) return hipErrorInvalidValue;
+                      double* partials, int xm, int pslot, hipStream_t s) {
+    if (!cg1_supported(g) || xm < 0 || xm > 2) return hipErrorInvalidValue;
+    // 1024^3 (measured, 200 sweeps): 128 x 16 tiles 9.14 ms per sweep = 5.64 TB/s
+    // against 10.4 ms for 64 x 32 (9.65 ms with the z column split in two);
+    // at 512^3 the two shapes are within 1% (1.077 / 1.086 ms)
+    if (g.n >= 1024 && g.n % 128 == 0)
+        return cg1_xm<double, 128, 16, 512>(xm, g.n, r_in, r_out, p_in, p_out, x, minv, inv_h2, st,
+                                            partials, 0, pslot, s);
     if (g.n % 64 == 0)
-        return cg1_t<double, 64, 32, 512>(g.n, r_in, r_out, p_in, p_out, x, minv, inv_h2, st,
-                                          partials, 0, s);
-    return cg1_t<double, 32, 16, 256>(g.n, r_in, r_out, p_in, p_out, x, minv, inv_h2, st, partials,
-                                      0, s);
+        return cg1_xm<double, 64, 32, 512>(xm, g.n, r_in, r_out, p_in, p_out, x, minv, inv_h2, st,
+                                           partials, 0, pslot, s);
+    return cg1_xm<double, 32, 16, 256>(xm, g.n, r_in, r_out, p_in, p_out, x, minv, inv_h2, st,
+                                       partials, 0, pslot, s);
+}
+
+static int stream_blocks(int64_t n);
+
+// x += alpha_pend p[pend_slot] when an odd sweep left its update pending;
+// the flag is cleared by a second launch (blocks of this one still read it).
+__global__ __launch_bounds__(kNT) void cg1_flush_kernel(int64_t n3, const double* __restrict__ p0,
+                                                        const double* __restrict__ p1,
+                                                        double* __restrict__ x,
+                                                        const DevState* st) {
+    if (!st->cg.xpend) return;
+    const double a = st->cg.alpha_pend;
+    const double* __restrict__ p = st->cg.pend_slot ? p1 : p0;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
+        x[i] = x[i] + a * p[i];
+}
+__global__ void cg1_flush_done_kernel(DevState* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) st->cg.xpend = 0;
+}
+
+hipError_t launch_cg1_flush(int64_t n3, const double* p0, const double* p1, double* x,
+                            DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(cg1_flush_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, p0, p1, x,
+                       (const DevState*)st);
+    hipLaunchKernelGGL(cg1_flush_done_kernel, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
 }
 
 hipError_t launch_cg1_32(const SweepGeo& g, const float* r_in, float* r_out, const float* p_in,
                          float* p_out, float* d, float minvf, float inv_h2f, int pgiven,
-                         DevState* st, double* partials, hipStream_t s) {
-    if (!cg1_supported(g)) return hipErrorInvalidValue;
+                         DevState* st, double* partials, int xm, int pslot, hipStream_t s) {
+    if (!cg1_supported(g) || xm < 0 || xm > 2) return hipErrorInvalidValue;
     if (g.n % 128 == 0)
-        return cg1_t<float, 128, 16, 512>(g.n, r_in, r_out, p_in, p_out, d, minvf, inv_h2f, st,
-                                          partials, pgiven, s);
+        return cg1_xm<float, 128, 16, 512>(xm, g.n, r_in, r_out, p_in, p_out, d, minvf, inv_h2f,
+                                           st, partials, pgiven, pslot, s);
     if (g.n % 64 == 0)
-        return cg1_t<float, 64, 32, 1024>(g.n, r_in, r_out, p_in, p_out, d, minvf, inv_h2f, st,
-                                          partials, pgiven, s);
-    return cg1_t<float, 32, 16, 256>(g.n, r_in, r_out, p_in, p_out, d, minvf, inv_h2f, st,
-                                     partials, pgiven, s);
+        return cg1_xm<float, 64, 32, 1024>(xm, g.n, r_in, r_out, p_in, p_out, d, minvf, inv_h2f,
+                                           st, partials, pgiven, pslot, s);
+    return cg1_xm<float, 32, 16, 256>(xm, g.n, r_in, r_out, p_in, p_out, d, minvf, inv_h2f, st,
+                                      partials, pgiven, pslot, s);
+}
+
+// d += (float)alpha_pend p[pend_slot]: the FP32 inner solve's pending step.
+__global__ __launch_bounds__(kNT) void cg1_flush32_kernel(int64_t n3, const float* __restrict__ p0,
+                                                          const float* __restrict__ p1,
+                                                          float* __restrict__ d,
+                                                          const DevState* st) {
+    if (!st->cg.xpend) return;
+    const float a = (float)st->cg.alpha_pend;
+    const float* __restrict__ p = st->cg.pend_slot ? p1 : p0;
+    for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
+        d[i] = d[i] + a * p[i];
+}
+
+hipError_t launch_cg1_flush32(int64_t n3, const float* p0, const float* p1, float* d,
+                              DevState* st, hipStream_t s) {
+    hipLaunchKernelGGL(cg1_flush32_kernel, dim3(stream_blocks(n3)), dim3(kNT), 0, s, n3, p0, p1, d,
+                       (const DevState*)st);
+    hipLaunchKernelGGL(cg1_flush_done_kernel, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
 }
 
 hipError_t launch_dir32(const SweepGeo& g, const float* r, const float* p_old, float* p_new,
@@ -1441,8 +1595,6 @@ __global__ __launch_bounds__(kNT) void shift_kernel(int64_t n3, double* __restri
     for (int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x; i < n3; i += (int64_t)gridDim.x * kNT)
         v[i] = v[i] - m;
 }
-
-static int stream_blocks(int64_t n);
 
 hipError_t launch_field(const SweepGeo& g, double* phi, double* ex, double* ey, double* ez,
                         double ehalf, double h3, DevState* st, double* partials, hipStream_t s) {

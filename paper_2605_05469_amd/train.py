@@ -5,9 +5,10 @@ The training set is made by the method itself: Landau-damping runs on a
 [0.01, 0.1], k in {0.5, 1.0}) advanced by this library's plain FP64 PIC step;
 every step contributes its right-hand side b and solved potential phi.  In the
 scale-free form the network maps r_hat = h^2 b / s (s = rms(h^2 b)) to the
-correction e_hat = phi / s, so one network serves any grid spacing.  Every
-forward, backward and Adam update runs in the library's kernels
-(pic_net_train_step).
+correction e_hat = phi / s, so one network serves any grid spacing.  The
+pairs are scaled (pic_net_make_pair), and every forward, backward, loss and
+Adam update runs (pic_net_train_step, pic_net_loss), in the library's
+kernels; torch only holds the device buffers.
 
     python -m paper_2605_05469_amd.train --out weights.npy
 """
@@ -26,9 +27,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def generate_pairs(N=128, ppc=8, alphas=None, ks=(0.5, 1.0), steps=100, seed=5000, dt=0.05,
-                   rtol=1e-10, device="cuda", stride=1, diffs=True):
-    """Run the plain solver and keep (r_hat, e_hat) FP32 pairs on the device.
+def generate_pairs(net, N=128, ppc=8, alphas=None, ks=(0.5, 1.0), steps=100, seed=5000,
+                   dt=0.05, rtol=1e-10, device="cuda", stride=1, diffs=True):
+    """Run the plain solver and keep (r_hat, e_hat) FP32 pairs on the device,
+    scaled by the library (pic_net_make_pair on the training network `net`).
     With `diffs`, the step-to-step changes (b_t - b_{t-1}, phi_t - phi_{t-1})
     are kept too: by linearity they are exact pairs as well, and they look like
     the residual corrections the preconditioner sees inside the solve."""
@@ -56,17 +58,18 @@ def generate_pairs(N=128, ppc=8, alphas=None, ks=(0.5, 1.0), steps=100, seed=500
                 info = sim.step()
                 if s % stride:
                     continue
-                b = sim.rho * (h * h)
-                sc = torch.sqrt(torch.mean(b * b))
-                rhs.append((b / sc).float())
-                tgt.append((sim.phi / sc).float())
+                r_t = torch.empty(N ** 3, dtype=torch.float32, device=device)
+                t_t = torch.empty_like(r_t)
+                net.make_pair(sim.rho, sim.phi, h, r_t, t_t)
+                rhs.append(r_t)
+                tgt.append(t_t)
                 if diffs and prev is not None:
-                    db, dphi = b - prev[0], sim.phi - prev[1]
-                    sd = torch.sqrt(torch.mean(db * db))
-                    if float(sd) > 0:
-                        rhs.append((db / sd).float())
-                        tgt.append((dphi / sd).float())
-                prev = (b, sim.phi.clone()) if diffs else None
+                    r_d = torch.empty_like(r_t)
+                    t_d = torch.empty_like(r_t)
+                    if net.make_pair(sim.rho, sim.phi, h, r_d, t_d, prev[0], prev[1]) > 0:
+                        rhs.append(r_d)
+                        tgt.append(t_d)
+                prev = (sim.rho.clone(), sim.phi.clone()) if diffs else None
             log("run %d (k=%.2f alpha=%.3f): %d pairs, last solve %d iterations"
                 % (run, k, a, len(rhs), info["iterations"]))
             run += 1
@@ -114,22 +117,10 @@ def train(net, rhs, tgt, epochs=10, lr=1e-3, lam=1.0, seed=0, holdout=0.1, log_e
 
 
 def evaluate(net, rhs, tgt, which, lam=1.0):
-    """Mean loss over the given pairs without updating (tiny-lr probes are not
-    used: the loss is recomputed from a forward pass)."""
-    import torch
-
+    """Mean loss over the given pairs without an update (pic_net_loss)."""
     tot = 0.0
-    out = torch.empty_like(rhs[0])
     for i in which:
-        net.forward(rhs[i], out)
-        r, t = rhs[i].double(), tgt[i].double()
-        o = out.double()
-        n = round(o.numel() ** (1 / 3))
-        ov = o.view(n, n, n)
-        a1 = 6 * ov - sum(torch.roll(ov, s, d) for d in range(3) for s in (1, -1))
-        l1 = torch.sum((o - t) ** 2) / torch.sum(t * t)
-        l2 = torch.sum((a1.reshape(-1) - r) ** 2) / torch.sum(r * r)
-        tot += float(l1 + lam * l2)
+        tot += net.loss(rhs[i], tgt[i], lam=lam)
     return tot / max(1, len(which))
 
 
@@ -179,12 +170,12 @@ def main():
     import paper_2605_05469_amd as P
 
     torch.cuda.set_device(0)
-    t0 = time.time()
-    rhs, tgt = generate_pairs(N=args.grid, ppc=args.ppc, steps=args.steps,
-                              diffs=not args.no_diffs)
-    log("generated %d pairs in %.1f s" % (len(rhs), time.time() - t0))
     net = P.Net(args.grid, training=True)
     net.set_params(torch.from_numpy(init_params(args.seed)).cuda())
+    t0 = time.time()
+    rhs, tgt = generate_pairs(net, N=args.grid, ppc=args.ppc, steps=args.steps,
+                              diffs=not args.no_diffs)
+    log("generated %d pairs in %.1f s" % (len(rhs), time.time() - t0))
     params = torch.empty(P.unet_param_count(), dtype=torch.float32, device="cuda")
 
     def save(ep):

@@ -1,7 +1,10 @@
 """Parity of the network kernels (BF16 MFMA convolutions, pooling, loss, Adam,
 the whole U-Net and the flexible-PCG solver) with the FP64 oracle on the same
 BF16-rounded operands."""
+import hashlib
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -308,3 +311,86 @@ def test_learned_warm_start_then_mixed(pic, orc):
     info = ctx.poisson(torch.from_numpy(b).cuda(), x)
     assert info["converged"] and info["outer_iterations"] >= 1 and info["flex_iterations"] == 0
     assert orc.residual_norm(N, P.L, b, x.cpu().numpy()) <= 1.0001e-10 * np.linalg.norm(b)
+
+
+# ---------------------------------------------- the trained network -----
+
+_GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fcg_trained.json")
+_WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2605_05469_amd", "weights", "unet_landau128.npy")
+
+
+def _trained():
+    with open(_GOLD) as f:
+        gold = json.load(f)
+    with open(_WEIGHTS, "rb") as f:
+        assert hashlib.sha256(f.read()).hexdigest() == gold["weights_sha256"], \
+            "fcg_trained.json was written for other weights"
+    return gold, np.load(_WEIGHTS)
+
+
+@pytest.mark.parametrize("N", [32, 64, 128])
+def test_trained_fcg_matches_oracle(pic, orc, N):
+    """Flexible PCG with the committed trained network (no warm start, as
+    in the oracle's flexible CG) against the oracle's flexible CG with the
+    same weights (tests/golden/fcg_trained.json, written by
+    make_fcg_trained.py from the oracle alone): neither side falls back,
+    the iteration counts agree within 2 (the BF16 network with FP32
+    accumulation against its FP64 emulation), the true residual under the
+    oracle's operator meets 1e-10, and both need far fewer iterations than
+    Jacobi-PCG."""
+    gold, w = _trained()
+    case = gold["cases"][str(N)]
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=7000 + N)
+    b, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    prm = pic.landau_params(N, 8, np_max=0, solver="fcg_learned", max_iter=gold["max_iter"],
+                            fcg_window=gold["window"], rtol=gold["rtol"])
+    prm.flags = pic.FLAG_NO_WARM_START
+    ctx = pic.Context(prm)
+    ctx.set_unet(f32dev(w))
+    x = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    info = ctx.poisson(torch.from_numpy(b).cuda(), x)
+    assert info["converged"], info
+    assert orc.residual_norm(N, P.L, b, x.cpu().numpy()) <= 1.0001e-10 * np.linalg.norm(b)
+    assert not case["fcg_fell_back"] and case["fcg_converged"]
+    assert not info["fell_back"], (info, case)
+    assert info["flex_iterations"] == info["iterations"]
+    assert abs(info["iterations"] - case["fcg_iters"]) <= 2, (info["iterations"], case)
+    assert case["fcg_iters"] <= case["pcg_iters"] / 2
+
+
+def test_training_pair_and_loss(pic):
+    """pic_net_make_pair (the scale-free pair the training uses) against its
+    definition in FP64, and pic_net_loss against the oracle's loss of the
+    oracle's forward pass."""
+    n = 16
+    specs = unet.layer_specs()
+    p = _params(21)
+    net = pic.Net(n, training=True)
+    net.set_params(f32dev(unet.flatten(p, specs)))
+    rng = np.random.default_rng(22)
+    rho, phi, rho0, phi0 = (rng.standard_normal(n ** 3) for _ in range(4))
+    h = 0.25
+    dev = [torch.from_numpy(a).cuda() for a in (rho, phi, rho0, phi0)]
+    r_t = torch.empty(n ** 3, dtype=torch.float32, device="cuda")
+    t_t = torch.empty_like(r_t)
+    for prev in (False, True):
+        if prev:
+            s = net.make_pair(dev[0], dev[1], h, r_t, t_t, dev[2], dev[3])
+            u, e = h * h * (rho - rho0), phi - phi0
+        else:
+            s = net.make_pair(dev[0], dev[1], h, r_t, t_t)
+            u, e = h * h * rho, phi
+        s_ref = math.sqrt(np.mean(u * u))
+        assert abs(s - s_ref) <= 1e-13 * s_ref
+        assert rel(r_t.cpu().numpy().astype(np.float64), u / s_ref) <= 1e-7
+        assert rel(t_t.cpu().numpy().astype(np.float64), e / s_ref) <= 1e-7
+    r32 = r_t.cpu().numpy().astype(np.float64)
+    t32 = t_t.cpu().numpy().astype(np.float64)
+    out, _ = unet.forward(p, r32.reshape(n, n, n), specs)
+    Lref, _ = unet.loss(out, t32.reshape(n, n, n), r32.reshape(n, n, n), lam=0.5)
+    L = net.loss(r_t, t_t, lam=0.5)
+    assert abs(L - Lref) <= 1e-2 * Lref
+    # no update: the same loss again
+    assert net.loss(r_t, t_t, lam=0.5) == L

@@ -132,3 +132,38 @@ def test_flatten_roundtrip_and_sizes():
     assert all(np.array_equal(p[k], q[k]) for k in p)
     n = sum(int(np.prod(unet.weight_shape(a, b))) + b for (_, a, b) in specs)
     assert flat.size == n
+
+
+@pytest.mark.slow
+def test_trained_fcg_golden_values_reproduce(orc):
+    """tests/golden/fcg_trained.json holds the oracle's flexible CG with the
+    committed trained weights (written by make_fcg_trained.py); the 32^3
+    entry is recomputed here so the stored values stay tied to the oracle
+    as it is."""
+    import hashlib
+    import json
+    import os
+    from paper_2605_05469_amd import synth
+    here = os.path.dirname(os.path.abspath(__file__))
+    wpath = os.path.join(os.path.dirname(here), "paper_2605_05469_amd", "weights",
+                         "unet_landau128.npy")
+    with open(os.path.join(here, "golden", "fcg_trained.json")) as f:
+        gold = json.load(f)
+    with open(wpath, "rb") as f:
+        assert hashlib.sha256(f.read()).hexdigest() == gold["weights_sha256"]
+    N = 32
+    case = gold["cases"][str(N)]
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=7000 + N)
+    b, _ = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    specs = unet.layer_specs()
+    params = unet.unflatten(np.load(wpath).astype(np.float64), specs)
+    h = P.L / N
+    _, info = orc.fcg(N, P.L, b, np.zeros(N ** 3), gold["rtol"], gold["max_iter"],
+                      lambda r: unet.precondition(params, r, h, specs), window=gold["window"])
+    assert info["converged"] and not info["fell_back"]
+    assert abs(info["iters"] - case["fcg_iters"]) <= 1
+    _, pinfo = orc.pcg(N, P.L, b, np.zeros(N ** 3), gold["rtol"], 20000)
+    assert pinfo["iters"] == case["pcg_iters"]
+    # the trained network is a real preconditioner: far fewer iterations
+    assert info["iters"] <= 0.4 * pinfo["iters"]
