@@ -1207,7 +1207,7 @@ int pic_sort_cells(pic_ctx* c, int64_t np, const uint32_t* key, const double* co
                     return fail(PIC_ERR_INVALID, "dst must not alias src");
         }
     }
-    HIPCHK(launch_sort_cells(np, c->n3, key, src, dst, cell_start, perm, &c->sort,
+    HIPCHK(launch_sort_cells(np, c->p.n, key, src, dst, cell_start, perm, &c->sort,
                              (hipStream_t)stream));
     return PIC_OK;
 }
@@ -1333,8 +1333,8 @@ int pic_gather_push(pic_ctx* c, int64_t np, double* x, double* y, double* z, dou
     if (np == 0) return PIC_OK;
     NEED(x, "x"); NEED(y, "y"); NEED(z, "z"); NEED(vx, "vx"); NEED(vy, "vy"); NEED(vz, "vz");
     NEED(ex, "ex"); NEED(ey, "ey"); NEED(ez, "ez");
-    HIPCHK(launch_gather_push(np, x, y, z, vx, vy, vz, ex, ey, ez, key_out, c->p.n, c->inv_h, c->L,
-                              c->p.dt, c->coef_push, (hipStream_t)stream));
+    HIPCHK(launch_gather_push(np, x, y, z, vx, vy, vz, ex, ey, ez, key_out, nullptr, c->p.n,
+                              c->inv_h, c->L, c->p.dt, c->coef_push, (hipStream_t)stream));
     return PIC_OK;
 }
 
@@ -1366,10 +1366,13 @@ static int check_parts(pic_ctx* c, pic_particles* P, pic_fields* F) {
     return PIC_OK;
 }
 
-static int sort_swap(pic_ctx* c, pic_particles* P, hipStream_t s) {
+// Sort into the second set of arrays and swap; from_rec: the push left the
+// particles in the sort's record array (the current arrays are stale).
+static int sort_swap(pic_ctx* c, pic_particles* P, hipStream_t s, bool from_rec = false) {
     const double* src[6] = {P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy, P->cur.vz};
     double* dst[6] = {P->alt.x, P->alt.y, P->alt.z, P->alt.vx, P->alt.vy, P->alt.vz};
-    HIPCHK(launch_sort_cells(P->np, c->n3, P->key, src, dst, P->cell_start, nullptr, &c->sort, s));
+    HIPCHK(launch_sort_cells(P->np, c->p.n, P->key, from_rec ? nullptr : src, dst, P->cell_start,
+                             nullptr, &c->sort, s));
     pic_particle_arrays t = P->cur;
     P->cur = P->alt;
     P->alt = t;
@@ -1485,10 +1488,10 @@ int pic_step(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, v
         return PIC_OK;
     }
     HIPCHK(launch_gather_push(P->np, P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy, P->cur.vz,
-                              F->ex, F->ey, F->ez, P->key, c->p.n, c->inv_h, c->L, c->p.dt,
-                              c->coef_push, s));
+                              F->ex, F->ey, F->ez, P->key, c->sort.rec, c->p.n, c->inv_h, c->L,
+                              c->p.dt, c->coef_push, s));
     RETCHK(T.mark(1, s));
-    RETCHK(sort_swap(c, P, s));
+    RETCHK(sort_swap(c, P, s, true));
     RETCHK(T.mark(2, s));
     HIPCHK(launch_deposit(P->np, P->cur.x, P->cur.y, P->cur.z, P->np > 0 ? P->cell_start : nullptr,
                           F->rho, c->p.n, c->inv_h, c->qh3, c->p.rho_bg, c->st, c->partials, dep_scratch(c), s));

@@ -27,7 +27,12 @@ namespace pic {
 
 constexpr int kPT = 256;
 
-// CIC gather of (Ex, Ey, Ez) at one particle.
+// CIC gather of (Ex, Ey, Ez) at one particle.  The two x corners of a
+// vertex row are adjacent in memory unless the row wraps (i0 = n - 1), so
+// each row's pair is one 16-byte load (8-byte aligned); the wrapping lanes
+// take their second corner from the start of the row.  Values and summation
+// order are those of the eight separate loads.
+typedef double pair_u __attribute__((ext_vector_type(2), aligned(8)));
 __device__ __forceinline__ void gather3(double px, double py, double pz, int n, double inv_h,
                                         const double* __restrict__ ex,
                                         const double* __restrict__ ey,
@@ -41,6 +46,10 @@ __device__ __forceinline__ void gather3(double px, double py, double pz, int n, 
     sx = 0.0;
     sy = 0.0;
     sz = 0.0;
+    // the pair starts at i0, or at n - 2 for the wrapping corner (grids
+    // have n >= 32)
+    const bool wraps = i0 == n - 1;
+    const int xs = wraps ? n - 2 : i0;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
         const double wz = c ? w2 : 1.0 - w2;
@@ -52,17 +61,22 @@ __device__ __forceinline__ void gather3(double px, double py, double pz, int n, 
             int vy = i1 + b;
             vy = vy == n ? 0 : vy;
             const size_t row = ((size_t)vz * n + vy) * n;
-#pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                const double wx = a ? w0 : 1.0 - w0;
-                int vx = i0 + a;
-                vx = vx == n ? 0 : vx;
-                const size_t v = row + vx;
-                const double W = (wz * wy) * wx;
-                sx = sx + W * ex[v];
-                sy = sy + W * ey[v];
-                sz = sz + W * ez[v];
+            const pair_u px2 = *(const pair_u*)(ex + row + xs);
+            const pair_u py2 = *(const pair_u*)(ey + row + xs);
+            const pair_u pz2 = *(const pair_u*)(ez + row + xs);
+            double ex0 = px2.x, ex1 = px2.y, ey0 = py2.x, ey1 = py2.y, ez0 = pz2.x, ez1 = pz2.y;
+            if (wraps) {
+                ex0 = ex1; ey0 = ey1; ez0 = ez1;
+                ex1 = ex[row]; ey1 = ey[row]; ez1 = ez[row];
             }
+            const double W0 = (wz * wy) * (1.0 - w0);
+            const double W1 = (wz * wy) * w0;
+            sx = sx + W0 * ex0;
+            sy = sy + W0 * ey0;
+            sz = sz + W0 * ez0;
+            sx = sx + W1 * ex1;
+            sy = sy + W1 * ey1;
+            sz = sz + W1 * ez1;
         }
     }
 }
@@ -80,14 +94,29 @@ __global__ __launch_bounds__(kPT) void keys_kernel(int64_t np, const double* __r
 // them before the first gather: 6 kPushK streaming loads in flight per
 // thread instead of 6.  The outputs are written once and not read again by
 // this kernel, so they bypass L2 retention.
+//
+// With a record array (the PIC step, before the cell sort) the new state
+// goes to 64-byte records (x, y | z, vx | vy, vz | padding) in the input
+// order instead of back into the six arrays: the sort then gathers one
+// record per sorted slot rather than six scattered 8-byte values.
 constexpr int kPushK = 4;
+template <bool REC>
 __global__ __launch_bounds__(kPT) void gather_push_kernel(
     int64_t np, double* __restrict__ x, double* __restrict__ y, double* __restrict__ z,
     double* __restrict__ vx, double* __restrict__ vy, double* __restrict__ vz,
     const double* __restrict__ ex, const double* __restrict__ ey, const double* __restrict__ ez,
-    uint32_t* __restrict__ key, int n, double inv_h, double L, double dt, double coef) {
+    uint32_t* __restrict__ key, double2* __restrict__ rec, int n, double inv_h, double L,
+    double dt, double coef) {
+    // records: each wave puts its 64 particles' records in its own 4 KB of
+    // LDS, then stores them as four runs of 1 KB (consecutive lanes,
+    // consecutive 16-byte parts)
+    __shared__ double2 srec[REC ? kPT * 4 : 1];
+    const int lane = threadIdx.x & (kWave - 1);
+    double2* wrec = srec + (REC ? (threadIdx.x - lane) * 4 : 0);
     const int64_t stride = (int64_t)gridDim.x * kPT * kPushK;
-    for (int64_t p0 = (int64_t)blockIdx.x * kPT * kPushK + threadIdx.x; p0 < np; p0 += stride) {
+    // the trip count is uniform over the workgroup (particles past np idle)
+    for (int64_t b0 = (int64_t)blockIdx.x * kPT * kPushK; b0 < np; b0 += stride) {
+        const int64_t p0 = b0 + threadIdx.x;
         double px[kPushK], py[kPushK], pz[kPushK], qx[kPushK], qy[kPushK], qz[kPushK];
 #pragma unroll
         for (int k = 0; k < kPushK; ++k) {
@@ -103,7 +132,7 @@ __global__ __launch_bounds__(kPT) void gather_push_kernel(
 #pragma unroll
         for (int k = 0; k < kPushK; ++k) {
             const int64_t p = p0 + (int64_t)kPT * k;
-            if (p >= np) break;
+            if (!REC && p >= np) break;
             double sx, sy, sz;
             gather3(px[k], py[k], pz[k], n, inv_h, ex, ey, ez, sx, sy, sz);
             const double ux = qx[k] + coef * sx;
@@ -112,13 +141,30 @@ __global__ __launch_bounds__(kPT) void gather_push_kernel(
             const double nx = wrap(px[k] + dt * ux, L);
             const double ny = wrap(py[k] + dt * uy, L);
             const double nz = wrap(pz[k] + dt * uz, L);
-            __builtin_nontemporal_store(ux, vx + p);
-            __builtin_nontemporal_store(uy, vy + p);
-            __builtin_nontemporal_store(uz, vz + p);
-            __builtin_nontemporal_store(nx, x + p);
-            __builtin_nontemporal_store(ny, y + p);
-            __builtin_nontemporal_store(nz, z + p);
-            if (key) __builtin_nontemporal_store(key_of(nx, ny, nz, n, inv_h), key + p);
+            if (REC) {
+                wrec[4 * lane] = make_double2(nx, ny);
+                wrec[4 * lane + 1] = make_double2(nz, ux);
+                wrec[4 * lane + 2] = make_double2(uy, uz);
+                wrec[4 * lane + 3] = make_double2(0.0, 0.0);
+                __builtin_amdgcn_wave_barrier();
+                const int64_t pb = p - lane;  // the wave's first particle
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int c = q * kWave + lane;  // part c % 4 of record c / 4
+                    if (pb + c / 4 < np) __builtin_nontemporal_store(wrec[c].x, &rec[4 * pb + c].x),
+                                             __builtin_nontemporal_store(wrec[c].y, &rec[4 * pb + c].y);
+                }
+                __builtin_amdgcn_wave_barrier();
+                if (key && p < np) __builtin_nontemporal_store(key_of(nx, ny, nz, n, inv_h), key + p);
+            } else {
+                __builtin_nontemporal_store(ux, vx + p);
+                __builtin_nontemporal_store(uy, vy + p);
+                __builtin_nontemporal_store(uz, vz + p);
+                __builtin_nontemporal_store(nx, x + p);
+                __builtin_nontemporal_store(ny, y + p);
+                __builtin_nontemporal_store(nz, z + p);
+                if (key) __builtin_nontemporal_store(key_of(nx, ny, nz, n, inv_h), key + p);
+            }
         }
     }
 }
@@ -324,12 +370,16 @@ hipError_t launch_keys(int64_t np, const double* x, const double* y, const doubl
 
 hipError_t launch_gather_push(int64_t np, double* x, double* y, double* z, double* vx, double* vy,
                               double* vz, const double* ex, const double* ey, const double* ez,
-                              uint32_t* key, int n, double inv_h, double L, double dt,
-                              double coef, hipStream_t s) {
+                              uint32_t* key, double2* rec, int n, double inv_h, double L,
+                              double dt, double coef, hipStream_t s) {
     if (np == 0) return hipSuccess;
     const int64_t groups = (np + kPushK - 1) / kPushK;
-    hipLaunchKernelGGL(gather_push_kernel, dim3(pblocks(groups, 4096)), dim3(kPT), 0, s, np, x, y,
-                       z, vx, vy, vz, ex, ey, ez, key, n, inv_h, L, dt, coef);
+    if (rec)
+        hipLaunchKernelGGL(gather_push_kernel<true>, dim3(pblocks(groups, 4096)), dim3(kPT), 0, s,
+                           np, x, y, z, vx, vy, vz, ex, ey, ez, key, rec, n, inv_h, L, dt, coef);
+    else
+        hipLaunchKernelGGL(gather_push_kernel<false>, dim3(pblocks(groups, 4096)), dim3(kPT), 0, s,
+                           np, x, y, z, vx, vy, vz, ex, ey, ez, key, rec, n, inv_h, L, dt, coef);
     return hipGetLastError();
 }
 

@@ -10,10 +10,13 @@ namespace pic {
 
 hipError_t launch_keys(int64_t np, const double* x, const double* y, const double* z,
                        uint32_t* key, int n, double inv_h, hipStream_t s);
+// With rec non-NULL the pushed state goes to 64-byte records rec[4p..4p+3]
+// = (x, y), (z, vx), (vy, vz), padding instead of back into x..vz (which
+// are then only read); launch_sort_cells takes such records as its source.
 hipError_t launch_gather_push(int64_t np, double* x, double* y, double* z, double* vx, double* vy,
                               double* vz, const double* ex, const double* ey, const double* ez,
-                              uint32_t* key, int n, double inv_h, double L, double dt,
-                              double coef, hipStream_t s);
+                              uint32_t* key, double2* rec, int n, double inv_h, double L,
+                              double dt, double coef, hipStream_t s);
 hipError_t launch_half_kick(int64_t np, const double* x, const double* y, const double* z,
                             double* vx, double* vy, double* vz, const double* ex,
                             const double* ey, const double* ez, int n, double inv_h, double coef,
@@ -32,16 +35,19 @@ hipError_t launch_deposit(int64_t np, const double* x, const double* y, const do
 struct SortScratch {
     uint32_t* key[2];
     uint32_t* idx[2];
-    uint32_t* hist;     // 256 * tiles (+ scan sums)
+    uint32_t* hist;     // radix * tiles (+ scan sums)
     uint32_t* sums;
+    double2* rec;       // 4 * cap: particle records (x, y | z, vx | vy, vz | pad)
     int64_t cap;        // particles
 };
 size_t sort_scratch_bytes(int64_t np_max);
 void sort_scratch_carve(void* base, int64_t np_max, SortScratch* s);
-// Sorts key[0..np) (values < ncell); writes the permutation (source index of
-// each sorted slot) to perm_out (may be NULL), cell_start[0..ncell], and the
-// six permuted particle arrays src -> dst.
-hipError_t launch_sort_cells(int64_t np, int64_t ncell, const uint32_t* key,
+// Sorts key[0..np) (values < n^3); writes the permutation (source index of
+// each sorted slot) to perm_out (may be NULL), cell_start[0..n^3], and the
+// six permuted particle arrays dst.  The source is sc->rec as filled by
+// launch_gather_push when src is NULL, else the six arrays src (packed into
+// sc->rec first).
+hipError_t launch_sort_cells(int64_t np, int n, const uint32_t* key,
                              const double* const src[6], double* const dst[6],
                              uint32_t* cell_start, uint32_t* perm_out, SortScratch* sc,
                              hipStream_t s);

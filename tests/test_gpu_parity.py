@@ -155,6 +155,25 @@ def test_sort_edge_cases(pic, orc, case):
     _sort_case(pic, orc, N, np.asarray(keys))
 
 
+@pytest.mark.parametrize("N,kind", [(64, "near"), (64, "random"), (128, "near"), (128, "random")])
+def test_sort_multi_tile(pic, orc, N, kind):
+    """Several 12288-key tiles and a ragged last one; 18-bit keys (two 9-bit
+    passes) at 64^3, 21-bit keys (three 7-bit passes) at 128^3; keys either
+    uniform or the near-sorted keys of a cell-sorted state whose particles
+    moved a few cells (the PIC step's case), so runs of equal digits are long
+    and ties are many."""
+    rng = np.random.default_rng(N + len(kind))
+    n = 5 * 12288 + 777
+    if kind == "random":
+        keys = rng.integers(0, N ** 3, n)
+    else:
+        c = np.sort(rng.integers(0, N ** 3, n))
+        iz, iy, ix = c // (N * N), (c // N) % N, c % N
+        d = np.rint(rng.standard_normal((3, n)) * 2).astype(np.int64)
+        keys = (((iz + d[0]) % N) * N + (iy + d[1]) % N) * N + (ix + d[2]) % N
+    _sort_case(pic, orc, N, np.asarray(keys))
+
+
 # ------------------------------------------------------------- deposit ----
 
 @pytest.mark.parametrize("N,ppc", [(32, 8), (64, 3)])
