@@ -44,6 +44,11 @@ SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 
 # every other iteration): 16 and 24, 20 on average.
 SINGLE_SWEEP_BYTES = 40
 SINGLE_SWEEP_BYTES_FP32 = 20
+# s-step form (three iterations per outer step): Gram sweep reads p and r,
+# update sweep reads p, r, x and writes them
+SSTEP_S = 3
+SSTEP_GRAM_BYTES = 16
+SSTEP_UPD_BYTES = 48
 # HBM bytes per launch of the dominant kernel at 512^3, from rocprofv3
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
@@ -186,7 +191,8 @@ def bench_poisson(args):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()  # the library allocates the network outside torch
     forms = {}
-    all_forms = ("pcg_fp64", "pcg_fp64_two_sweep", "pcg_mixed", "pcg_mixed_reliable",
+    all_forms = ("pcg_fp64", "pcg_fp64_single", "pcg_fp64_two_sweep", "pcg_mixed",
+                 "pcg_mixed_reliable",
                  "pcg_ssor", "pcg_ssor_unfused",
                  "fcg_learned",
                  "learned_warm_start_only", "learned_warm_start_mixed", "fft", "fft_spectral")
@@ -211,7 +217,8 @@ def bench_poisson(args):
                       | (P.FLAG_LEARNED_MIXED if form == "learned_warm_start_mixed" else 0)
                       | (P.FLAG_FFT_SPECTRAL if form == "fft_spectral" else 0)
                       | (P.FLAG_SSOR_UNFUSED if form == "pcg_ssor_unfused" else 0)
-                      | (P.FLAG_PCG_TWO_SWEEP if form == "pcg_fp64_two_sweep" else 0))
+                      | (P.FLAG_PCG_TWO_SWEEP if form == "pcg_fp64_two_sweep" else 0)
+                      | (P.FLAG_PCG_SINGLE_SWEEP if form == "pcg_fp64_single" else 0))
         ctx.set_solver(solver)
         phi = torch.zeros_like(rho)
         torch.cuda.synchronize()
@@ -342,6 +349,9 @@ def main():
     ap.add_argument("--two-sweep", action="store_true",
                     help="FP64 Jacobi-PCG as a direction and an update sweep per iteration "
                          "(instead of the single-reduction sweep)")
+    ap.add_argument("--single-sweep", action="store_true",
+                    help="FP64 Jacobi-PCG as one single-reduction sweep per iteration "
+                         "(instead of the s-step form's Gram and update sweeps)")
     ap.add_argument("--warm-start-only", action="store_true",
                     help="learned form: network warm start, then Jacobi-PCG")
     ap.add_argument("--no-learned", action="store_true",
@@ -384,6 +394,8 @@ def main():
         flags |= P.FLAG_FFT_SPECTRAL
     if args.two_sweep:
         flags |= P.FLAG_PCG_TWO_SWEEP
+    if args.single_sweep:
+        flags |= P.FLAG_PCG_SINGLE_SWEEP
     fp32_inner = args.solver == "pcg_mixed" or args.learned_mixed
     run = run_pic(args, args.solver, flags, args.inner_rtol, fp32_inner, "main")
     sim, ctx, p, infos = run.pop("_sim"), run.pop("_ctx"), run.pop("_p"), run.pop("_infos")
@@ -557,7 +569,22 @@ def run_pic(args, solver, flags, inner_rtol, fp32_inner, label):
     # two sweeps are asked for; its launches are sampled in timing slot 0
     single = (solver in ("pcg_fp64", "pcg_mixed", "fcg_learned")
               and not (flags & P.FLAG_PCG_TWO_SWEEP) and N % 32 == 0)
-    if single:
+    sstep = (solver == "pcg_fp64" and N % 32 == 0
+             and not (flags & (P.FLAG_PCG_TWO_SWEEP | P.FLAG_PCG_SINGLE_SWEEP)))
+    if sstep:
+        # s-step form: per outer step (three iterations) a Gram sweep reading
+        # p and r (16 B/point) and an update sweep reading p, r, x and writing
+        # them (48 B/point); timing slots 0 and 1
+        gbs_gram = SSTEP_GRAM_BYTES * n3 / (ms_dir * 1e-3) / 1e9 if ms_dir > 0 else 0.0
+        gbs_upd = SSTEP_UPD_BYTES * n3 / (ms_upd * 1e-3) / 1e9 if ms_upd > 0 else 0.0
+        kernels = {"pcg_sstep_gram": {"avg_ms": ms_dir, "launches_timed": cnt_dir,
+                                      "bytes_per_point": SSTEP_GRAM_BYTES, "gbs": gbs_gram},
+                   "pcg_sstep_update": {"avg_ms": ms_upd, "launches_timed": cnt_upd,
+                                        "bytes_per_point": SSTEP_UPD_BYTES, "gbs": gbs_upd}}
+        gbs_iter = ((SSTEP_GRAM_BYTES + SSTEP_UPD_BYTES) * n3 / ((ms_dir + ms_upd) * 1e-3) / 1e9
+                    if ms_upd > 0 else 0.0)
+        dom, gbs_dom = "pcg_sstep_update", gbs_upd
+    elif single:
         b1 = SINGLE_SWEEP_BYTES_FP32 if fp32_inner else SINGLE_SWEEP_BYTES
         dom = "pcg_single_sweep_fp32" if fp32_inner else "pcg_single_sweep"
         gbs_one = b1 * n3 / (ms_dir * 1e-3) / 1e9 if ms_dir > 0 else 0.0
@@ -581,7 +608,8 @@ def run_pic(args, solver, flags, inner_rtol, fp32_inner, label):
     traffic = SWEEP_TRAFFIC.get((N, "pcg_mixed" if fp32_inner else solver, dom))
     return {
         "s_per_step": s_step,
-        "pcg_form": "single_reduction_sweep" if single else "two_sweeps",
+        "pcg_form": ("sstep_%d" % SSTEP_S if sstep else
+                     "single_reduction_sweep" if single else "two_sweeps"),
         "particles_per_s": npart / s_step,
         "pcg_iterations_per_step": iters,
         "pcg_outer_iterations_per_step": sum(i["outer_iterations"] for i in infos) / len(infos),

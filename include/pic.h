@@ -110,12 +110,22 @@ enum {
                                       solve and the mixed form's FP32 inner
                                       solves): one direction sweep and one
                                       update sweep per iteration (two
-                                      reductions) instead of the default
-                                      single-reduction sweep (the
-                                      Chronopoulos-Gear arrangement of the same
-                                      iteration: 48 instead of 64 bytes per
-                                      grid point in FP64).  Bounded boxes
-                                      always take the two-sweep form. */
+                                      reductions; 64 bytes per grid point in
+                                      FP64).  Bounded boxes always take this
+                                      form. */
+#define PIC_FLAG_PCG_SINGLE_SWEEP 128 /* FP64 Jacobi-PCG on the periodic box:
+                                      one single-reduction sweep per
+                                      iteration (the Chronopoulos-Gear
+                                      arrangement; 40 bytes per grid point)
+                                      instead of the default s-step form (per
+                                      three iterations one Gram sweep over a
+                                      Chebyshev basis of p and r and one
+                                      update sweep: 64 bytes per grid point).
+                                      All three forms give the textbook
+                                      iterates up to rounding.  The mixed
+                                      form's FP32 inner solves take the
+                                      single-reduction sweep unless
+                                      PIC_FLAG_PCG_TWO_SWEEP is set. */
 
 typedef struct pic_params {
     int32_t n;            /* grid points per axis N                         */
@@ -267,10 +277,12 @@ int pic_deposit_cic_noalloc(const pic_params *params, int64_t np, const double *
  * operator on the context's box (periodic unless pic_params.bc says
  * otherwise), by the solver form selected in the context, starting from the
  * phi passed in (the previous step's solution, Sec. 4.1), to
- * ||rho - A phi|| <= rtol ||rho||.  Jacobi-PCG on the periodic box runs as
- * one sweep per iteration with a single reduction (Chronopoulos-Gear: the
- * same iterates as the textbook recurrences in exact arithmetic; see
- * PIC_FLAG_PCG_TWO_SWEEP).  Every candidate that meets the tolerance by its
+ * ||rho - A phi|| <= rtol ||rho||.  FP64 Jacobi-PCG on the periodic box runs
+ * in s-step form: per three iterations a Gram sweep and an update sweep,
+ * the iteration count exact (the stop test runs after every iteration on
+ * the Gram matrix); the same iterates as the textbook recurrences in exact
+ * arithmetic (see PIC_FLAG_PCG_SINGLE_SWEEP, PIC_FLAG_PCG_TWO_SWEEP for the
+ * other arrangements).  Every candidate that meets the tolerance by its
  * recursive residual is verified by the true residual, which replaces the
  * recursive one when it does not.  rho must have zero mean (not so on a
  * Dirichlet box).  If ex, ey, ez are all non-NULL, the field is computed as

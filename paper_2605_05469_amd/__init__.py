@@ -25,6 +25,7 @@ FLAG_LEARNED_MIXED = 8
 FLAG_FFT_SPECTRAL = 16
 FLAG_SSOR_UNFUSED = 32
 FLAG_PCG_TWO_SWEEP = 64
+FLAG_PCG_SINGLE_SWEEP = 128
 
 # pic_params.bc: the box's boundary kind (the particle phases need PERIODIC)
 BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2

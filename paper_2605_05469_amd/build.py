@@ -13,7 +13,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic.so")
 
 SOURCES = ["stencil.hip", "particles.hip", "sort.hip", "net_kernels.hip", "net.hip", "fft.hip", "pif.hip",
-           "capi.hip", "capi_net.hip", "noalloc.hip"]
+           "capi.hip", "capi_net.hip", "noalloc.hip", "sstep.hip"]
 ROCM_LIB = "/opt/rocm/lib"
 
 FLAGS = [

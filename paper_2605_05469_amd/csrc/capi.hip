@@ -96,7 +96,7 @@ static bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 constexpr int32_t kKnownFlags = PIC_FLAG_NO_WARM_START | PIC_FLAG_WARM_START_ONLY |
                                  PIC_FLAG_MIXED_RELIABLE | PIC_FLAG_LEARNED_MIXED |
                                  PIC_FLAG_FFT_SPECTRAL | PIC_FLAG_SSOR_UNFUSED |
-                                 PIC_FLAG_PCG_TWO_SWEEP;
+                                 PIC_FLAG_PCG_TWO_SWEEP | PIC_FLAG_PCG_SINGLE_SWEEP;
 
 // The solver forms that take a bounded box: the matrix-free stencil ones.
 // The FFT form and the network (periodic convolutions) need the periodic box.
@@ -168,6 +168,17 @@ static int dev_alloc(pic_ctx* c, void** out, size_t bytes) {
     }
     c->allocs.push_back(ptr);
     *out = ptr;
+    return PIC_OK;
+}
+
+// The sort's particle records (64 bytes per particle) are allocated by the
+// first call that sorts (a context that only deposits and solves never
+// needs them).
+static int ensure_rec(pic_ctx* c) {
+    if (c->sort.rec || c->p.np_max <= 0) return PIC_OK;
+    void* m = nullptr;
+    RETCHK(dev_alloc(c, &m, sort_rec_bytes(c->p.np_max)));
+    c->sort.rec = (double2*)m;
     return PIC_OK;
 }
 
@@ -373,9 +384,61 @@ static int pcg64_iterate_cg1(pic_ctx* c, const double* b, double* x, hipStream_t
     }
 }
 
+// s-step form: batches of (Gram sweep, update sweep) pairs, each pair up to
+// kSstepS iterations; p and r alternate between two buffers each (the
+// update sweep reads both as halos while writing the new ones).  Every
+// (re)computed residual lands in c->r with the restart flag set, which makes
+// the next Gram sweep take p = M^{-1} r.  Timing: slot 0 Gram, slot 1 update.
+static bool use_sstep(const pic_ctx* c) {
+    return !(c->p.flags & (PIC_FLAG_PCG_TWO_SWEEP | PIC_FLAG_PCG_SINGLE_SWEEP)) &&
+           sstep_supported(c->geo);
+}
+
+static int pcg64_iterate_sstep(pic_ctx* c, const double* b, double* x, hipStream_t s) {
+    const SweepGeo& g = c->geo;
+    const int K = c->p.check_every > 0 ? (c->p.check_every + kSstepS - 1) / kSstepS : 8;
+    double* rb[2] = {c->r, c->t3};
+    const int npart = 4 * c->npartials;
+    int cur = 0;
+    if (c->timing) RETCHK(timing_events(c, (size_t)4 * K));
+    for (;;) {
+        CgScalars& cg = c->st_host->cg;
+        if (cg.state == CG_RUNNING) {
+            const int64_t it0 = cg.iter;
+            for (int k = 0; k < K; ++k) {
+                const bool tm = timed_iter(c, k);
+                if (tm) HIPCHK(hipEventRecord(c->ev[4 * k + 0], s));
+                HIPCHK(launch_sstep(g, 0, rb[cur], c->p2[cur], nullptr, nullptr, x, c->minv,
+                                    c->st, c->partials, npart, s));
+                if (tm) HIPCHK(hipEventRecord(c->ev[4 * k + 1], s));
+                if (tm) HIPCHK(hipEventRecord(c->ev[4 * k + 2], s));
+                HIPCHK(launch_sstep(g, 1, rb[cur], c->p2[cur], rb[cur ^ 1], c->p2[cur ^ 1], x,
+                                    c->minv, c->st, c->partials, npart, s));
+                if (tm) HIPCHK(hipEventRecord(c->ev[4 * k + 3], s));
+                cur ^= 1;
+            }
+            RETCHK(read_state(c, s));
+            if (c->timing) RETCHK(timing_collect(c, K, (c->st_host->cg.iter - it0 + kSstepS - 1) / kSstepS));
+            if (c->st_host->cg.state == CG_RUNNING && c->st_host->cg.iter == it0)
+                return fail(PIC_ERR_STATE, "solver made no progress (iteration %lld)",
+                            (long long)it0);
+            continue;
+        }
+        if (cg.state == CG_CANDIDATE) {
+            HIPCHK(launch_residual64(g, b, x, c->r, c->minv, c->inv_h2, 0, c->p.rtol, c->p.max_iter,
+                                     c->st, c->partials, s));
+            cur = 0;
+            RETCHK(read_state(c, s));
+            continue;
+        }
+        return PIC_OK;  // CONVERGED, MAXIT, BREAKDOWN, ZERO_RHS
+    }
+}
+
 // Runs batches of (direction, update) sweeps until the device state leaves
 // RUNNING; handles candidate verification (residual replacement).
 static int pcg64_iterate(pic_ctx* c, const double* b, double* x, hipStream_t s) {
+    if (use_sstep(c)) return pcg64_iterate_sstep(c, b, x, s);
     if (use_cg1(c)) return pcg64_iterate_cg1(c, b, x, s);
     const SweepGeo& g = c->geo;
     const int K = c->p.check_every > 0 ? c->p.check_every : 16;
@@ -978,14 +1041,14 @@ static int field(pic_ctx* c, double* phi, double* ex, double* ey, double* ez, hi
 
 extern "C" {
 
-int pic_abi_version(void) { return 2; }
+int pic_abi_version(void) { return 3; }
 
 const char* pic_last_error(void) { return g_err.c_str(); }
 
 size_t pic_workspace_bytes(const pic_params* p) {
     if (validate_params(p) != PIC_OK) return 0;
     size_t b = base_bytes(p);
-    if (p->np_max > 0) b += sort_scratch_bytes(p->np_max);
+    if (p->np_max > 0) b += sort_scratch_bytes(p->np_max) + sort_rec_bytes(p->np_max);
     if (p->solver == PIC_SOLVER_PCG_MIXED) b += mixed_bytes(p);
     if (p->solver == PIC_SOLVER_FCG_LEARNED) b += learned_bytes(p);
     if (p->solver == PIC_SOLVER_PCG_SSOR) b += ssor_bytes(p);
@@ -1207,6 +1270,7 @@ int pic_sort_cells(pic_ctx* c, int64_t np, const uint32_t* key, const double* co
                     return fail(PIC_ERR_INVALID, "dst must not alias src");
         }
     }
+    RETCHK(ensure_rec(c));
     HIPCHK(launch_sort_cells(np, c->p.n, key, src, dst, cell_start, perm, &c->sort,
                              (hipStream_t)stream));
     return PIC_OK;
@@ -1369,6 +1433,7 @@ static int check_parts(pic_ctx* c, pic_particles* P, pic_fields* F) {
 // Sort into the second set of arrays and swap; from_rec: the push left the
 // particles in the sort's record array (the current arrays are stale).
 static int sort_swap(pic_ctx* c, pic_particles* P, hipStream_t s, bool from_rec = false) {
+    RETCHK(ensure_rec(c));
     const double* src[6] = {P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy, P->cur.vz};
     double* dst[6] = {P->alt.x, P->alt.y, P->alt.z, P->alt.vx, P->alt.vy, P->alt.vz};
     HIPCHK(launch_sort_cells(P->np, c->p.n, P->key, from_rec ? nullptr : src, dst, P->cell_start,
@@ -1487,6 +1552,7 @@ int pic_step(pic_ctx* c, pic_particles* P, pic_fields* F, pic_step_info* info, v
         }
         return PIC_OK;
     }
+    RETCHK(ensure_rec(c));
     HIPCHK(launch_gather_push(P->np, P->cur.x, P->cur.y, P->cur.z, P->cur.vx, P->cur.vy, P->cur.vz,
                               F->ex, F->ey, F->ez, P->key, c->sort.rec, c->p.n, c->inv_h, c->L,
                               c->p.dt, c->coef_push, s));

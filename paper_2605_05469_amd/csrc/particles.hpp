@@ -41,6 +41,9 @@ struct SortScratch {
     int64_t cap;        // particles
 };
 size_t sort_scratch_bytes(int64_t np_max);
+// The particle records (64 bytes each), a separate allocation made on the
+// first sort.
+size_t sort_rec_bytes(int64_t np_max);
 void sort_scratch_carve(void* base, int64_t np_max, SortScratch* s);
 // Sorts key[0..np) (values < n^3); writes the permutation (source index of
 // each sorted slot) to perm_out (may be NULL), cell_start[0..n^3], and the

@@ -38,6 +38,10 @@ struct CgScalars {
     int32_t pad;
 };
 
+// s-step Jacobi-PCG: iterations per outer step (Gram sweep + update sweep).
+constexpr int kSstepS = 3;
+constexpr int kSstepNV = 2 * kSstepS + 1;  // basis vectors
+
 struct DevState {
     CgScalars cg;      // the FP64 solve, or the inner FP32 solve of the mixed form
     double out_nr;     // mixed: ||b - A x|| of the current outer step
@@ -54,6 +58,17 @@ struct DevState {
     int32_t outer_state;
     int32_t gap_restarts;  // mixed: carried directions the residual-gap test refused
     uint32_t tickets[8];
+    // s-step form: coefficients of the new p and r and of the x increment on
+    // the basis of the last Gram sweep; whether that outer step ended the
+    // solve (1: candidate, 2: iteration limit) or a restart follows; its
+    // iterations
+    double ss_cp[kSstepNV];
+    double ss_cr[kSstepNV];
+    double ss_cx[kSstepNV];
+    int32_t ss_final;
+    int32_t ss_restart;
+    int32_t ss_steps;
+    int32_t ss_pad;
 };
 
 // Geometry of a z-marching stencil sweep: the caller sets n; the launcher
@@ -89,6 +104,14 @@ hipError_t launch_cg1(const SweepGeo& g, const double* r_in, double* r_out, cons
                       double* partials, int xm, int pslot, hipStream_t s);
 hipError_t launch_cg1_flush(int64_t n3, const double* p0, const double* p1, double* x,
                             DevState* st, hipStream_t s);
+// s-step form (periodic box): mode 0 = Gram sweep of (r_in, p_in) -- with
+// cg.restart set p is taken as M^{-1} r -- whose last workgroup leaves the
+// coefficients in the state; mode 1 = update sweep writing p_out, r_out and
+// x.  npartials: doubles available in partials.
+bool sstep_supported(const SweepGeo& g);
+hipError_t launch_sstep(const SweepGeo& g, int mode, const double* r_in, const double* p_in,
+                        double* r_out, double* p_out, double* x, double minv, DevState* st,
+                        double* partials, int npartials, hipStream_t s);
 // The same in FP32 for the inner solve of the mixed form (d: the inner
 // solution); pgiven: p_in already holds this step's direction (a direction
 // sweep formed it and its curvature: the continued first step).

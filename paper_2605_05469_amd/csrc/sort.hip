@@ -43,11 +43,15 @@ size_t sort_scratch_bytes(int64_t np_max) {
     const int64_t hist = t * kMaxRadix;
     const int64_t sums = (hist + kScanTile - 1) / kScanTile + 1;
     size_t b = 0;
-    b += 4 * (size_t)cap * sizeof(double2) + 256;
     b += 4 * (size_t)cap * sizeof(uint32_t);
     b += (size_t)(hist + 64) * sizeof(uint32_t);
     b += (size_t)(sums + 1088) * sizeof(uint32_t);
     return b + 1024;
+}
+
+size_t sort_rec_bytes(int64_t np_max) {
+    const int64_t cap = np_max > 0 ? np_max : 1;
+    return 4 * (size_t)cap * sizeof(double2);
 }
 
 void sort_scratch_carve(void* base, int64_t np_max, SortScratch* s) {
@@ -60,7 +64,7 @@ void sort_scratch_carve(void* base, int64_t np_max, SortScratch* s) {
         p += (bytes + 255) & ~(size_t)255;
         return r;
     };
-    s->rec = (double2*)take(4 * (size_t)cap * sizeof(double2));
+    s->rec = nullptr;  // sort_rec_bytes, allocated on the first sort
     s->key[0] = (uint32_t*)take((size_t)cap * 4);
     s->key[1] = (uint32_t*)take((size_t)cap * 4);
     s->idx[0] = (uint32_t*)take((size_t)cap * 4);

@@ -44,12 +44,12 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_abi_version_and_errors_without_gpu(lib):
     import paper_2605_05469_amd as P
-    assert lib.pic_abi_version() == 2
+    assert lib.pic_abi_version() == 3
     p = P.landau_params(32, 8)
     assert lib.pic_workspace_bytes(ctypes.byref(p)) > 3 * 8 * 32 ** 3
     h = ctypes.c_void_p()
     for field, bad in (("n", 33), ("n", 16), ("n", 2048), ("rtol", 0.0), ("length", -1.0),
-                       ("solver", 7), ("np_max", -5), ("flags", 128),
+                       ("solver", 7), ("np_max", -5), ("flags", 256),
                        ("ssor_omega", 2.5), ("ssor_inner", -1), ("bc", 3), ("bc", -1)):
         q = P.landau_params(32, 8)
         setattr(q, field, bad)

@@ -84,7 +84,12 @@ def test_fullsize_1024_deposit_solves_field(orc):
     _say("field checked")
 
     # the mixed form (reliable updates, inner tolerance 0.1) on the same
-    # right-hand side, cold start
+    # right-hand side, cold start; the particle arrays (96 GiB) are released
+    # first: with them, the sort's particle records (64 GiB) and the fields,
+    # the mixed form's four FP32 vectors would not fit in 288 GB
+    sim._cur = sim._alt = None
+    sim.key = None
+    torch.cuda.empty_cache()
     ctx.set_solver("pcg_mixed")
     ctx.set_flags(P.FLAG_MIXED_RELIABLE)
     x = torch.zeros_like(sim.phi)

@@ -294,7 +294,7 @@ def test_learned_warm_start_only(pic, orc):
         _, pinfo = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 5000)
         assert abs(info["iterations"] - pinfo["iters"]) <= 1
     with pytest.raises(pic.PicError):
-        ctx.set_flags(128)
+        ctx.set_flags(256)
 
 
 def test_learned_warm_start_then_mixed(pic, orc):

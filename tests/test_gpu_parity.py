@@ -238,18 +238,24 @@ def _rhs(orc, N, ppc, seed):
     return b
 
 
-@pytest.mark.parametrize("two_sweep", [False, True])
+def _pcg_flags(pic, form):
+    return {"single": pic.FLAG_PCG_SINGLE_SWEEP, "two_sweep": pic.FLAG_PCG_TWO_SWEEP,
+            "sstep": 0}[form]
+
+
+@pytest.mark.parametrize("form", ["sstep", "single", "two_sweep"])
 @pytest.mark.parametrize("N", [32, 64, 96, 128])
-def test_pcg_fp64_parity(pic, orc, N, two_sweep):
-    """Both arrangements of Jacobi-PCG on the GPU (the single-reduction sweep,
-    64- and 32-wide tiles, and the direction + update pair) against the
-    oracle's textbook recurrences.  At 128^3 the 64 x 32 tiles of the
-    single-reduction sweep (the 512^3 launch shape) sit two to a row, so
-    halos cross tiles in x and y.  When the two sides stop one iteration
-    apart (dot products summed in another order), the side that ran longer is
-    run again with the other's count, so the iterates are always compared
-    after the same number of iterations."""
-    flags = pic.FLAG_PCG_TWO_SWEEP if two_sweep else 0
+def test_pcg_fp64_parity(pic, orc, N, form):
+    """Every arrangement of Jacobi-PCG on the GPU (the s-step form's Gram and
+    update sweeps on 32 x 32 tiles, the default; the single-reduction sweep,
+    64- and 32-wide tiles; the direction + update pair) against the oracle's
+    textbook recurrences.  At 128^3 the 64 x 32 tiles of the single-reduction sweep
+    (the 512^3 launch shape) sit two to a row, so halos cross tiles in x and
+    y; the s-step tiles sit four to a row.  When the two sides stop one
+    iteration apart (dot products summed in another order), the side that
+    ran longer is run again with the other's count, so the iterates are
+    always compared after the same number of iterations."""
+    flags = _pcg_flags(pic, form)
     ctx, p = _ctx(pic, N, 8, np_max=0, check_every=8, flags=flags)
     b = _rhs(orc, N, 8, 6000 + N)
     x0 = np.zeros(N ** 3)
@@ -274,9 +280,10 @@ def test_pcg_fp64_parity(pic, orc, N, two_sweep):
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-def test_pcg_warm_start_and_zero_rhs(pic, orc):
+@pytest.mark.parametrize("form", ["sstep", "single"])
+def test_pcg_warm_start_and_zero_rhs(pic, orc, form):
     N = 32
-    ctx, p = _ctx(pic, N, 8, np_max=0)
+    ctx, p = _ctx(pic, N, 8, np_max=0, flags=_pcg_flags(pic, form))
     b = _rhs(orc, N, 8, 6100)
     ref, _ = orc.pcg(N, p.length, b, np.zeros(N ** 3), 1e-12, 20000)
     dx = _dev(ref)
@@ -288,9 +295,12 @@ def test_pcg_warm_start_and_zero_rhs(pic, orc):
     assert info["converged"] and info["iterations"] == 0 and np.all(_host(dx) == 0)
 
 
-def test_pcg_not_converged_status(pic, orc):
+@pytest.mark.parametrize("form", ["sstep", "single"])
+def test_pcg_not_converged_status(pic, orc, form):
+    """The iteration cap ends the solve at exactly max_iter iterations (five:
+    inside the s-step form's second outer step)."""
     N = 32
-    ctx, p = _ctx(pic, N, 8, np_max=0, max_iter=5, check_every=4)
+    ctx, p = _ctx(pic, N, 8, np_max=0, max_iter=5, check_every=4, flags=_pcg_flags(pic, form))
     b = _rhs(orc, N, 8, 6200)
     dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
     info = ctx.poisson(_dev(b), dx)
