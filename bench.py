@@ -52,7 +52,7 @@ SSTEP_UPD_BYTES = 48
 # HBM bytes per launch of the dominant kernel at 512^3, from rocprofv3
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
-SWEEP_TRAFFIC = {(512, "pcg_fp64", "pcg_update_sweep"): 5.571e9}
+SWEEP_TRAFFIC = {(512, "pcg_fp64", "pcg_sstep_update"): 6.937e9}
 TRAFFIC_SOURCE = ("rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of this kernel "
                   "(profiles/pcg_sweeps_landau512_hbm_counters.md)")
 
@@ -567,22 +567,22 @@ def run_pic(args, solver, flags, inner_rtol, fp32_inner, label):
     # Jacobi-PCG (FP64, the mixed form's FP32 inner solves, the learned form's
     # hand-over) runs as one kernel per iteration on the periodic box unless
     # two sweeps are asked for; its launches are sampled in timing slot 0
-    single = (solver in ("pcg_fp64", "pcg_mixed", "fcg_learned")
-              and not (flags & P.FLAG_PCG_TWO_SWEEP) and N % 32 == 0)
     sstep = (solver == "pcg_fp64" and N % 32 == 0
              and not (flags & (P.FLAG_PCG_TWO_SWEEP | P.FLAG_PCG_SINGLE_SWEEP)))
+    single = (not sstep and solver in ("pcg_fp64", "pcg_mixed", "fcg_learned")
+              and not (flags & P.FLAG_PCG_TWO_SWEEP) and N % 32 == 0)
     if sstep:
         # s-step form: per outer step (three iterations) a Gram sweep reading
         # p and r (16 B/point) and an update sweep reading p, r, x and writing
         # them (48 B/point); timing slots 0 and 1
-        gbs_gram = SSTEP_GRAM_BYTES * n3 / (ms_dir * 1e-3) / 1e9 if ms_dir > 0 else 0.0
-        gbs_upd = SSTEP_UPD_BYTES * n3 / (ms_upd * 1e-3) / 1e9 if ms_upd > 0 else 0.0
+        bg, bu = SSTEP_GRAM_BYTES, SSTEP_UPD_BYTES
+        gbs_gram = bg * n3 / (ms_dir * 1e-3) / 1e9 if ms_dir > 0 else 0.0
+        gbs_upd = bu * n3 / (ms_upd * 1e-3) / 1e9 if ms_upd > 0 else 0.0
         kernels = {"pcg_sstep_gram": {"avg_ms": ms_dir, "launches_timed": cnt_dir,
-                                      "bytes_per_point": SSTEP_GRAM_BYTES, "gbs": gbs_gram},
+                                      "bytes_per_point": bg, "gbs": gbs_gram},
                    "pcg_sstep_update": {"avg_ms": ms_upd, "launches_timed": cnt_upd,
-                                        "bytes_per_point": SSTEP_UPD_BYTES, "gbs": gbs_upd}}
-        gbs_iter = ((SSTEP_GRAM_BYTES + SSTEP_UPD_BYTES) * n3 / ((ms_dir + ms_upd) * 1e-3) / 1e9
-                    if ms_upd > 0 else 0.0)
+                                        "bytes_per_point": bu, "gbs": gbs_upd}}
+        gbs_iter = (bg + bu) * n3 / ((ms_dir + ms_upd) * 1e-3) / 1e9 if ms_upd > 0 else 0.0
         dom, gbs_dom = "pcg_sstep_update", gbs_upd
     elif single:
         b1 = SINGLE_SWEEP_BYTES_FP32 if fp32_inner else SINGLE_SWEEP_BYTES

@@ -469,7 +469,7 @@ static hipError_t ss_launch(int n, const double* r_in, const double* p_in, doubl
     const int tiles = nbx * nby;
     int nbz = occ * cus / tiles;
     if (nbz > max_blocks / tiles) nbz = max_blocks / tiles;
-    if (nbz > n / 8) nbz = n / 8;
+    if (nbz > n / 2) nbz = n / 2;  // at least two output planes per workgroup
     if (nbz < 1) nbz = 1;
     const int nb = tiles * nbz;
     if (nb > max_blocks) return hipErrorInvalidConfiguration;
