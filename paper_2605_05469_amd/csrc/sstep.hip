@@ -98,6 +98,31 @@ __device__ void ss_gram(const double* a, double* Gp) {
         }
 }
 
+// Tile of a workgroup.  Workgroups are dealt to the eight XCDs in turn and
+// (one per CU) run in rounds of 256 when the grid has more tiles than CUs
+// (1024^3: 1024 tiles).  With tiles in rows of a multiple of 16 and one
+// workgroup per tile column, each round takes a 16 x 16 block of tiles and
+// each XCD two adjacent tile rows of it, so the halo rows a workgroup reads
+// belong to tiles running at the same time on the same XCD or the next (in
+// its L2, or read once more); otherwise the generic XCD-contiguous order.
+__device__ __forceinline__ void ss_tile(uint32_t bid, int nbx, int nby, int nbz, int& bx, int& by,
+                                        int& bz) {
+    if (nbz == 1 && nbx % 16 == 0 && nby % 16 == 0) {
+        const uint32_t group = bid >> 8, w = bid & 255u;
+        const uint32_t xcd = w & 7u, k = w >> 3;  // k-th workgroup of this XCD in the round
+        const uint32_t gpr = (uint32_t)nbx / 16u;  // 16 x 16 blocks per block row
+        by = (int)((group / gpr) * 16u + 2u * xcd + (k >> 4));
+        bx = (int)((group % gpr) * 16u + (k & 15u));
+        bz = 0;
+        return;
+    }
+    const uint32_t nb = (uint32_t)(nbx * nby * nbz);
+    const uint32_t lb = remap_xcd(bid, nb);
+    bx = (int)(lb % nbx);
+    by = (int)((lb / nbx) % nby);
+    bz = (int)(lb / (nbx * nby));
+}
+
 // Coefficient step (one thread): G packed upper triangle of Y^T Y (r-world
 // basis), c = M^{-1} scalar.  Runs up to S iterations of CG on coordinates.
 template <int S>
@@ -228,8 +253,9 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
 
     const int tid = threadIdx.x;
     const uint32_t nb = (uint32_t)(nbx * nby * nbz);
-    const uint32_t lb = remap_xcd(blockIdx.x, nb);
-    const int bx = (int)(lb % nbx), by = (int)((lb / nbx) % nby), bz = (int)(lb / (nbx * nby));
+    const uint32_t lb = blockIdx.x;  // partials slot
+    int bx, by, bz;
+    ss_tile(blockIdx.x, nbx, nby, nbz, bx, by, bz);
     const int x0 = bx * TX, y0 = by * TY;
     const int z0 = (int)(((int64_t)bz * n) / nbz);
     const int z1 = (int)((((int64_t)bz + 1) * n) / nbz);
@@ -281,7 +307,8 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
     for (int i = 0; i < TOT; ++i)
 #pragma unroll
         for (int k = 0; k < NP; ++k) ring[i][k] = 0.0;
-    double ldp[NP], ldr[NP];
+    double ldp[NP], ldr[NP];    // level 0 of the plane about to be pushed
+    double ldp2[NP], ldr2[NP];  // and of the plane after it (loads in flight)
     double xn[MODE == 1 ? NP : 1];  // update sweep: x of the next output plane
 #pragma unroll
     for (int k = 0; k < (MODE == 1 ? NP : 1); ++k) xn[k] = 0.0;
@@ -289,8 +316,8 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
         const size_t zo = (size_t)wrap(zr) * nn;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            ldr[k] = r_in[zo + goff[k]];
-            ldp[k] = restart ? 0.0 : p_in[zo + goff[k]];
+            ldr2[k] = r_in[zo + goff[k]];
+            ldp2[k] = restart ? 0.0 : p_in[zo + goff[k]];
         }
     };
     double acc[MODE == 0 ? NM : 1];
@@ -299,6 +326,12 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
 
     const int t0 = z0 - S, t1 = z1 + S;  // level 0 planes t0 .. t1 - 1
     fetch(t0);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        ldr[k] = ldr2[k];
+        ldp[k] = ldp2[k];
+    }
+    fetch(t0 + 1);
     __syncthreads();  // LDS cleared
     for (int t = t0; t < t1; ++t) {
         double(*lb2)[PLANE] = lds[t & 1];
@@ -320,7 +353,12 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
             l0r[k] = ldr[k];
             l0p[k] = restart ? c * ldr[k] : ldp[k];
         }
-        if (t + 1 < t1) fetch(t + 1);
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            ldr[k] = ldr2[k];
+            ldp[k] = ldp2[k];
+        }
+        if (t + 2 < t1) fetch(t + 2);
         const int zo = t - S;  // output plane of this step
         const bool outp = zo >= z0 && zo < z1;
         // x of this step's output plane was loaded one step ahead; load the next
