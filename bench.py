@@ -354,6 +354,8 @@ def main():
                          "(instead of the s-step form's Gram and update sweeps)")
     ap.add_argument("--warm-start-only", action="store_true",
                     help="learned form: network warm start, then Jacobi-PCG")
+    ap.add_argument("--no-1024", action="store_true",
+                    help="default run: skip the 1024^3 standalone solves")
     ap.add_argument("--no-learned", action="store_true",
                     help="default run: skip the learned + mixed form and the 32^3 line")
     ap.add_argument("--accuracy-vs-fp64", action="store_true",
@@ -466,6 +468,11 @@ def main():
             "learned_over_mixed": out["mixed"]["s_per_step"] / out["learned_mixed"]["s_per_step"]}
         del ref
         out["config0"] = bench_config0(args)
+        if not args.no_1024:
+            try:
+                out["config4"] = bench_config4(args)
+            except Exception as e:  # the main line must still be printed
+                out["config4"] = {"error": repr(e)}
         out["hbm_triad"] = triad
     print(json.dumps(out), flush=True)
 
@@ -624,6 +631,71 @@ def run_pic(args, solver, flags, inner_rtol, fp32_inner, label):
                      "traffic_source": TRAFFIC_SOURCE if traffic else None},
         "_sim": sim, "_ctx": ctx, "_p": p, "_infos": infos,
     }
+
+
+def bench_config4(args):
+    """The 1024^3 standalone solves: the CIC deposit of 2^30 Landau particles
+    (1 ppc, seed 20265) solved from zero to the same rtol three ways -- plain
+    FP64 Jacobi-PCG (s-step form), the mixed form (reliable updates, inner
+    tolerance 0.1) and the trained network's warm start followed by the mixed
+    form -- with the s-step sweeps' kernel times of the FP64 solve."""
+    import torch
+
+    import paper_2605_05469_amd as P
+    from paper_2605_05469_amd import synth
+
+    N, ppc = 1024, 1
+    p = P.landau_params(N, ppc, rtol=args.rtol, solver="pcg_fp64", check_every=32,
+                        inner_rtol=0.1)
+    ctx = P.Context(p)
+    parts = synth.landau_particles_torch(N, ppc, seed=20265, device="cuda")
+    rho = torch.empty(N ** 3, dtype=torch.float64, device="cuda")
+    ctx.deposit(parts[0], parts[1], parts[2], None, rho)
+    del parts
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    out = {"workload": "poisson_solve_1024^3_rhs_1ppc_landau", "rtol": args.rtol}
+    n3 = N ** 3
+    for name, solver, flags in (
+            ("pcg_fp64", "pcg_fp64", 0),
+            ("mixed", "pcg_mixed", P.FLAG_MIXED_RELIABLE),
+            ("learned_mixed", "fcg_learned",
+             P.FLAG_WARM_START_ONLY | P.FLAG_LEARNED_MIXED | P.FLAG_MIXED_RELIABLE)):
+        if solver == "fcg_learned":
+            load_weights(ctx, args.weights)
+        ctx.set_flags(flags)
+        ctx.set_solver(solver)
+        phi = torch.zeros_like(rho)
+        ctx.set_kernel_timing(name == "pcg_fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ctx.poisson(rho, phi)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        r = {"s_per_solve": dt, "iterations": info["iterations"],
+             "outer_iterations": info["outer_iterations"], "rel_res": info["rel_res"],
+             "converged": bool(info["converged"])}
+        if solver == "fcg_learned":
+            r["warm_start_used"] = bool(info["warm_start_used"])
+        if name == "pcg_fp64":
+            ms_g, c_g = ctx.kernel_time(0)
+            ms_u, c_u = ctx.kernel_time(1)
+            r["kernels"] = {
+                "pcg_sstep_gram": {"avg_ms": ms_g, "launches_timed": c_g,
+                                   "gbs": SSTEP_GRAM_BYTES * n3 / (ms_g * 1e-3) / 1e9
+                                   if ms_g > 0 else 0.0},
+                "pcg_sstep_update": {"avg_ms": ms_u, "launches_timed": c_u,
+                                     "gbs": SSTEP_UPD_BYTES * n3 / (ms_u * 1e-3) / 1e9
+                                     if ms_u > 0 else 0.0}}
+        ctx.set_kernel_timing(False)
+        out[name] = r
+        log("1024^3 %s: %.2f s, %d iterations, rel_res %.2e" % (name, dt, info["iterations"],
+                                                              info["rel_res"]))
+        del phi
+    ctx.close()
+    del ctx, rho
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_config0(args):
