@@ -369,3 +369,83 @@ def test_single_reduction_arrangement_reproduces_textbook_pcg(orc):
     assert info["converged"] and info["replacements"] == 0
     assert it == info["iters"]
     assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_sstep_arrangement_reproduces_textbook_pcg(orc):
+    """The GPU's s-step arrangement of Jacobi-PCG (S = 3 iterations per outer
+    step), written out here with the oracle's operator: the basis T_0..T_S of
+    p and T_0..T_{S-1} of r, T_j Chebyshev polynomials of Ahat - I with Ahat =
+    M^{-1} A; the Gram matrix from the 6S inner products the Gram sweep
+    reduces (T_i T_j = (T_{i+j} + T_{|i-j|}) / 2); S CG iterations on
+    coordinates, stopping on ||r|| = sqrt(z'G z') / c after each one; the new
+    p, r and the x increment as combinations of the basis.  It takes the same
+    iterations as the oracle's textbook recurrences and reaches the same
+    solution to rounding (host check of the recurrence the two sweeps use)."""
+    S = 3
+    N = 16
+    P = synth.LandauParams(N=N, ppc=8)
+    parts = synth.landau_particles_np(N, 8, seed=78)
+    b, nb = orc.deposit(N, P.L, P.q, P.rho_bg, *parts[:3])
+    h = P.L / N
+    c = h * h / 6.0
+
+    def T(v, m):  # Chebyshev basis of Ahat - I applied to v, levels 0..m
+        out = [v, c * orc.apply_A(N, P.L, v) - v]
+        for _ in range(1, m):
+            out.append(2.0 * (c * orc.apply_A(N, P.L, out[-1]) - out[-1]) - out[-2])
+        return out[:m + 1]
+
+    nv = 2 * S + 1
+    B = np.zeros((nv, nv))  # Ahat on coordinates
+    for b0, top in ((0, S), (S + 1, S - 1)):
+        B[b0, b0] = B[b0 + 1, b0] = 1.0
+        for j in range(1, top + 1):
+            B[b0 + j, b0 + j] = 1.0
+            B[b0 + j - 1, b0 + j] = 0.5
+            if j + 1 <= top:
+                B[b0 + j + 1, b0 + j] = 0.5
+    x, r, p = np.zeros(N ** 3), b.copy(), c * b
+    it, done = 0, False
+    while not done and it < 5000:
+        Y = T(p, S) + T(r, S - 1)
+        # the 6S products, then the moments and the whole Gram matrix
+        mp = [Y[0] @ Y[k] for k in range(S + 1)]
+        mp += [2.0 * (Y[S] @ Y[j]) - mp[S - j] for j in range(1, S + 1)]
+        mr = [Y[S + 1] @ Y[S + 1 + k] for k in range(S)]
+        mr += [2.0 * (Y[2 * S] @ Y[S + 1 + j]) - mr[S - 1 - j] for j in range(1, S)]
+        mx = [Y[0] @ Y[S + 1 + k] for k in range(S)]
+        for i in range(1, S + 1):
+            mx.append(2.0 * (Y[i] @ Y[2 * S]) - mx[abs(i - (S - 1))])
+        G = np.empty((nv, nv))
+        for i in range(nv):
+            for j in range(nv):
+                a, bb = min(i, j), max(i, j)
+                if bb <= S:
+                    G[i, j] = 0.5 * (mp[a + bb] + mp[bb - a])
+                elif a > S:
+                    G[i, j] = 0.5 * (mr[a + bb - 2 * S - 2] + mr[bb - a])
+                else:
+                    G[i, j] = 0.5 * (mx[a + bb - S - 1] + mx[abs(a - (bb - S - 1))])
+        assert np.allclose(G, np.array([[u @ v for v in Y] for u in Y]), rtol=1e-12, atol=0)
+        D = np.array([1.0] * (S + 1) + [c] * S)  # z-world basis: r-chain times c
+        Gz = G * np.outer(D, D)
+        pp, zz, xx = np.eye(nv)[0], np.eye(nv)[S + 1], np.zeros(nv)
+        mu = zz @ Gz @ zz
+        for _ in range(S):
+            w = B @ pp
+            alpha = mu / (pp @ Gz @ w)
+            xx, zz = xx + alpha * pp, zz - alpha * w
+            mu2 = zz @ Gz @ zz
+            it += 1
+            if np.sqrt(mu2) / c <= 1e-10 * nb:
+                done = True
+                break
+            pp, mu = zz + (mu2 / mu) * pp, mu2
+        x = x + sum(a * v for a, v in zip(xx * D, Y))
+        r = sum(a * v for a, v in zip(zz / np.where(D == 1.0, c, 1.0), Y))
+        p = sum(a * v for a, v in zip(pp * D, Y))
+    ref, info = orc.pcg(N, P.L, b, np.zeros(N ** 3), 1e-10, 5000)
+    assert info["converged"] and info["replacements"] == 0
+    assert it == info["iters"]
+    assert np.linalg.norm(x - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert orc.residual_norm(N, P.L, b, x) <= 1e-10 * nb * 1.0001
