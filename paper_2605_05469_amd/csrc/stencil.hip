@@ -3,14 +3,17 @@
 // field E = -grad phi (Sec. 2, Eq. poisson).
 //
 // Design (MI355X / gfx950):
-//  * Jacobi-PCG on the periodic box runs ONE sweep per iteration
+//  * FP64 Jacobi-PCG on the periodic box runs by default in s-step form
+//    (sstep.hip: a Gram sweep and an update sweep per three iterations).
+//    Here: the single-reduction sweep (the mixed form's FP32 inner solves,
+//    and FP64 with PIC_FLAG_PCG_SINGLE_SWEEP), ONE sweep per iteration
 //    (cg1_kernel, the single-reduction arrangement of the same iteration):
 //    a 512-thread workgroup owns a 64 x 32 (x, y) tile (128 x 16 for the
 //    mixed form's FP32 inner sweeps) and an equal share of its column's
 //    z-planes.  From r_k, p_{k-1}, x_k it forms p_k, x_{k+1} and r_{k+1} and
 //    reduces the five dot products that give the next beta and alpha, so it
 //    streams r, p and x once each: 48 bytes per grid point in FP64 (24 in
-//    FP32).  A r_{k+1} on the tile needs r_{k+1} on a one-point ring, which
+//    FP32); with x updated every other sweep (XM 1 / 2) 40 on average (20).  A r_{k+1} on the tile needs r_{k+1} on a one-point ring, which
 //    needs p_k on a two-point ring: every stage is evaluated on the 68 x 36
 //    region; each thread keeps the z-neighbours of its region points in
 //    registers and in-plane neighbours pass through two double-buffered LDS
