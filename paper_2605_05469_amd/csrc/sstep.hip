@@ -307,8 +307,7 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
     for (int i = 0; i < TOT; ++i)
 #pragma unroll
         for (int k = 0; k < NP; ++k) ring[i][k] = 0.0;
-    double ldp[NP], ldr[NP];    // level 0 of the plane about to be pushed
-    double ldp2[NP], ldr2[NP];  // and of the plane after it (loads in flight)
+    double ldp[NP], ldr[NP];  // level 0 of the next plane (loads in flight)
     double xn[MODE == 1 ? NP : 1];  // update sweep: x of the next output plane
 #pragma unroll
     for (int k = 0; k < (MODE == 1 ? NP : 1); ++k) xn[k] = 0.0;
@@ -316,8 +315,8 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
         const size_t zo = (size_t)wrap(zr) * nn;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            ldr2[k] = r_in[zo + goff[k]];
-            ldp2[k] = restart ? 0.0 : p_in[zo + goff[k]];
+            ldr[k] = r_in[zo + goff[k]];
+            ldp[k] = restart ? 0.0 : p_in[zo + goff[k]];
         }
     };
     double acc[MODE == 0 ? NM : 1];
@@ -326,12 +325,6 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
 
     const int t0 = z0 - S, t1 = z1 + S;  // level 0 planes t0 .. t1 - 1
     fetch(t0);
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        ldr[k] = ldr2[k];
-        ldp[k] = ldp2[k];
-    }
-    fetch(t0 + 1);
     __syncthreads();  // LDS cleared
     for (int t = t0; t < t1; ++t) {
         double(*lb2)[PLANE] = lds[t & 1];
@@ -353,12 +346,7 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
             l0r[k] = ldr[k];
             l0p[k] = restart ? c * ldr[k] : ldp[k];
         }
-#pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            ldr[k] = ldr2[k];
-            ldp[k] = ldp2[k];
-        }
-        if (t + 2 < t1) fetch(t + 2);
+        if (t + 1 < t1) fetch(t + 1);
         const int zo = t - S;  // output plane of this step
         const bool outp = zo >= z0 && zo < z1;
         // x of this step's output plane was loaded one step ahead; load the next
@@ -525,9 +513,9 @@ hipError_t launch_sstep(const SweepGeo& g, int mode, const double* r_in, const d
     if (!sstep_supported(g)) return hipErrorInvalidValue;
     const int maxb = npartials / (6 * S);
     if (mode == 0)
-        return ss_launch<S, 32, 32, 512, 0>(g.n, r_in, p_in, r_out, p_out, x, minv, st, partials,
+        return ss_launch<S, 32, 32, 768, 0>(g.n, r_in, p_in, r_out, p_out, x, minv, st, partials,
                                             maxb, s);
-    return ss_launch<S, 32, 32, 512, 1>(g.n, r_in, p_in, r_out, p_out, x, minv, st, partials, maxb,
+    return ss_launch<S, 32, 32, 768, 1>(g.n, r_in, p_in, r_out, p_out, x, minv, st, partials, maxb,
                                         s);
 }
 
