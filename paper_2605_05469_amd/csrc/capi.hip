@@ -419,7 +419,9 @@ static int pcg64_iterate_sstep(pic_ctx* c, const double* b, double* x, hipStream
             }
             RETCHK(read_state(c, s));
             if (c->timing) RETCHK(timing_collect(c, K, (c->st_host->cg.iter - it0 + kSstepS - 1) / kSstepS));
-            if (c->st_host->cg.state == CG_RUNNING && c->st_host->cg.iter == it0)
+            // (a batch may end on an outer step that only set up a restart)
+            if (c->st_host->cg.state == CG_RUNNING && c->st_host->cg.iter == it0 &&
+                !c->st_host->cg.restart)
                 return fail(PIC_ERR_STATE, "solver made no progress (iteration %lld)",
                             (long long)it0);
             continue;

@@ -175,11 +175,14 @@ __device__ void ss_coefficients(const double* Gp, double c, DevState* st) {
         bmul(pp, w);
         const double nu = quad(pp, w);
         if (!(nu > 0.0) || !isfinite(nu) || !isfinite(mu)) {
-            if (j == 0) {
+            // p . A p lost to cancellation (the residual at the rounding
+            // floor): keep the steps made and restart from p = M^{-1} r; a
+            // restarted direction without positive curvature is a breakdown
+            if (j == 0 && (cg.restart || !isfinite(nu) || !isfinite(mu))) {
                 cg.state = CG_BREAKDOWN;
                 return;
             }
-            rst = 1;  // keep the steps made, restart from p = M^{-1} r
+            rst = 1;
             break;
         }
         const double alpha = mu / nu;

@@ -308,6 +308,14 @@ def test_pcg_not_converged_status(pic, orc, form):
     ref, rinfo = orc.pcg(N, p.length, b, np.zeros(N ** 3), p.rtol, 5)
     assert np.linalg.norm(_host(dx) - ref) <= 1e-13 * np.linalg.norm(ref)
     assert abs(info["rel_res"] - rinfo["true_rel_res"]) <= 1e-10 * rinfo["true_rel_res"]
+    # an unattainable tolerance: the iterations go on at the rounding floor
+    # (directions whose curvature is lost to cancellation restart) until the
+    # cap, which ends the solve with PIC_NOT_CONVERGED
+    ctx2, p2 = _ctx(pic, N, 8, np_max=0, max_iter=400, rtol=1e-17, flags=_pcg_flags(pic, form))
+    dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    info = ctx2.poisson(_dev(b), dx)
+    assert info["status"] == 1 and not info["converged"] and info["iterations"] == 400, info
+    assert orc.residual_norm(N, p.length, b, _host(dx)) <= 1e-12 * np.linalg.norm(b)
 
 
 def test_efield_parity(pic, orc):
