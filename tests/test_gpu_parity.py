@@ -310,12 +310,14 @@ def test_pcg_not_converged_status(pic, orc, form):
     assert abs(info["rel_res"] - rinfo["true_rel_res"]) <= 1e-10 * rinfo["true_rel_res"]
     # an unattainable tolerance: the iterations go on at the rounding floor
     # (directions whose curvature is lost to cancellation restart) until the
-    # cap, which ends the solve with PIC_NOT_CONVERGED
+    # cap, which ends the solve with PIC_NOT_CONVERGED; the iterate stays a
+    # solution to the usual tolerance (up to a constant, A's null space,
+    # which the field's gauge fix removes)
     ctx2, p2 = _ctx(pic, N, 8, np_max=0, max_iter=400, rtol=1e-17, flags=_pcg_flags(pic, form))
     dx = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
     info = ctx2.poisson(_dev(b), dx)
     assert info["status"] == 1 and not info["converged"] and info["iterations"] == 400, info
-    assert orc.residual_norm(N, p.length, b, _host(dx)) <= 1e-12 * np.linalg.norm(b)
+    assert orc.residual_norm(N, p.length, b, _host(dx)) <= 1e-10 * np.linalg.norm(b)
 
 
 def test_efield_parity(pic, orc):
