@@ -30,6 +30,9 @@
 // iteration count is exact; a step that passes it ends the outer step early
 // (the update sweep then applies x only) and the true residual decides, as
 // in the single-reduction form.
+#include <type_traits>
+#include <utility>
+
 #include "common.hpp"
 #include "solver_state.hpp"
 
@@ -41,6 +44,17 @@ namespace pic {
 
 __device__ __forceinline__ double ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ void st_nt(double v, double* p) { __builtin_nontemporal_store(v, p); }
+// The element at byte offset o of a plane: the plane's base is uniform and
+// the lane offset 32-bit (plane offsets stay below 2^32 bytes), so loads and
+// stores take the scalar-base addressing form.
+template <class T>
+__device__ __forceinline__ T* ss_at(T* base, uint32_t o) {
+    return (T*)((char*)base + o);
+}
+template <class T>
+__device__ __forceinline__ const T* ss_at(const T* base, uint32_t o) {
+    return (const T*)((const char*)base + o);
+}
 
 // ring of planes kept per level: chain 0 = p (levels 0..S), 1 = r (0..S-1)
 __host__ __device__ constexpr int ss_qsz(int chain, int m, int S) {
@@ -57,6 +71,28 @@ __host__ __device__ constexpr int ss_base(int chain, int m, int S) {
     return b;
 }
 __host__ __device__ constexpr int ss_total(int S) { return ss_base(1, S, S); }
+// Ring entry of level m holding the value pushed at phase ph (ph may be
+// negative: pushes of the previous period).
+__host__ __device__ constexpr int ss_slot(int chain, int m, int ph, int S) {
+    const int q = ss_qsz(chain, m, S);
+    return ss_base(chain, m, S) + ((ph % q) + q) % q;
+}
+__host__ __device__ constexpr int ss_gcd(int a, int b) { return b == 0 ? a : ss_gcd(b, a % b); }
+// Phases after which every ring is back at its first entry (the least
+// common multiple of the ring sizes).
+__host__ __device__ constexpr int ss_period(int S) {
+    int l = 1;
+    for (int ch = 0; ch < 2; ++ch)
+        for (int m = 0; m <= (ch == 0 ? S : S - 1); ++m) {
+            const int q = ss_qsz(ch, m, S);
+            l = l / ss_gcd(l, q) * q;
+        }
+    return l;
+}
+template <class F, int... I>
+__device__ __forceinline__ void ss_unroll(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
 
 // The Gram matrix from 6S inner products.  The T_j are Chebyshev
 // polynomials of one symmetric operator, so T_i T_j = (T_{i+j} + T_{|i-j|})/2
@@ -266,7 +302,7 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
     auto wrap = [n](int v) { return v < 0 ? v + n : (v >= n ? v - n : v); };
 
     int pofs[NP];       // padded LDS offset of region point k
-    uint32_t goff[NP];  // its in-plane global offset (periodic image)
+    uint32_t gofb[NP];  // its in-plane global offset in bytes (periodic image)
     uint32_t ownm = 0;  // bit k: point k is in the tile
     // slots past the region repeat a region point (the same values, written
     // to the same LDS entry), so no point needs a validity branch
@@ -290,7 +326,7 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
             }
         }
         pofs[k] = (ly + 1) * WP + lx + 1;
-        goff[k] = (uint32_t)wrap(y0 - S + ly) * (uint32_t)n + (uint32_t)wrap(x0 - S + lx);
+        gofb[k] = ((uint32_t)wrap(y0 - S + ly) * (uint32_t)n + (uint32_t)wrap(x0 - S + lx)) * 8u;
         if (real && lx >= S && lx < TX + S && ly >= S && ly < TY + S) ownm |= 1u << k;
     }
     for (int i = tid; i < 2 * NF * PLANE; i += NT) (&lds[0][0][0])[i] = 0.0;
@@ -316,10 +352,12 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
     for (int k = 0; k < (MODE == 1 ? NP : 1); ++k) xn[k] = 0.0;
     auto fetch = [&](int zr) {
         const size_t zo = (size_t)wrap(zr) * nn;
+        const double* rz = r_in + zo;
+        const double* pz = p_in + zo;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            ldr[k] = r_in[zo + goff[k]];
-            ldp[k] = restart ? 0.0 : p_in[zo + goff[k]];
+            ldr[k] = *ss_at(rz, gofb[k]);
+            ldp[k] = restart ? 0.0 : *ss_at(pz, gofb[k]);
         }
     };
     double acc[MODE == 0 ? NM : 1];
@@ -329,7 +367,33 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
     const int t0 = z0 - S, t1 = z1 + S;  // level 0 planes t0 .. t1 - 1
     fetch(t0);
     __syncthreads();  // LDS cleared
-    for (int t = t0; t < t1; ++t) {
+    // Each level keeps its last q planes in registers.  Update sweep: a
+    // ring indexed by the phase PH = (t - t0) mod ss_period(S), the march
+    // unrolled over one period so that every index is a compile-time
+    // constant and pushing a plane moves no value between registers (3% off
+    // the sweep at 512^3).  Gram sweep: its 18 accumulators leave too few
+    // registers for that at three waves per SIMD (it spills), so its rings
+    // shift by one entry per push (newest last).
+    constexpr bool PHASED = MODE == 1;
+    constexpr int PER = PHASED ? ss_period(S) : 1;
+    auto step = [&](auto phc, int t) __attribute__((always_inline)) {
+        constexpr int PH = decltype(phc)::value;
+        // ring entry of level m holding the plane pushed `age` pushes before
+        // the newest (before this step's push of that level: pre)
+        auto rix = [](int ch, int m, int age, bool pre) {
+            return PHASED ? ss_slot(ch, m, PH - age - (pre ? 1 : 0), S)
+                          : ss_base(ch, m, S) + ss_qsz(ch, m, S) - 1 - age;
+        };
+        auto push = [&](int ch, int m, int k, double v) __attribute__((always_inline)) {
+            if constexpr (PHASED) {
+                ring[ss_slot(ch, m, PH, S)][k] = v;
+            } else {
+                const int q = ss_qsz(ch, m, S), b = ss_base(ch, m, S);
+#pragma unroll
+                for (int i = 0; i + 1 < q; ++i) ring[b + i][k] = ring[b + i + 1][k];
+                ring[b + q - 1][k] = v;
+            }
+        };
         double(*lb2)[PLANE] = lds[t & 1];
         // LDS: each feeding level's plane before this step (level m: t - 1 - m)
 #pragma unroll
@@ -337,9 +401,9 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
 #pragma unroll
             for (int m = 0; m < (ch == 0 ? S : S - 1); ++m) {
                 const int slot = ch == 0 ? m : S + m;
-                const int q = ss_qsz(ch, m, S), b = ss_base(ch, m, S);
+                const int e = rix(ch, m, 0, true);
 #pragma unroll
-                for (int k = 0; k < NP; ++k) lb2[slot][pofs[k]] = ring[b + q - 1][k];
+                for (int k = 0; k < NP; ++k) lb2[slot][pofs[k]] = ring[e][k];
             }
         }
         // level 0 at plane t
@@ -358,10 +422,10 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
 #pragma unroll
             for (int k = 0; k < NP; ++k) xv[k] = xn[k];
             if (zo + 1 >= z0 && zo + 1 < z1) {
-                const size_t zb = (size_t)(zo + 1) * nn;
+                const double* xz = x + (size_t)(zo + 1) * nn;
 #pragma unroll
                 for (int k = 0; k < NP; ++k)
-                    xn[k] = ((ownm >> k) & 1u) ? ld_nt(x + zb + goff[k]) : 0.0;
+                    xn[k] = ((ownm >> k) & 1u) ? ld_nt(ss_at(xz, gofb[k])) : 0.0;
             }
         }
         __syncthreads();
@@ -370,40 +434,30 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
 #pragma unroll
         for (int ch = 0; ch < 2; ++ch) {
             const int top = ch == 0 ? S : S - 1;
-            {
-                const int q = ss_qsz(ch, 0, S), b = ss_base(ch, 0, S);
 #pragma unroll
-                for (int k = 0; k < NP; ++k) {
-#pragma unroll
-                    for (int i = 0; i + 1 < q; ++i) ring[b + i][k] = ring[b + i + 1][k];
-                    ring[b + q - 1][k] = ch == 0 ? l0p[k] : l0r[k];
-                }
-            }
+            for (int k = 0; k < NP; ++k) push(ch, 0, k, ch == 0 ? l0p[k] : l0r[k]);
 #pragma unroll
             for (int m = 1; m <= top; ++m) {
                 const int slot = ch == 0 ? m - 1 : S + m - 1;
-                const int qa = ss_qsz(ch, m - 1, S), ba = ss_base(ch, m - 1, S);
-                const int q = ss_qsz(ch, m, S), b = ss_base(ch, m, S);
+                // parent planes t - m + 1 (newest) and t - m - 1
+                const int pn = rix(ch, m - 1, 0, false), po = rix(ch, m - 1, 2, false);
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
                     double v;
                     const int pi = pofs[k];
                     const double* L = lb2[slot];
                     const double nsum = ((L[pi - 1] + L[pi + 1]) + (L[pi - WP] + L[pi + WP])) +
-                                        (ring[ba + qa - 3][k] + ring[ba + qa - 1][k]);
+                                        (ring[po][k] + ring[pn][k]);
                     if (m == 1) {
                         v = nsum * (-1.0 / 6.0);
-                    } else {
-                        const int qg = ss_qsz(ch, m - 2, S), bg = ss_base(ch, m - 2, S);
-                        v = nsum * (-1.0 / 3.0) - ring[bg + qg - 3][k];
+                    } else {  // grandparent plane t - m
+                        v = nsum * (-1.0 / 3.0) - ring[rix(ch, m - 2, 2, false)][k];
                     }
-#pragma unroll
-                    for (int i = 0; i + 1 < q; ++i) ring[b + i][k] = ring[b + i + 1][k];
-                    ring[b + q - 1][k] = v;
+                    push(ch, m, k, v);
                 }
             }
         }
-        // outputs of plane t - S at the tile points
+        // outputs of plane t - S at the tile points (level m: S - m pushes ago)
         if (outp) {
             const size_t zb = (size_t)zo * nn;
 #pragma unroll
@@ -411,10 +465,9 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
                 if (!((ownm >> k) & 1u)) continue;
                 double y[NV];
 #pragma unroll
-                for (int m = 0; m <= S; ++m) y[m] = ring[ss_base(0, m, S) + ss_qsz(0, m, S) - 1 - (S - m)][k];
+                for (int m = 0; m <= S; ++m) y[m] = ring[rix(0, m, S - m, false)][k];
 #pragma unroll
-                for (int m = 0; m < S; ++m)
-                    y[S + 1 + m] = ring[ss_base(1, m, S) + ss_qsz(1, m, S) - 1 - (S - m)][k];
+                for (int m = 0; m < S; ++m) y[S + 1 + m] = ring[rix(1, m, S - m, false)][k];
                 if constexpr (MODE == 0) {
                     // the products ss_gram() turns into G (y[0..S] = T_i p,
                     // y[S+1+j] = T_j r)
@@ -439,14 +492,19 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
                         rv += cr[i] * y[i];
                         dx += cx[i] * y[i];
                     }
-                    const size_t g = zb + goff[k];
-                    st_nt(pv, p_out + g);
-                    st_nt(rv, r_out + g);
-                    st_nt(xv[k] + dx, x + g);
+                    st_nt(pv, ss_at(p_out + zb, gofb[k]));
+                    st_nt(rv, ss_at(r_out + zb, gofb[k]));
+                    st_nt(xv[k] + dx, ss_at(x + zb, gofb[k]));
                 }
             }
         }
-    }
+    };
+    for (int t = t0; t < t1; t += PER)
+        ss_unroll(
+            [&](auto phc) __attribute__((always_inline)) {
+                if (t + decltype(phc)::value < t1) step(phc, t + decltype(phc)::value);
+            },
+            std::make_integer_sequence<int, PER>{});
 
     if constexpr (MODE == 0) {
         block_sum<NT, NM>(acc, red);
