@@ -12,8 +12,9 @@
 // T_{j-1}(v).  Two sweeps per outer step:
 //   * Gram sweep: forms Y at every point from p and r (a z-march with the
 //     levels T_j staggered by one plane each; in-plane neighbours through
-//     one LDS plane per level that feeds another) and reduces the 6S inner
-//     products that fix G = Y^T Y (ss_gram).
+//     one LDS plane per level that feeds another; a level only where some
+//     point of the work unit needs it) and reduces the 6S inner products
+//     that fix G = Y^T Y (ss_gram).
 //     The last workgroup runs the S iterations on coordinate vectors of
 //     length 2S + 1 (alpha, beta and ||r|| from G; Ahat acts on coordinates
 //     through the Chebyshev three-term relation) and leaves the coefficients
@@ -93,6 +94,46 @@ template <class F, int... I>
 __device__ __forceinline__ void ss_unroll(F&& f, std::integer_sequence<int, I...>) {
     (f(std::integral_constant<int, I>{}), ...);
 }
+
+// Work units of a workgroup's (TX + 2S) x (TY + 2S) region: RU units of two
+// region rows' TX tile columns (whole cache lines), HU units of 64 halo-column
+// points taken row by row (2S points per row: short contiguous runs), then
+// units with no point; unit k * NW + w is slot k of wave w.  A point at
+// distance d from the tile (the larger of its x and y distances) needs
+// p-level m only for d <= S - m and r-level m only for d <= S - 1 - m, so a
+// unit need not form the levels that none of its points needs (the outer
+// row pairs form p-level 1 only, the halo-column units no top level).
+template <int S, int TX, int TY, int NT>
+struct SsUnits {
+    static constexpr int H0 = TY + 2 * S, NW = NT / kWave, RU = (H0 + 1) / 2;
+    static constexpr int NH = 2 * S * H0;  // halo-column points
+    static constexpr int HU = (NH + kWave - 1) / kWave;
+    static constexpr int NU = (RU + HU + NW - 1) / NW * NW;
+    int dmin[NU];  // distance of the unit's nearest point (S + 1: no point)
+    static constexpr int dist(int l, int t) { return l < S ? S - l : (l >= t + S ? l - t - S + 1 : 0); }
+    // halo-column entry e: region column and row
+    static constexpr int halo_lx(int e) {
+        const int cc = e % (2 * S);
+        return cc < S ? cc : TX + cc;
+    }
+    static constexpr int halo_ly(int e) { return e / (2 * S); }
+    constexpr SsUnits() : dmin() {
+        for (int u = 0; u < NU; ++u) {
+            int d = S + 1;
+            if (u < RU) {
+                for (int ly = 2 * u; ly < 2 * u + 2 && ly < H0; ++ly)
+                    d = dist(ly, TY) < d ? dist(ly, TY) : d;
+            } else if (u < RU + HU) {
+                for (int e = (u - RU) * kWave; e < (u - RU + 1) * kWave && e < NH; ++e) {
+                    const int dx = dist(halo_lx(e), TX), dy = dist(halo_ly(e), TY);
+                    const int de = dx > dy ? dx : dy;
+                    d = de < d ? de : d;
+                }
+            }
+            dmin[u] = d;
+        }
+    }
+};
 
 // The Gram matrix from 6S inner products.  The T_j are Chebyshev
 // polynomials of one symmetric operator, so T_i T_j = (T_{i+j} + T_{|i-j|})/2
@@ -273,7 +314,9 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
     constexpr int NM = 6 * S;  // Gram sweep: moments reduced per point
     constexpr int W0 = TX + 2 * S, H0 = TY + 2 * S;
     constexpr int WP = W0 + 2, HP = H0 + 2;
-    constexpr int PLANE = WP * HP;
+    // two rows past the padded region: the LDS entries of the slots that
+    // hold no region point (their writes land there and are never read)
+    constexpr int PLANE = WP * (HP + 2);
     // Region points per thread.  Each wave takes two region rows' 32 tile
     // columns (whole cache lines for every load and store of the tile
     // columns); the spare waves take the 2S halo columns of every row.
@@ -301,15 +344,26 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
     const size_t nn = (size_t)n * n;
     auto wrap = [n](int v) { return v < 0 ? v + n : (v >= n ? v - n : v); };
 
+    // Gram sweep: skip the levels no point of a unit needs (13% off the
+    // sweep at 512^3, and the registers this frees let its rings be
+    // phase-indexed too); update sweep: form every level at every point
+    constexpr bool SKIP = MODE == 0;
+    using Units = SsUnits<S, TX, TY, NT>;
+    static_assert(Units::NU == NP * NW, "one unit per slot");
+    constexpr Units units{};
     int pofs[NP];       // padded LDS offset of region point k
     uint32_t gofb[NP];  // its in-plane global offset in bytes (periodic image)
     uint32_t ownm = 0;  // bit k: point k is in the tile
-    // slots past the region repeat a region point (the same values, written
-    // to the same LDS entry), so no point needs a validity branch
+    uint32_t ldpm = 0, ldrm = 0;  // bit k: point k loads p / r
+    int dmn[NP];        // nearest distance of slot k's unit (uniform)
+    // slots past the region (no point) compute on a spare LDS row, so no
+    // slot needs a validity branch and none writes a region point's entry
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
-        const int unit = k * NW + tid / kWave, lane = tid % kWave;
-        int lx = S, ly = 0;  // spare slots: a tile-column point of row 0
+        const int unit = k * NW + wv, lane = tid % kWave;
+        dmn[k] = units.dmin[unit];
+        int lx = S, ly = 0;  // no point: a tile-column point for the global offset
         bool real = false;
         if (unit < RU) {
             ly = 2 * unit + (lane >> 5);
@@ -318,17 +372,25 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
             if (!real) ly = H0 - 1;
         } else {
             const int e = (unit - RU) * kWave + lane;  // halo column entry
-            if (e < 2 * S * H0) {
-                const int cc = e % (2 * S);
-                lx = cc < S ? cc : TX + cc;
-                ly = e / (2 * S);
+            if (e < Units::NH) {
+                lx = Units::halo_lx(e);
+                ly = Units::halo_ly(e);
                 real = true;
             }
         }
-        pofs[k] = (ly + 1) * WP + lx + 1;
+        pofs[k] = real ? (ly + 1) * WP + lx + 1 : HP * WP + 1 + lane % (WP - 2);
         gofb[k] = ((uint32_t)wrap(y0 - S + ly) * (uint32_t)n + (uint32_t)wrap(x0 - S + lx)) * 8u;
         if (real && lx >= S && lx < TX + S && ly >= S && ly < TY + S) ownm |= 1u << k;
+        const int dx = Units::dist(lx, TX), dy = Units::dist(ly, TY), d = dx > dy ? dx : dy;
+        // p (level 0 of the p chain) to distance S; r to S - 1, or to S when
+        // the direction restarts as M^{-1} r
+        if (real) ldpm |= 1u << k;
+        if (real && (!SKIP || d <= S - 1 || restart)) ldrm |= 1u << k;
     }
+    // the p- or r-chain level m is formed in slot k (and its plane kept in LDS)
+    auto lvl_on = [&](int k, int ch, int m) {
+        return !SKIP || dmn[k] <= (ch == 0 ? S - m : S - 1 - m);
+    };
     for (int i = tid; i < 2 * NF * PLANE; i += NT) (&lds[0][0][0])[i] = 0.0;
 
     double cp[NV], cr[NV], cx[NV];
@@ -356,8 +418,8 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
         const double* pz = p_in + zo;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            ldr[k] = *ss_at(rz, gofb[k]);
-            ldp[k] = restart ? 0.0 : *ss_at(pz, gofb[k]);
+            ldr[k] = ((ldrm >> k) & 1u) ? *ss_at(rz, gofb[k]) : 0.0;
+            ldp[k] = (restart || !((ldpm >> k) & 1u)) ? 0.0 : *ss_at(pz, gofb[k]);
         }
     };
     double acc[MODE == 0 ? NM : 1];
@@ -367,32 +429,20 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
     const int t0 = z0 - S, t1 = z1 + S;  // level 0 planes t0 .. t1 - 1
     fetch(t0);
     __syncthreads();  // LDS cleared
-    // Each level keeps its last q planes in registers.  Update sweep: a
-    // ring indexed by the phase PH = (t - t0) mod ss_period(S), the march
-    // unrolled over one period so that every index is a compile-time
-    // constant and pushing a plane moves no value between registers (3% off
-    // the sweep at 512^3).  Gram sweep: its 18 accumulators leave too few
-    // registers for that at three waves per SIMD (it spills), so its rings
-    // shift by one entry per push (newest last).
-    constexpr bool PHASED = MODE == 1;
-    constexpr int PER = PHASED ? ss_period(S) : 1;
+    // Each level keeps its last q planes in registers, in a ring indexed by
+    // the phase PH = (t - t0) mod ss_period(S); the march is unrolled over
+    // one period, so every ring index is a compile-time constant and pushing
+    // a plane moves no value between registers.
+    constexpr int PER = ss_period(S);
     auto step = [&](auto phc, int t) __attribute__((always_inline)) {
         constexpr int PH = decltype(phc)::value;
         // ring entry of level m holding the plane pushed `age` pushes before
         // the newest (before this step's push of that level: pre)
         auto rix = [](int ch, int m, int age, bool pre) {
-            return PHASED ? ss_slot(ch, m, PH - age - (pre ? 1 : 0), S)
-                          : ss_base(ch, m, S) + ss_qsz(ch, m, S) - 1 - age;
+            return ss_slot(ch, m, PH - age - (pre ? 1 : 0), S);
         };
         auto push = [&](int ch, int m, int k, double v) __attribute__((always_inline)) {
-            if constexpr (PHASED) {
-                ring[ss_slot(ch, m, PH, S)][k] = v;
-            } else {
-                const int q = ss_qsz(ch, m, S), b = ss_base(ch, m, S);
-#pragma unroll
-                for (int i = 0; i + 1 < q; ++i) ring[b + i][k] = ring[b + i + 1][k];
-                ring[b + q - 1][k] = v;
-            }
+            ring[ss_slot(ch, m, PH, S)][k] = v;
         };
         double(*lb2)[PLANE] = lds[t & 1];
         // LDS: each feeding level's plane before this step (level m: t - 1 - m)
@@ -403,7 +453,8 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
                 const int slot = ch == 0 ? m : S + m;
                 const int e = rix(ch, m, 0, true);
 #pragma unroll
-                for (int k = 0; k < NP; ++k) lb2[slot][pofs[k]] = ring[e][k];
+                for (int k = 0; k < NP; ++k)
+                    if (lvl_on(k, ch, m)) lb2[slot][pofs[k]] = ring[e][k];
             }
         }
         // level 0 at plane t
@@ -443,6 +494,7 @@ __global__ __launch_bounds__(NT) void sstep_kernel(int n, int nbx, int nby, int 
                 const int pn = rix(ch, m - 1, 0, false), po = rix(ch, m - 1, 2, false);
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
+                    if (!lvl_on(k, ch, m)) continue;
                     double v;
                     const int pi = pofs[k];
                     const double* L = lb2[slot];
