@@ -189,18 +189,34 @@ __global__ __launch_bounds__(kPT) void half_kick_kernel(
 // order into the eight CIC corner sums S[a][b][c]; lanes then combine the two
 // cells of a row that touch vertex x (cell x-1 with a = 1, cell x with a = 0)
 // and store T[2c+b][(z, y) row][x]: the contribution of cell row (y, z) to
-// vertex (x, y+b, z+c).  Every particle is read once.
+// vertex (x, y+b, z+c).  Every particle is read once: the cells of a segment
+// hold one contiguous run of sorted particles, which the wave stages through
+// LDS in chunks of kDepCh with whole-line loads (a lane reading its own
+// cell's particles touches a new line per particle, and the lines a wave
+// needs outlive their stay in L2), and each lane then takes its cell's part
+// of the chunk in order.
+constexpr int kDepCh = 256;  // particles per staged chunk
+
+// LDS written by some lanes of a wave and then read by others
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(kPT) void deposit_cells_kernel(
     const double* __restrict__ x, const double* __restrict__ y, const double* __restrict__ z,
     const uint32_t* __restrict__ cs, int n, double inv_h, double* __restrict__ T0,
     double* __restrict__ T1, double* __restrict__ T2, double* __restrict__ T3) {
-    const int lane = threadIdx.x & 63;
+    __shared__ double sp[kPT / kWave][3][kDepCh];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t wid = ((int64_t)blockIdx.x * kPT + threadIdx.x) >> 6;
     const int segs = (n + 62) / 63;
     const int64_t rows = (int64_t)n * n;
     if (wid >= rows * segs) return;  // uniform per wave
     const int64_t row = wid / segs;
-    const int xl = (int)(wid % segs) * 63 + lane - 1;  // this lane's cell x (lane 0: x0 - 1)
+    const int x0 = (int)(wid % segs) * 63;
+    const int xl = x0 + lane - 1;  // this lane's cell x (lane 0: x0 - 1)
     const bool active = xl < n;
     const int cx = xl < 0 ? n - 1 : xl;
     double s[2][2][2];
@@ -210,26 +226,56 @@ __global__ __launch_bounds__(kPT) void deposit_cells_kernel(
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int c = 0; c < 2; ++c) s[a][b][c] = 0.0;
+    uint32_t pb = 0, pe = 0;  // this lane's particles
     if (active) {
         const size_t cell = (size_t)row * n + cx;
-        const uint32_t pe = cs[cell + 1];
-        for (uint32_t p = cs[cell]; p < pe; ++p) {
-            int i0;
-            double w0, w1, w2;
-            locate(x[p], n, inv_h, i0, w0);
-            locate(y[p], n, inv_h, i0, w1);
-            locate(z[p], n, inv_h, i0, w2);
+        pb = cs[cell];
+        pe = cs[cell + 1];
+    }
+    // particles [rb, re) through LDS; lanes lo..hi take theirs
+    auto run = [&](uint32_t rb, uint32_t re, int lo, int hi) {
+        for (uint32_t c0 = rb; c0 < re; c0 += kDepCh) {
+            const uint32_t cn = re - c0 < (uint32_t)kDepCh ? re - c0 : (uint32_t)kDepCh;
+            for (uint32_t q = lane; q < cn; q += kWave) {
+                sp[wv][0][q] = x[c0 + q];
+                sp[wv][1][q] = y[c0 + q];
+                sp[wv][2][q] = z[c0 + q];
+            }
+            wave_lds_sync();
+            if (active && lane >= lo && lane <= hi) {
+                const uint32_t p0 = pb > c0 ? pb : c0;
+                const uint32_t p1 = pe < c0 + cn ? pe : c0 + cn;
+                for (uint32_t p = p0; p < p1; ++p) {
+                    int i0;
+                    double w0, w1, w2;
+                    locate(sp[wv][0][p - c0], n, inv_h, i0, w0);
+                    locate(sp[wv][1][p - c0], n, inv_h, i0, w1);
+                    locate(sp[wv][2][p - c0], n, inv_h, i0, w2);
 #pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                const double wz = c ? w2 : 1.0 - w2;
+                    for (int c = 0; c < 2; ++c) {
+                        const double wz = c ? w2 : 1.0 - w2;
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const double wy = b ? w1 : 1.0 - w1;
-                    s[0][b][c] += (wz * wy) * (1.0 - w0);
-                    s[1][b][c] += (wz * wy) * w0;
+                        for (int b = 0; b < 2; ++b) {
+                            const double wy = b ? w1 : 1.0 - w1;
+                            s[0][b][c] += (wz * wy) * (1.0 - w0);
+                            s[1][b][c] += (wz * wy) * w0;
+                        }
+                    }
                 }
             }
+            wave_lds_sync();  // the chunk is consumed before the next overwrites it
         }
+    };
+    // cells x0 - 1 .. x0 + last - 1 of the row (lanes 0..last) hold one run,
+    // except in the first segment, whose lane 0 takes the row's last cell
+    const int last = n - x0 < 63 ? n - x0 : 63;
+    const uint32_t b0 = __shfl(pb, 0, 64), e0 = __shfl(pe, 0, 64);
+    const uint32_t b1 = __shfl(pb, 1, 64), e1 = __shfl(pe, last, 64);
+    if (x0 > 0) {
+        run(b0, e1, 0, 63);
+    } else {
+        run(b0, e0, 0, 0);
+        run(b1, e1, 1, 63);
     }
     double* T[4] = {T0, T1, T2, T3};
 #pragma unroll
