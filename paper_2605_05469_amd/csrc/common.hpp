@@ -19,6 +19,12 @@ __device__ __forceinline__ uint32_t remap_xcd(uint32_t bid, uint32_t nb) {
     if ((nb & 7u) != 0u) return bid;
     return (bid & 7u) * (nb >> 3) + (bid >> 3);
 }
+// The same for any nb: XCD j takes the nb / 8 (+1 for j < nb % 8) logical
+// ids that follow those of XCDs 0..j-1.
+__device__ __forceinline__ uint32_t remap_xcd_any(uint32_t bid, uint32_t nb) {
+    const uint32_t j = bid & 7u, q = nb >> 3, r = nb & 7u;
+    return j * q + (j < r ? j : r) + (bid >> 3);
+}
 
 // ---------------------------------------------------------------------------
 // Deterministic block reductions of doubles (fixed shape: lane tree inside a

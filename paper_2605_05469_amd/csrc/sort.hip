@@ -97,7 +97,9 @@ __global__ __launch_bounds__(kHistNT) void hist_kernel(int64_t np, const uint32_
     const uint32_t radix = 1u << bits, mask = radix - 1;
     for (int d = tid; d < NW * kMaxRadix; d += kHistNT) (&cnt[0][0])[d] = 0;
     __syncthreads();
-    const int64_t t = blockIdx.x;
+    // consecutive tiles on one XCD (their entries of each digit's row of the
+    // table are adjacent and merge in that XCD's L2)
+    const int64_t t = remap_xcd_any(blockIdx.x, (uint32_t)tiles);
     const int64_t base = t * kTile;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
     // each wave counts its own contiguous quarter of the tile, loading
@@ -220,7 +222,10 @@ __global__ __launch_bounds__(kSortNT, 6) void scatter_kernel(int64_t np,
     __shared__ uint32_t sbuf[kTile];
     const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
     const uint32_t radix = 1u << bits, mask = radix - 1;
-    const int64_t t = blockIdx.x;
+    // consecutive tiles on one XCD: their runs of each digit are adjacent in
+    // the output, so the partial cache lines where two runs meet merge in
+    // that XCD's L2 instead of being written twice
+    const int64_t t = remap_xcd_any(blockIdx.x, (uint32_t)tiles);
     const int64_t tbase = t * kTile;
     const int64_t nvalid64 = np - tbase < kTile ? np - tbase : kTile;
     const int nvalid = (int)nvalid64;
