@@ -11,8 +11,10 @@ call) are recorded and asserted: at 128^3, the size the network was trained
 at, flexible PCG needs at most 0.4x Jacobi-PCG's iterations, but one network
 application costs more than the iterations it saves, so it is slower; at
 512^3 (the headline workload) the 128^3-trained network stalls, flexible PCG
-falls back and the residual test still decides, while the warm start
-followed by the mixed form beats plain FP64 PCG's wall time.  Every solution
+falls back and the residual test still decides, and its warm start saves
+the mixed form no inner iterations (out of distribution it costs a few) nor
+time; plain FP64 PCG (s-step form) and the mixed form take about the same
+time there, both moving about 21 bytes per grid point per iteration.  Every solution
 meets the tolerance under the oracle's operator.  The figures are printed
 (and written to $PIC_GAIN_OUT as JSON lines when that is set)."""
 import json
@@ -113,8 +115,13 @@ def test_gain_at_headline_size(orc):
     w = torch.from_numpy(np.load(_WEIGHTS)).cuda()
     r = _solve_all(P, orc, N, rho, p.length, w)
     _record({"grid": N, "forms": r})
-    plain = r["pcg_fp64"]
-    # mixed precision plus the learned warm start beats plain FP64 PCG's wall
-    # time at the same tolerance
-    assert r["learned_warm_start_mixed"]["seconds"] < plain["seconds"]
-    assert r["pcg_mixed"]["seconds"] < plain["seconds"]
+    plain, mixed = r["pcg_fp64"], r["pcg_mixed"]
+    ws = r["learned_warm_start_mixed"]
+    # the 128^3-trained network stalls here: flexible PCG falls back
+    assert r["fcg_learned"]["fell_back"]
+    # its warm start saves the mixed form less than 3% of the inner
+    # iterations, and no wall time beyond the box-to-box spread
+    assert ws["iterations"] >= 0.97 * mixed["iterations"]
+    assert ws["seconds"] >= 0.95 * mixed["seconds"]
+    # plain FP64 (s-step form) and the mixed form: within 20% of each other
+    assert abs(mixed["seconds"] - plain["seconds"]) <= 0.2 * plain["seconds"]
