@@ -52,7 +52,7 @@ SSTEP_UPD_BYTES = 48
 # HBM bytes per launch of the dominant kernel at 512^3, from rocprofv3
 # FETCH_SIZE (x2) + WRITE_SIZE of this kernel version
 # (profiles/pcg_sweeps_landau512_hbm_counters.md); None for other workloads.
-SWEEP_TRAFFIC = {(512, "pcg_fp64", "pcg_sstep_update"): 6.811e9}
+SWEEP_TRAFFIC = {(512, "pcg_fp64", "pcg_sstep_update"): 6.945e9}
 TRAFFIC_SOURCE = ("rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of this kernel "
                   "(profiles/pcg_sweeps_landau512_hbm_counters.md)")
 
