@@ -44,6 +44,11 @@ SWEEP_BYTES = {"pcg_fp64": (24, 40), "pcg_mixed": (12, 20), "fcg_learned": (24, 
 # every other iteration): 16 and 24, 20 on average.
 SINGLE_SWEEP_BYTES = 40
 SINGLE_SWEEP_BYTES_FP32 = 20
+# SSOR preconditioner, fused triangular solves of its last outer step:
+# forward reads the right side and writes y, backward reads y, the running z
+# and r (for r . z) and writes z
+SSOR_FWD_BYTES = 16
+SSOR_BWD_BYTES = 32
 # s-step form (three iterations per outer step): Gram sweep reads p and r,
 # update sweep reads p, r, x and writes them
 SSTEP_S = 3
@@ -570,6 +575,8 @@ def run_pic(args, solver, flags, inner_rtol, fp32_inner, label):
     bdir, bupd = SWEEP_BYTES["pcg_mixed" if fp32_inner else solver]
     ms_dir, cnt_dir = P.Context.kernel_time(ctx, 0)
     ms_upd, cnt_upd = P.Context.kernel_time(ctx, 1)
+    ms_f, cnt_f = P.Context.kernel_time(ctx, 2)  # SSOR-PCG only
+    ms_b, cnt_b = P.Context.kernel_time(ctx, 3)
     ctx.set_kernel_timing(False)
     # Jacobi-PCG (FP64, the mixed form's FP32 inner solves, the learned form's
     # hand-over) runs as one kernel per iteration on the periodic box unless
@@ -607,6 +614,19 @@ def run_pic(args, solver, flags, inner_rtol, fp32_inner, label):
                    "pcg_update_sweep": {"avg_ms": ms_upd, "launches_timed": cnt_upd,
                                         "bytes_per_point": bupd, "gbs": gbs_upd}}
         dom, gbs_dom = "pcg_update_sweep", gbs_upd
+        if solver == "pcg_ssor" and not (flags & P.FLAG_SSOR_UNFUSED):
+            # the preconditioner's fused triangular solves of its last outer
+            # step (timing slots 2, 3): forward reads r - A z and writes y
+            # (16 B/point), backward reads y, z and r and writes z (32)
+            gbs_f = SSOR_FWD_BYTES * n3 / (ms_f * 1e-3) / 1e9 if ms_f > 0 else 0.0
+            gbs_b = SSOR_BWD_BYTES * n3 / (ms_b * 1e-3) / 1e9 if ms_b > 0 else 0.0
+            kernels["ssor_forward_solve"] = {"avg_ms": ms_f, "launches_timed": cnt_f,
+                                             "bytes_per_point": SSOR_FWD_BYTES, "gbs": gbs_f}
+            kernels["ssor_backward_solve"] = {"avg_ms": ms_b, "launches_timed": cnt_b,
+                                              "bytes_per_point": SSOR_BWD_BYTES, "gbs": gbs_b}
+            # per SSOR-PCG iteration two backward solves (the last one with
+            # its added terms) take the most time
+            dom, gbs_dom = "ssor_backward_solve", gbs_b
     phases = {k: sum(i[k] for i in infos) / len(infos)
               for k in ("ms_push", "ms_sort", "ms_deposit", "ms_solve", "ms_field")}
     for i, inf in enumerate(infos):

@@ -344,7 +344,9 @@ int pic_pif_field(pic_ctx *ctx, int64_t np, const double *x, const double *y,
 /* Average duration (ms) of the most recent solve's dominant kernel launches,
  * measured with HIP events on the solve's stream when timing is enabled by
  * pic_set_kernel_timing(ctx, 1); kernel_id: 0 = direction/stencil kernel,
- * 1 = update kernel.  Host out.                                            */
+ * 1 = update kernel, 2 / 3 = the SSOR preconditioner's forward / backward
+ * fused triangular solve (of its last outer step; SSOR-PCG only).  Host
+ * out; an id outside 0..3 gives PIC_ERR_INVALID.                           */
 int pic_set_kernel_timing(pic_ctx *ctx, int32_t enable);
 int pic_kernel_time(pic_ctx *ctx, int32_t kernel_id, double *avg_ms, int64_t *count);
 

@@ -85,8 +85,8 @@ struct pic_ctx {
     // kernel timing
     bool timing = false;
     std::vector<hipEvent_t> ev;
-    double t_sum[2] = {0, 0};
-    int64_t t_cnt[2] = {0, 0};
+    double t_sum[4] = {0, 0, 0, 0};  // 0, 1: sweeps; 2, 3: SSOR triangular solves
+    int64_t t_cnt[4] = {0, 0, 0, 0};
 };
 
 // ------------------------------------------------------------------ helpers --
@@ -284,8 +284,10 @@ __global__ void state_init_kernel(DevState* st, int32_t outer_state) {
 // --------------------------------------------------------------- timing ----
 
 static void timing_reset(pic_ctx* c) {
-    c->t_sum[0] = c->t_sum[1] = 0;
-    c->t_cnt[0] = c->t_cnt[1] = 0;
+    for (int j = 0; j < 4; ++j) {
+        c->t_sum[j] = 0;
+        c->t_cnt[j] = 0;
+    }
 }
 
 static int timing_events(pic_ctx* c, size_t need) {
@@ -835,17 +837,22 @@ static int solve_learned(pic_ctx* c, const double* b, double* x, pic_solve_info*
 // PIC_FLAG_SSOR_UNFUSED every step is a sweep of its own (same values of z).
 // Buffers: sv[2], sv[3] forward ping-pong, sv[4] backward, sv[5] = r - A z.
 static int ssor_once(pic_ctx* c, const double* rhs, double* out, const double* add,
-                     const double* rdot, hipStream_t s) {
+                     const double* rdot, hipStream_t s, bool timed = false) {
     const SweepGeo& g = c->geo_tri;
     const int bounded = c->p.bc != PIC_BC_PERIODIC;
     const int k = c->p.ssor_inner;
     const double w = c->p.ssor_omega;
     const double cc = w / 6.0, dinv = c->minv, sc = w * (2.0 - w);
     if (!(c->p.flags & PIC_FLAG_SSOR_UNFUSED) && ssor_fused_supported(c->p.n, k)) {
+        // timed: events 4..7 around the two solves (read by ssor_timing_collect)
+        if (timed) HIPCHK(hipEventRecord(c->ev[4], s));
         HIPCHK(launch_ssor_fused(c->p.n, bounded, k, 0, rhs, nullptr, nullptr, c->sv[2], dinv, cc,
                                  1.0, c->st, c->partials, s));
+        if (timed) HIPCHK(hipEventRecord(c->ev[5], s));
+        if (timed) HIPCHK(hipEventRecord(c->ev[6], s));
         HIPCHK(launch_ssor_fused(c->p.n, bounded, k, 1, c->sv[2], add, rdot, out, 1.0, cc, sc,
                                  c->st, c->partials, s));
+        if (timed) HIPCHK(hipEventRecord(c->ev[7], s));
         return PIC_OK;
     }
     double* ya = c->sv[2];
@@ -874,13 +881,25 @@ static int ssor_once(pic_ctx* c, const double* rhs, double* out, const double* a
     return PIC_OK;
 }
 
-// z = SSOR^outer(r); r . z into st->flex_zr.
-static int ssor_apply(pic_ctx* c, const double* r, double* z, hipStream_t s) {
+// z = SSOR^outer(r); r . z into st->flex_zr.  timed: the last outer step's
+// two fused triangular solves are timed (timing slots 2 and 3, collected by
+// ssor_timing_collect once the stream has passed them).
+static int ssor_apply(pic_ctx* c, const double* r, double* z, hipStream_t s, bool timed = false) {
     const int o = c->p.ssor_outer;
-    RETCHK(ssor_once(c, r, z, nullptr, o == 1 ? r : nullptr, s));
+    RETCHK(ssor_once(c, r, z, nullptr, o == 1 ? r : nullptr, s, timed && o == 1));
     for (int i = 1; i < o; ++i) {
         HIPCHK(launch_resid_norm(c->geo, r, z, c->sv[5], c->inv_h2, c->st, c->partials, s));
-        RETCHK(ssor_once(c, c->sv[5], z, z, i + 1 == o ? r : nullptr, s));
+        RETCHK(ssor_once(c, c->sv[5], z, z, i + 1 == o ? r : nullptr, s, timed && i + 1 == o));
+    }
+    return PIC_OK;
+}
+
+static int ssor_timing_collect(pic_ctx* c) {
+    for (int j = 0; j < 2; ++j) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->ev[4 + 2 * j], c->ev[5 + 2 * j]));
+        c->t_sum[2 + j] += ms;
+        c->t_cnt[2 + j] += 1;
     }
     return PIC_OK;
 }
@@ -917,9 +936,13 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
     int cur = 0;      // p2[cur] holds the current direction
     int64_t it = 0;
     // kernel timing: every kTimeStride-th iteration, the direction sweep
-    // (slot 0) and the update sweep (slot 1); the state is read back after
-    // each, so the events have completed when they are read
-    if (c->timing) RETCHK(timing_events(c, 4));
+    // (slot 0), the update sweep (slot 1) and, with the fused triangular
+    // solves, the forward and backward solve of the preconditioner's last
+    // outer step (slots 2, 3); the state is read back after each, so the
+    // events have completed when they are read
+    if (c->timing) RETCHK(timing_events(c, 8));
+    const bool fused =
+        !(c->p.flags & PIC_FLAG_SSOR_UNFUSED) && ssor_fused_supported(c->p.n, c->p.ssor_inner);
     while (it < c->p.max_iter) {
         const bool timed = c->timing && (it % kTimeStride) == 0;
         // p_new = z + beta p and p_new . A p_new (A p_new not stored)
@@ -962,8 +985,9 @@ static int solve_ssor(pic_ctx* c, const double* b, double* x, pic_solve_info* ou
             out->replacements += 1;
             continue;
         }
-        RETCHK(ssor_apply(c, c->r, z, s));
+        RETCHK(ssor_apply(c, c->r, z, s, timed && fused));
         RETCHK(read_state(c, s));
+        if (timed && fused) RETCHK(ssor_timing_collect(c));
         const double rz_new = c->st_host->flex_zr;
         beta = rz_new / rz;
         rz = rz_new;
@@ -1217,7 +1241,7 @@ int pic_stream_triad(int64_t n, const double* b, const double* cv, double* a, do
 }
 
 int pic_kernel_time(pic_ctx* c, int32_t id, double* avg_ms, int64_t* count) {
-    if (!c || !avg_ms || !count || id < 0 || id > 1)
+    if (!c || !avg_ms || !count || id < 0 || id > 3)
         return fail(PIC_ERR_INVALID, "bad arguments to pic_kernel_time");
     *count = c->t_cnt[id];
     *avg_ms = c->t_cnt[id] ? c->t_sum[id] / (double)c->t_cnt[id] : 0.0;
